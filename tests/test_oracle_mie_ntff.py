@@ -1,0 +1,134 @@
+"""Pins of the oracle's Lorenz-Mie series and near-to-far-field transform.
+
+Mie: the paper's printed table values (tests/golden/paper_mie_tables.txt,
+section 3.2 Table cylinder_RMS_combined and section 3.4 Table sphere_RMS),
+the optical theorem (lossless scatterer: extinction = scattering), the
+perfect-conductor limit.  NTFF (section 2.4): exact Mie near fields must
+transform to the Mie far field, an exact dipole field to the dipole
+pattern, converging at second order.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mie, ntff
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_mie_tables.txt")
+
+
+def _rows():
+    rows = []
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        parts = line.split()
+        rows.append(parts)
+    return rows
+
+
+@pytest.mark.parametrize("row", [r for r in _rows() if r[6] == "pin"], ids=lambda r: "-".join(r[:5]))
+def test_mie_matches_paper_tables(row):
+    kind, eps, aol, phi, stat, printed = row[:6]
+    printed = float(printed)
+    x = 2 * np.pi * float(aol)
+    th = np.arange(0.0, 180.0 + 1e-9, 0.5)
+    m = None if eps == "pec" else np.sqrt(float(eps))
+    if kind == "cyl":
+        S = mie.cylinder_S2(th, x, m, "TM")
+    else:
+        phis = [0.0, 45.0, 90.0] if phi == "-" else [float(phi)]
+        S = np.concatenate([mie.sphere_S2(th, p, x, m) for p in phis])
+    val = S.min() if stat == "min" else S.max()
+    assert abs(val - printed) <= 0.04 * printed, (val, printed)
+
+
+@pytest.mark.parametrize("x", [0.3, 2.0, 5.0069, 12.0])
+@pytest.mark.parametrize("m", [1.2247, 1.5, 2.0])
+def test_optical_theorem(x, m):
+    """For a lossless scatterer the extinction (forward amplitude) equals the
+    scattered power; a dropped term or wrong sign in a_n/b_n breaks it."""
+    for pol in ("TM", "TE"):
+        qe, qs = mie.cylinder_efficiencies(x, m, pol)
+        assert abs(qe - qs) < 1e-10 * qs
+    qe, qs = mie.sphere_efficiencies(x, m)
+    assert abs(qe - qs) < 1e-10 * qs
+
+
+def test_perfect_conductor_limit():
+    """A very high index dielectric tends to the PEC cylinder (TM)."""
+    th = np.arange(0, 180.1, 1.0)
+    pec = mie.cylinder_S2(th, 3.0, None, "TM")
+    diel = mie.cylinder_S2(th, 3.0, 3000.0, "TM")
+    assert np.max(np.abs(pec - diel)) < 2e-3 * pec.max()
+
+
+def test_sphere_forward_equals_s1_s2_and_phi_symmetry():
+    """At theta = 0, S1 = S2 (no azimuth dependence in exact forward
+    scattering) and |S(0, phi)|^2 is independent of phi."""
+    S1, S2 = mie.sphere_S1S2(np.array([0.0]), 6.0, 1.5)
+    assert abs(S1[0] - S2[0]) < 1e-10 * abs(S1[0])
+    vals = [mie.sphere_S2(np.array([0.0]), p, 6.0, 1.5)[0] for p in (0, 30, 90)]
+    assert np.ptp(vals) < 1e-9 * vals[0]
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_ntff_of_exact_mie_near_field(pol):
+    """Section 2.4: the transform of the exact scattered near field on the
+    contour (configuration of the 1024^2 cylinder: a = 25.5, lambda = 32,
+    box half-width 34.5) must reproduce the Lorenz-Mie far field."""
+    lam, a = 32.0, 25.5
+    k = 2 * np.pi / lam
+    c = np.array([511.5, 511.5])
+    lo, hi = (477, 477), (546, 546)
+    nodes = ntff.box_nodes(lo, hi)
+    R = nodes - c
+    E, H = mie.cylinder_near_field(R[:, 0], R[:, 1], k * a, k, 1.5, pol)
+    # exp(-i w t) field of unit incidence -> this code's exp(+j w t) phasor of
+    # an incident wave sin(w t - k x):  X = conj(i X_bh)
+    E, H = np.conj(1j * E), np.conj(1j * H)
+    th = np.arange(0, 360, 0.5)
+    S = ntff.farfield_2d(nodes, E, H, lo, hi, k, th, pol, c, 1.0)
+    ref = mie.cylinder_S2(th, k * a, 1.5, pol)
+    assert np.sqrt(np.mean((S - ref) ** 2)) / ref.max() < 1e-4
+
+
+def test_ntff_incident_field_radiates_nothing():
+    """A plane wave passing through the contour has no scattered far field
+    (extinction theorem); only discretisation noise remains."""
+    lam = 32.0
+    k = 2 * np.pi / lam
+    lo, hi = (0, 0), (60, 60)
+    nodes = ntff.box_nodes(lo, hi).astype(float)
+    ph = np.exp(-1j * k * nodes[:, 0])
+    E = np.zeros((len(nodes), 3), complex)
+    H = np.zeros((len(nodes), 3), complex)
+    E[:, 2] = ph
+    H[:, 1] = -ph
+    S = ntff.farfield_2d(nodes.astype(int), E, H, lo, hi, k, np.arange(0, 360, 5.0), "TM",
+                         (30.0, 30.0), 1.0)
+    # compare with the forward peak of a weak scatterer for scale
+    assert S.max() < 1e-3
+
+
+def test_ntff_3d_dipole_second_order():
+    """3-D transform of the exact electric-dipole field on a box: error vs
+    the closed-form pattern k^6 sin^2(gamma)/(16 pi^2) falls as h^2."""
+    errs = []
+    for s in (1, 2):
+        lam, hw = 12.0 * s, 6 * s
+        k = 2 * np.pi / lam
+        c = np.array([hw + 0.3, hw - 0.2, hw + 0.1])
+        lo, hi = (0, 0, 0), (2 * hw,) * 3
+        nodes = ntff.box_nodes(lo, hi)
+        E, H = ntff.dipole_fields((nodes - c).astype(float), k)
+        th = np.arange(0, 180.1, 5.0)
+        e = []
+        for phi in (0, 45, 90):
+            S = ntff.farfield_3d(nodes, E, H, lo, hi, k, th, phi, c, 1.0)
+            t, p = np.deg2rad(th), np.deg2rad(phi)
+            ref = k ** 6 * (1 - (np.sin(t) * np.cos(p)) ** 2) / (16 * np.pi ** 2)
+            e.append(np.abs(S - ref).max() / ref.max())
+        errs.append(max(e))
+    assert errs[1] < 5e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5

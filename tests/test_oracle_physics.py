@@ -1,0 +1,93 @@
+"""Oracle end-to-end physics pins: Fresnel (section 3.1), open boundary /
+absorbing layer energy decay (section 2.2), Lorenz-Mie (section 3.2)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mie, run
+from oracle.analytic import fresnel_normal, fresnel_oblique
+from oracle.core import Oracle
+
+
+def _row_phasors(case):
+    """DFT of E (and H) along the row y = 0 over the last period."""
+    o = Oracle(case.nx, case.ny, 1, case.absorb, W.SIGMA_MAX)
+    o.set_eps(case.eps)
+    kh, eh = W.plane_wave_2d(case.theta_deg, case.pol)
+    o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    w0, wl = case.window
+    o.set_dft(np.arange(case.nx), w0, wl)
+    o.step(case.steps)
+    return o.get_dft()
+
+
+@pytest.mark.parametrize("theta,pol", [(0.0, "TM"), (30.0, "TM"), (0.0, "TE"), (30.0, "TE")])
+def test_fresnel_planar_interface(theta, pol):
+    """Planar interface eps_r = 2.25 at x >= 128 (section 3.1, Eq. ref_trans;
+    oblique: textbook s/p forms, TM_z = s).  Normal incidence -- the paper's
+    own test -- must hold the paper's ~1 %.  At 30 degrees the transmitted
+    amplitude still must; the reflected one carries the absorbing layer's
+    oblique reflection of the transmitted wave (an extrapolation boundary
+    reflects ~(1 - cos t)/(1 + cos t) off-normal), so it is held to 0.03."""
+    case = W.fresnel_case(theta, pol)
+    tot = _row_phasors(case)
+    inc = _row_phasors(W.vacuum_companion(case))
+    E_t, E_i = tot[:, :3], inc[:, :3]
+    amp = lambda v: np.sqrt(np.sum(np.abs(v) ** 2, axis=1))
+    vac = slice(20 + 4, case.nx // 2 - 4)
+    die = slice(case.nx // 2 + 4, case.nx - 20 - 4)
+    r_meas = np.mean(amp(E_t[vac] - E_i[vac]) / amp(E_i[vac]))
+    t_meas = np.mean(amp(E_t[die]) / amp(E_i[die]))
+    if theta == 0:
+        r_ref, t_ref = fresnel_normal(2.25)
+    else:
+        r_ref, t_ref, _ = fresnel_oblique(2.25, theta, "s" if pol == "TM" else "p")
+    assert abs(r_meas - abs(r_ref)) < (0.01 if theta == 0 else 0.03), (r_meas, r_ref)
+    assert abs(t_meas - abs(t_ref)) < 0.01, (t_meas, t_ref)
+    if pol == "TM" and theta == 0:
+        # phase: E_r/E_i at the interface is real and negative
+        k = 2 * np.pi / case.lam
+        x = np.arange(case.nx)
+        ratio = (E_t[vac, 2] - E_i[vac, 2]) / E_i[vac, 2] * np.exp(-2j * k * (x[vac] - 127.5))
+        assert np.real(np.mean(ratio)) < -0.19
+
+
+def test_absorbing_layer_energy_decay():
+    """Section 2.2 open-boundary check: a pulse leaving the domain leaves
+    ~1e-3 of the peak energy once the main packet has gone and <= 1e-5
+    later (measured in a 2-D box absorbing on all faces)."""
+    n = 160
+    o = Oracle(n, n, 1, (20, 20, 0), W.SIGMA_MAX)
+    y, x = np.mgrid[0:n, 0:n]
+    f = np.zeros((1, n, n, 7, 6))
+    for i in range(1, 7):
+        f[0, :, :, i, 2] = np.exp(-((x - 80) ** 2 + (y - 80) ** 2) / 32.0) / 6.0
+    o.set_state(f)
+    E, H = o.fields()
+    e0 = np.sum(E ** 2 + H ** 2)
+    o.step(400)
+    E, H = o.fields()
+    assert np.sum(E ** 2 + H ** 2) / e0 < 2e-3
+    o.step(800)
+    E, H = o.fields()
+    assert np.sum(E ** 2 + H ** 2) / e0 < 1e-5
+
+
+@pytest.mark.slow
+def test_lbm_cylinder_matches_mie():
+    """End-to-end (sections 2.3-2.4, 3.2): small dielectric cylinder, TM and
+    TE, |S(theta)|^2 from the NTFF of the oracle run vs Lorenz-Mie.  At this
+    coarse resolution (a = 10.5 cells, lambda = 32) the staircase boundary
+    dominates: the series at the area-equivalent radius is the sharper
+    reference."""
+    th = np.arange(0, 360, 0.5)
+    for pol, bound in (("TM", 0.015), ("TE", 0.015)):
+        case = W.cylinder_case(2.25, pol, n=192, a=10.5, lam=32.0, W=32, steps=2400, half=19.5)
+        tot = run.run_2d(case, W.SIGMA_MAX, W.RAMP_PERIODS)
+        inc = run.run_2d(W.vacuum_companion(case), W.SIGMA_MAX, W.RAMP_PERIODS)
+        S = run.intensity_2d(case, tot, inc, th)
+        aeq = np.sqrt(np.count_nonzero(case.eps > 1) / np.pi)
+        ref = mie.cylinder_S2(th, 2 * np.pi * aeq / 32.0, 1.5, pol)
+        assert run.normalized_rms(S, ref) < bound, (pol, run.normalized_rms(S, ref))
+        # forward-backward mirror symmetry of normal incidence
+        assert np.allclose(S[1:360], S[719:360:-1], rtol=1e-6, atol=1e-9 * S.max())
