@@ -1,0 +1,162 @@
+/*
+ * lbm_em.h -- C ABI of the MI355X (gfx950) electromagnetic lattice Boltzmann
+ * library: the hot path of "Lattice Boltzmann method for electromagnetic wave
+ * scattering" (Khan, Thampi, Roy; arXiv 2510.11042).
+ *
+ * The problem the calls follow (paper sections 2 and 3):
+ *   - Maxwell's equations on a D3Q7 lattice, vector distributions e_i, h_i,
+ *     tau = 1/2 update  e_i(r + c_i, t+1) = 2 e_i^eq - e_i   (section 2.1,
+ *     Eq. LBGK_equation) with the equilibria of Eq. EDF; c = 1/3 lattice units.
+ *   - a per-cell relative permittivity eps_r(x) (mu_r = 1, section 3.1 end);
+ *   - a linearly polarised plane wave of wavelength lambda (cells);
+ *   - an open boundary (section 2.2) inside a graded absorbing layer;
+ *   - steady-state time stepping, a one-period DFT of E and H on a closed
+ *     contour and the near-to-far-field transform to the angular scattering
+ *     intensity |S(theta)|^2 / |S(theta, phi)|^2 (sections 2.3, 2.4).
+ *
+ * Conventions for every call
+ *   - Return value: LBM_EM_OK or a negative lbm_em_status; the library never
+ *     aborts or throws across this boundary.  lbm_em_last_error() gives a
+ *     message for the last failing call on the calling thread.
+ *   - Arrays are indexed [z][y][x] with x fastest (nx*ny*nz elements).
+ *   - A handle is not thread safe.  All device work of a handle is ordered
+ *     on the stream given at creation; calls that return host data
+ *     synchronise that stream before returning.
+ *   - Ownership: the library owns all device state of a handle (allocated at
+ *     create, freed at destroy).  Caller arrays are only read or written
+ *     during the call (device pointers: until the work queued by the call
+ *     has run on the handle's stream).
+ */
+#ifndef LBM_EM_H
+#define LBM_EM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_EM_OK = 0,
+    LBM_EM_EINVAL = -1,       /* bad argument (size, pointer, range)            */
+    LBM_EM_ENOMEM = -2,       /* device allocation failed                         */
+    LBM_EM_EDEVICE = -3,      /* no HIP device or a HIP runtime error             */
+    LBM_EM_ESTATE = -4,       /* call not valid in the handle's current state     */
+    LBM_EM_EUNSUPPORTED = -5  /* valid request this build does not implement      */
+} lbm_em_status;
+
+typedef struct lbm_em *lbm_em_handle;
+
+/* Field layout of a handle.  2-D runs are D3Q7 on nz == 1 with z streaming the
+ * identity; TM carries (E_z, H_x, H_y) -- E along the invariant axis, the
+ * paper's TM incidence on cylinders (section 3.2) -- and TE (E_x, E_y, H_z). */
+enum { LBM_EM_TM = 0, LBM_EM_TE = 1, LBM_EM_3D = 2 };
+enum { LBM_EM_FP32 = 0, LBM_EM_FP64 = 1 };
+enum { LBM_EM_HOST = 0, LBM_EM_DEVICE = 1 };
+
+typedef struct {
+    int32_t nx, ny, nz;     /* cells; nz must be 1 for TM/TE                        */
+    int32_t pol;            /* LBM_EM_TM, LBM_EM_TE or LBM_EM_3D                     */
+    int32_t precision;      /* LBM_EM_FP32 (storage and arithmetic) or LBM_EM_FP64   */
+    int32_t absorb[3];      /* absorbing-layer width W per axis, 0 = periodic axis;
+                               2W <= n.  Layer strength sigma(d) = sigma_max (d/W)^2,
+                               d = 1..W counted from the layer's inner edge          */
+    double sigma_max;       /* e.g. 0.25                                              */
+    void *stream;           /* hipStream_t to order all work on; NULL = null stream  */
+} lbm_em_config;
+
+/* Incident plane wave E = g(t) E0 ehat sin(omega t - k khat.(r - center)),
+ * H = khat x E, omega = 2 pi/(3 lambda), k = 2 pi/lambda, g(t) =
+ * sin^2(pi t/(2 t_r)) for t < t_r = ramp_periods * 3 lambda, 1 afterwards.
+ * It is imposed in absorbing-layer cells whose eps_r is exactly 1; the layer
+ * relaxes every other layer cell towards zero field. */
+typedef struct {
+    double lambda;          /* free-space wavelength in cells; 3*lambda must be integral */
+    double khat[3];         /* unit propagation direction (in-plane for TM/TE)           */
+    double ehat[3];         /* unit E polarisation, perpendicular to khat;
+                               TM: +-z, TE: in-plane                                       */
+    double amplitude;       /* E0                                                          */
+    double ramp_periods;    /* ramp length in periods                                      */
+    double center[3];       /* phase reference point in cell coordinates                   */
+} lbm_em_plane_wave;
+
+/* Create a handle: allocates the distributions (reduced exact state: 11
+ * scalars per cell in 2-D, 27 in 3-D, two buffers), eps_r (initialised to 1)
+ * and zeroes the state (t = 0).  *out is set only on success.
+ * Errors: EINVAL for bad sizes / pointers, EDEVICE without a HIP device,
+ * ENOMEM when device memory runs out. */
+lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out);
+
+/* Release all device memory of the handle (synchronises its stream). */
+lbm_em_status lbm_em_destroy(lbm_em_handle h);
+
+/* Set eps_r(x) (paper section 2.1: it enters the rest equilibrium and
+ * E = D/eps_r).  eps: nx*ny*nz values, where = LBM_EM_HOST or LBM_EM_DEVICE,
+ * dtype = LBM_EM_FP32 (float) or LBM_EM_FP64 (double).  Values are copied.
+ * Errors: EINVAL if a value is < 1 or not finite (checked on the host copy). */
+lbm_em_status lbm_em_set_permittivity(lbm_em_handle h, const void *eps, int32_t where,
+                                      int32_t dtype);
+
+/* Set the incident plane wave (see lbm_em_plane_wave).  EINVAL if khat or
+ * ehat is not a unit vector, not perpendicular, 3*lambda is not integral,
+ * or the polarisation does not match the handle (TM: ehat = +-z; TE/TM:
+ * khat_z = 0). */
+lbm_em_status lbm_em_set_source(lbm_em_handle h, const lbm_em_plane_wave *pw);
+
+/* Record E and H phasors on the surface of the node box [lo, hi] (inclusive
+ * cell coordinates; in 2-D lo[2] = hi[2] = 0) and at the probe node
+ * ((lo+hi)/2) by a running DFT over the steps [window_start,
+ * window_start + window_len):  X += (2/window_len) F(t) exp(-j omega t)
+ * (section 2.4, "one period of the steady-state oscillation").  Clears the
+ * accumulators.  EINVAL if the box is not strictly inside the grid, is
+ * thinner than 3 nodes, or the window is empty. */
+lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_t hi[3],
+                              int64_t window_start, int64_t window_len);
+
+/* Advance n >= 0 time steps (asynchronous on the handle's stream): pull
+ * streaming with the open boundary, moments, tau = 1/2 collision, absorbing
+ * layer / source, contour DFT -- one fused kernel per step.  Steps are
+ * replayed from a captured HIP graph in chunks. */
+lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
+
+/* Advance `count` handles n steps together: one launch per step covers all
+ * instances (a flattened tile worklist).  All handles must share precision,
+ * polarisation and stream and be at the same time step.  Results are
+ * bit-identical to lbm_em_step on each handle. */
+lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);
+
+/* Current time step t (number of steps taken). */
+lbm_em_status lbm_em_time(lbm_em_handle h, int64_t *t);
+
+/* Fields at the current time t: E and H, each nx*ny*nz*3 values [cell][3]
+ * in the handle's precision, on the host (synchronises) or device. */
+lbm_em_status lbm_em_get_fields(lbm_em_handle h, void *E, void *H, int32_t where);
+
+/* Raw DFT phasors: out[(node*6 + c)*2 + {0,1}] = (re, im) of component c in
+ * (Ex, Ey, Ez, Hx, Hy, Hz) for the box-surface nodes in ascending linear
+ * cell index, followed by the probe node.  *n_nodes receives the number of
+ * surface nodes (the array must hold (n_nodes + 1) * 12 doubles; pass
+ * out = NULL to query the count).  Synchronises. */
+lbm_em_status lbm_em_get_phasors(lbm_em_handle h, double *out, int32_t *n_nodes);
+
+/* Angular scattering intensity (sections 2.3-2.4).  Scattered phasors are
+ * those of h minus those of `incident` (a companion handle with eps_r = 1 and
+ * the same grid, source and contour), transformed with the background
+ * (eps = mu = 1, unit impedance) far-field formulas, and normalised by the
+ * incident probe amplitude |ehat . E_inc| (TM, 3-D) or |hhat . H_inc| (TE).
+ * Angles: theta from khat; 2-D: in the plane, counter-clockwise about +z
+ * (phi ignored); 3-D: phi about khat measured from ehat.  Host arrays of
+ * n_angles; out_S2 receives |S|^2 (2-D: k r |E_s|^2/|E_i|^2, Eq. S2D; 3-D:
+ * k^2 r^2 |E_s|^2/|E_i|^2, Eq. S3D).  incident = NULL: no subtraction and
+ * normalisation by the source amplitude.  ESTATE if the DFT window has not
+ * been completed.  Synchronises. */
+lbm_em_status lbm_em_farfield(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
+                              const double *phi_deg, int32_t n_angles, double *out_S2);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lbm_em_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_EM_H */

@@ -1,0 +1,83 @@
+"""ctypes binding of liblbm_em.so (include/lbm_em.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Loading fails loudly when the library has not been built -- there
+is no fallback implementation.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_em.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+TM, TE, D3 = 0, 1, 2
+FP32, FP64 = 0, 1
+HOST, DEVICE = 0, 1
+
+# Every exported symbol the header declares (checked by the ABI test).
+EXPORTS = [
+    "lbm_em_create", "lbm_em_destroy", "lbm_em_set_permittivity", "lbm_em_set_source",
+    "lbm_em_set_ntff", "lbm_em_step", "lbm_em_step_many", "lbm_em_time", "lbm_em_get_fields",
+    "lbm_em_get_phasors", "lbm_em_farfield", "lbm_em_last_error",
+]
+
+
+class LbmEmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbm_em status {status}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pol", C.c_int32),
+                ("precision", C.c_int32), ("absorb", C.c_int32 * 3), ("sigma_max", C.c_double),
+                ("stream", C.c_void_p)]
+
+
+class PlaneWave(C.Structure):
+    _fields_ = [("lam", C.c_double), ("khat", C.c_double * 3), ("ehat", C.c_double * 3),
+                ("amplitude", C.c_double), ("ramp_periods", C.c_double), ("center", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm_em.so once; raise if it is missing (no silent fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python paper_2510_11042_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        S = C.c_int
+        sig = {
+            "lbm_em_create": [C.POINTER(Config), C.POINTER(C.c_void_p)],
+            "lbm_em_destroy": [H],
+            "lbm_em_set_permittivity": [H, C.c_void_p, C.c_int32, C.c_int32],
+            "lbm_em_set_source": [H, C.POINTER(PlaneWave)],
+            "lbm_em_set_ntff": [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int64, C.c_int64],
+            "lbm_em_step": [H, C.c_int64],
+            "lbm_em_step_many": [C.POINTER(C.c_void_p), C.c_int32, C.c_int64],
+            "lbm_em_time": [H, C.POINTER(C.c_int64)],
+            "lbm_em_get_fields": [H, C.c_void_p, C.c_void_p, C.c_int32],
+            "lbm_em_get_phasors": [H, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
+            "lbm_em_farfield": [H, H, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
+                                C.POINTER(C.c_double)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = S
+        L.lbm_em_last_error.restype = C.c_char_p
+        L.lbm_em_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != OK:
+        raise LbmEmError(status, lib().lbm_em_last_error().decode())
+    return status

@@ -1,0 +1,612 @@
+// kernels.hpp -- gfx950 kernels of the electromagnetic lattice Boltzmann hot path.
+//
+// Scheme (paper section 2.1, Eq. LBGK_equation and Eq. EDF): D3Q7 velocities
+// c_0 = 0, +-x, +-y, +-z; vector distributions e_i, h_i; tau = 1/2 update
+//   f_i(r + c_i, t+1) = 2 f_i^eq(r,t) - f_i(r,t),
+//   e_i^eq = (E - c_i x H)/6, h_i^eq = (H + c_i x E)/6 (i != 0),
+//   e_0^eq = (eps_r - 1) E, h_0^eq = (mu_r - 1) H, with mu_r = 1 here,
+// and fields from the zeroth moments, E = sum_i e_i / eps_r, H = sum_i h_i.
+//
+// Exact reduced state.  For every moving direction the combination
+// e_i_perp + c_i x h_i has zero equilibrium, so collision only flips its sign,
+// streaming carries it along, and the absorbing layer relaxes it towards
+// zero: from a zero (or equilibrium) start it stays zero and
+// h_i = eta_i c_i + c_i x e_i with eta_i = h_i . c_i.  h_0 stays zero for
+// mu_r = 1.  That leaves 27 scalars per cell in 3-D (e_i and eta_i for six
+// directions, e_0).  In 2-D (nz = 1, z streaming the identity) the +z and -z
+// populations never move and have equal equilibria, so they stay equal and
+// merge into one "z-pair", and the rest population is slaved to it,
+// e_0 = 6 (eps_r - 1) e_zpair (the difference flips sign every step and
+// starts at zero).  A 2-D polarisation then needs 11 scalars per cell:
+//   TM (E_z, H_x, H_y): planes 0..3  e_z of +x,-x,+y,-y
+//                       planes 4..7  h_x of +-x, h_y of +-y   (eta)
+//                       planes 8..10 z-pair e_z, h_x, h_y
+//   TE (E_x, E_y, H_z): planes 0..3  e_x of +x,-x,+y,-y
+//                       planes 4..7  e_y of +x,-x,+y,-y
+//                       planes 8..10 z-pair e_x, e_y, h_z
+//   3-D:                planes 4d..4d+2 e of direction d (+x,-x,+y,-y,+z,-z),
+//                       plane 4d+3 eta_d, planes 24..26 e_0.
+// Fields computed from this state equal those of the literal 42-scalar scheme.
+//
+// Storage: structure of arrays, one plane per scalar, x fastest, each buffer
+// holding the post-collision state f*(t-1); a step PULLS f_i(r,t) =
+// f*_i(r - c_i, t-1).  On an absorbing axis the pull is clamped at the faces,
+// which is exactly the paper's open boundary (section 2.2, f_i^L = f_i^{L-dx}
+// for incoming populations): the incoming population of the boundary node
+// takes the post-collision value of the node itself, the one the first
+// interior node received by streaming.  Periodic axes wrap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum { TM = 0, TE = 1, D3 = 2 };
+
+struct Box {
+    int lo[3], hi[3];
+};
+
+// Unique index of a node on the surface of a node box (2-D: nz == 1 box with
+// lo[2] == hi[2]).  Ordering: 2-D bottom edge, top edge, left edge without
+// corners, right edge without corners; 3-D faces z_lo, z_hi (full), y_lo,
+// y_hi (z strictly inside), x_lo, x_hi (y and z strictly inside).
+__host__ __device__ inline int64_t box_nodes(const Box &b, int dim) {
+    int64_t nbx = b.hi[0] - b.lo[0] + 1, nby = b.hi[1] - b.lo[1] + 1, nbz = b.hi[2] - b.lo[2] + 1;
+    if (dim == 2) return 2 * nbx + 2 * (nby - 2);
+    return 2 * nbx * nby + 2 * nbx * (nbz - 2) + 2 * (nby - 2) * (nbz - 2);
+}
+
+__host__ __device__ inline int64_t box_node_index(const Box &b, int dim, int x, int y, int z) {
+    int64_t nbx = b.hi[0] - b.lo[0] + 1, nby = b.hi[1] - b.lo[1] + 1, nbz = b.hi[2] - b.lo[2] + 1;
+    int64_t dx = x - b.lo[0], dy = y - b.lo[1], dz = z - b.lo[2];
+    if (dim == 2) {
+        if (y == b.lo[1]) return dx;
+        if (y == b.hi[1]) return nbx + dx;
+        if (x == b.lo[0]) return 2 * nbx + (dy - 1);
+        return 2 * nbx + (nby - 2) + (dy - 1);
+    }
+    int64_t fxy = nbx * nby, fxz = nbx * (nbz - 2), fyz = (nby - 2) * (nbz - 2);
+    if (z == b.lo[2]) return dy * nbx + dx;
+    if (z == b.hi[2]) return fxy + dy * nbx + dx;
+    if (y == b.lo[1]) return 2 * fxy + (dz - 1) * nbx + dx;
+    if (y == b.hi[1]) return 2 * fxy + fxz + (dz - 1) * nbx + dx;
+    if (x == b.lo[0]) return 2 * fxy + 2 * fxz + (dz - 1) * (nby - 2) + (dy - 1);
+    return 2 * fxy + 2 * fxz + fyz + (dz - 1) * (nby - 2) + (dy - 1);
+}
+
+__host__ __device__ inline bool on_box(const Box &b, int dim, int x, int y, int z) {
+    bool in = x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] &&
+              z >= b.lo[2] && z <= b.hi[2];
+    if (!in) return false;
+    bool sx = x == b.lo[0] || x == b.hi[0];
+    bool sy = y == b.lo[1] || y == b.hi[1];
+    if (dim == 2) return sx || sy;
+    return sx || sy || z == b.lo[2] || z == b.hi[2];
+}
+
+// Everything one step needs.  Per-step quantities (source ramp and phase,
+// DFT factor) are derived in the kernel from the step index t, so the same
+// launch can be replayed from a graph with t read from device memory.
+template <typename T>
+struct StepArgs {
+    int nx, ny, nz;
+    int64_t sy, sz, plane;      // element strides: row, slab, plane
+    int W[3];                   // absorbing width per axis, 0 = periodic
+    T sigma_max;
+    const T *__restrict__ src;  // f*(t-1), nplanes planes
+    T *__restrict__ dst;        // f*(t)
+    const T *__restrict__ eps;
+    const int64_t *t_base;      // graph replay: t = *t_base + t_off; else NULL
+    int64_t t_off;
+    // plane-wave source
+    int src_on;
+    int period;                 // T = 3 lambda steps
+    double amp, t_ramp, inv_lam;
+    double khat[3], ehat[3], hhat[3], rc[3];
+    // running DFT on the contour box + probe node
+    int dft_on;
+    Box box;
+    int probe[3];
+    int64_t nnodes;
+    int64_t win0, winlen;
+    double *acc;                // (nnodes + 1) x 6 x (re, im)
+    int tiles_x, tiles_y;       // tile grid of the launch (3-D: per z slab)
+};
+
+template <typename T>
+__device__ inline T sigma_axis(int x, int n, int W, T smax) {
+    if (W <= 0) return T(0);
+    int d = 0;
+    if (x < W) d = W - x;
+    else if (x >= n - W) d = x - (n - W) + 1;
+    if (d == 0) return T(0);
+    T u = T(d) / T(W);
+    return smax * u * u;
+}
+
+__device__ inline int64_t step_time(const int64_t *t_base, int64_t t_off) {
+    return (t_base ? *t_base : 0) + t_off;
+}
+
+// Incident plane-wave value w = g(t) E0 sin(omega t - k khat.(r - rc)) at a
+// cell; the phase is reduced exactly with t mod T (T integral) in FP64.
+template <typename T>
+__device__ inline double plane_wave(const StepArgs<T> &a, int64_t t, int x, int y, int z) {
+    double g = 1.0;
+    if ((double)t < a.t_ramp) {
+        double s = sin(M_PI * (double)t / (2.0 * a.t_ramp));
+        g = s * s;
+    }
+    double tf = (double)(t % a.period) / (double)a.period;
+    double kr = a.khat[0] * ((double)x - a.rc[0]) + a.khat[1] * ((double)y - a.rc[1]) +
+                a.khat[2] * ((double)z - a.rc[2]);
+    double u = tf - kr * a.inv_lam;
+    u -= floor(u);
+    return g * a.amp * sin(2.0 * M_PI * u);
+}
+
+// Fields at a cell from pulled 2-D reduced populations.
+//   TM: F = (E_z, H_x, H_y); TE: F = (E_x, E_y, H_z).
+template <typename T, int POL>
+__device__ inline void fields2d(const T s[11], T eps, T inv_eps, T F[3]) {
+    const T rest = T(6) * eps - T(4);  // z-pair (x2) plus slaved rest population
+    if (POL == TM) {
+        F[0] = (s[0] + s[1] + s[2] + s[3] + rest * s[8]) * inv_eps;
+        F[1] = s[4] + s[5] + s[2] - s[3] + T(2) * s[9];
+        F[2] = s[6] + s[7] - s[0] + s[1] + T(2) * s[10];
+    } else {
+        F[0] = (s[0] + s[1] + s[2] + s[3] + rest * s[8]) * inv_eps;
+        F[1] = (s[4] + s[5] + s[6] + s[7] + rest * s[9]) * inv_eps;
+        F[2] = s[4] - s[5] - s[2] + s[3] + T(2) * s[10];
+    }
+}
+
+// Equilibrium of the 11 reduced scalars for fields F, scaled by `scale`
+// (scale = 2 gives 2 f^eq for the collision, 1 the plain equilibrium).
+template <typename T, int POL>
+__device__ inline void equilibrium2d(const T F[3], T scale, T q[11]) {
+    const T c = scale / T(6);
+    if (POL == TM) {
+        const T Ez = F[0], Hx = F[1], Hy = F[2];
+        q[0] = c * (Ez - Hy);
+        q[1] = c * (Ez + Hy);
+        q[2] = c * (Ez + Hx);
+        q[3] = c * (Ez - Hx);
+        q[4] = q[5] = c * Hx;
+        q[6] = q[7] = c * Hy;
+        q[8] = c * Ez;
+        q[9] = c * Hx;
+        q[10] = c * Hy;
+    } else {
+        const T Ex = F[0], Ey = F[1], Hz = F[2];
+        q[0] = q[1] = c * Ex;
+        q[2] = c * (Ex - Hz);
+        q[3] = c * (Ex + Hz);
+        q[4] = c * (Ey + Hz);
+        q[5] = c * (Ey - Hz);
+        q[6] = q[7] = c * Ey;
+        q[8] = c * Ex;
+        q[9] = c * Ey;
+        q[10] = c * Hz;
+    }
+}
+
+// Accumulate the running DFT of the fields at a contour / probe node.
+template <typename T>
+__device__ inline void dft_accumulate(const StepArgs<T> &a, int64_t t, int dim, int x, int y,
+                                      int z, const double E[3], const double H[3]) {
+    if (!a.dft_on || t < a.win0 || t >= a.win0 + a.winlen) return;
+    bool surf = on_box(a.box, dim, x, y, z);
+    bool probe = x == a.probe[0] && y == a.probe[1] && z == a.probe[2];
+    if (!surf && !probe) return;
+    double ph = 2.0 * M_PI * (double)(t % a.period) / (double)a.period;
+    double sc = 2.0 / (double)a.winlen;
+    double cr = sc * cos(ph), ci = -sc * sin(ph);
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t node;
+        if (pass == 0) {
+            if (!surf) continue;
+            node = box_node_index(a.box, dim, x, y, z);
+        } else {
+            if (!probe) continue;
+            node = a.nnodes;
+        }
+        double *p = a.acc + node * 12;
+        for (int c = 0; c < 3; ++c) {
+            p[2 * c] += E[c] * cr;
+            p[2 * c + 1] += E[c] * ci;
+            p[6 + 2 * c] += H[c] * cr;
+            p[6 + 2 * c + 1] += H[c] * ci;
+        }
+    }
+}
+
+// Pull neighbours with the open boundary (clamp) or periodic wrap.
+__device__ inline int pull_lo(int x, int n, int W) { return x > 0 ? x - 1 : (W ? 0 : n - 1); }
+__device__ inline int pull_hi(int x, int n, int W) { return x < n - 1 ? x + 1 : (W ? n - 1 : 0); }
+
+// ---------------------------------------------------------------------------
+// 2-D fused step: pull + moments + DFT + collision + layer/source + store
+// ---------------------------------------------------------------------------
+template <typename T, int POL>
+__global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
+    const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
+    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
+    const int64_t P = a.plane, row = (int64_t)y * a.sy, c = row + x;
+    const int64_t rm = (int64_t)ym * a.sy, rp = (int64_t)yp * a.sy;
+    const T *s = a.src;
+    T f[11];
+    f[0] = s[0 * P + row + xm];   // +x from x-1
+    f[1] = s[1 * P + row + xp];   // -x from x+1
+    f[2] = s[2 * P + rm + x];     // +y from y-1
+    f[3] = s[3 * P + rp + x];     // -y from y+1
+    f[4] = s[4 * P + row + xm];
+    f[5] = s[5 * P + row + xp];
+    f[6] = s[6 * P + rm + x];
+    f[7] = s[7 * P + rp + x];
+    f[8] = s[8 * P + c];
+    f[9] = s[9 * P + c];
+    f[10] = s[10 * P + c];
+    const T eps = a.eps[c];
+    const T inv_eps = T(1) / eps;
+    T F[3];
+    fields2d<T, POL>(f, eps, inv_eps, F);
+
+    const int64_t t = step_time(a.t_base, a.t_off);
+    if (a.dft_on) {
+        double E[3] = {0, 0, 0}, H[3] = {0, 0, 0};
+        if (POL == TM) { E[2] = F[0]; H[0] = F[1]; H[1] = F[2]; }
+        else { E[0] = F[0]; E[1] = F[1]; H[2] = F[2]; }
+        dft_accumulate(a, t, 2, x, y, 0, E, H);
+    }
+
+    T q[11];
+    equilibrium2d<T, POL>(F, T(2), q);
+#pragma unroll
+    for (int i = 0; i < 11; ++i) f[i] = q[i] - f[i];
+
+    const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max),
+                       sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max));
+    if (sig > T(0)) {
+        T R[3] = {0, 0, 0};
+        if (a.src_on && eps == T(1)) {
+            const T w = (T)plane_wave(a, t, x, y, 0);
+            if (POL == TM) { R[0] = w * (T)a.ehat[2]; R[1] = w * (T)a.hhat[0]; R[2] = w * (T)a.hhat[1]; }
+            else { R[0] = w * (T)a.ehat[0]; R[1] = w * (T)a.ehat[1]; R[2] = w * (T)a.hhat[2]; }
+        }
+        T qr[11];
+        equilibrium2d<T, POL>(R, T(1), qr);
+#pragma unroll
+        for (int i = 0; i < 11; ++i) f[i] = f[i] - sig * (f[i] - qr[i]);
+    }
+    T *d = a.dst;
+#pragma unroll
+    for (int i = 0; i < 11; ++i) d[i * P + c] = f[i];
+}
+
+// ---------------------------------------------------------------------------
+// 3-D fused step (27 scalars)
+// ---------------------------------------------------------------------------
+__device__ constexpr int C3[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+template <typename T>
+__device__ inline void cross3(const T a[3], const T b[3], T o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename T>
+__device__ inline void fields3d(const T f[27], T inv_eps, T E[3], T H[3]) {
+    T D[3] = {f[24], f[25], f[26]}, B[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const T *e = f + 4 * d;
+        const T eta = f[4 * d + 3];
+        T cv[3] = {T(C3[d][0]), T(C3[d][1]), T(C3[d][2])}, cxe[3];
+        cross3(cv, e, cxe);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            D[k] += e[k];
+            B[k] += eta * cv[k] + cxe[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        E[k] = D[k] * inv_eps;
+        H[k] = B[k];
+    }
+}
+
+template <typename T>
+__device__ inline void equilibrium3d(const T E[3], const T H[3], T eps, T scale, T q[27]) {
+    const T c = scale / T(6);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        T cv[3] = {T(C3[d][0]), T(C3[d][1]), T(C3[d][2])}, cxh[3];
+        cross3(cv, H, cxh);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[4 * d + k] = c * (E[k] - cxh[k]);
+        q[4 * d + 3] = c * (cv[0] * H[0] + cv[1] * H[1] + cv[2] * H[2]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q[24 + k] = scale * (eps - T(1)) * E[k];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
+    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
+    const int zm = pull_lo(z, a.nz, a.W[2]), zp = pull_hi(z, a.nz, a.W[2]);
+    const int64_t P = a.plane;
+    const int64_t c = (int64_t)z * a.sz + (int64_t)y * a.sy + x;
+    const int64_t src_cell[6] = {
+        (int64_t)z * a.sz + (int64_t)y * a.sy + xm, (int64_t)z * a.sz + (int64_t)y * a.sy + xp,
+        (int64_t)z * a.sz + (int64_t)ym * a.sy + x, (int64_t)z * a.sz + (int64_t)yp * a.sy + x,
+        (int64_t)zm * a.sz + (int64_t)y * a.sy + x, (int64_t)zp * a.sz + (int64_t)y * a.sy + x};
+    const T *s = a.src;
+    T f[27];
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[4 * d + k] = s[(4 * d + k) * P + src_cell[d]];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[24 + k] = s[(24 + k) * P + c];
+    const T eps = a.eps[c];
+    const T inv_eps = T(1) / eps;
+    T E[3], H[3];
+    fields3d(f, inv_eps, E, H);
+
+    const int64_t t = step_time(a.t_base, a.t_off);
+    if (a.dft_on) {
+        double Ed[3] = {E[0], E[1], E[2]}, Hd[3] = {H[0], H[1], H[2]};
+        dft_accumulate(a, t, 3, x, y, z, Ed, Hd);
+    }
+
+    T q[27];
+    equilibrium3d(E, H, eps, T(2), q);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = q[i] - f[i];
+
+    const T sig = fmax(fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max),
+                            sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max)),
+                       sigma_axis<T>(z, a.nz, a.W[2], a.sigma_max));
+    if (sig > T(0)) {
+        T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
+        if (a.src_on && eps == T(1)) {
+            const T w = (T)plane_wave(a, t, x, y, z);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Er[k] = w * (T)a.ehat[k];
+                Hr[k] = w * (T)a.hhat[k];
+            }
+        }
+        T qr[27];
+        equilibrium3d(Er, Hr, eps, T(1), qr);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) f[i] = f[i] - sig * (f[i] - qr[i]);
+    }
+    T *d = a.dst;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) d[i * P + c] = f[i];
+}
+
+// ---------------------------------------------------------------------------
+// Field snapshot at the current time: pull + moments only.
+// ---------------------------------------------------------------------------
+template <typename T, int POL>
+__global__ void __launch_bounds__(256) k_fields(StepArgs<T> a, T *E, T *H) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int64_t P = a.plane;
+    const int64_t cell = ((int64_t)z * a.ny + y) * a.nx + x;   // dense output index
+    T Ev[3] = {0, 0, 0}, Hv[3] = {0, 0, 0};
+    const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
+    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
+    if (POL != D3) {
+        const int64_t row = (int64_t)y * a.sy, c = row + x;
+        const int64_t rm = (int64_t)ym * a.sy, rp = (int64_t)yp * a.sy;
+        const T *s = a.src;
+        T f[11] = {s[0 * P + row + xm], s[1 * P + row + xp], s[2 * P + rm + x], s[3 * P + rp + x],
+                   s[4 * P + row + xm], s[5 * P + row + xp], s[6 * P + rm + x], s[7 * P + rp + x],
+                   s[8 * P + c],        s[9 * P + c],        s[10 * P + c]};
+        const T eps = a.eps[c];
+        T F[3];
+        fields2d<T, POL>(f, eps, T(1) / eps, F);
+        if (POL == TM) { Ev[2] = F[0]; Hv[0] = F[1]; Hv[1] = F[2]; }
+        else { Ev[0] = F[0]; Ev[1] = F[1]; Hv[2] = F[2]; }
+    } else {
+        const int zm = pull_lo(z, a.nz, a.W[2]), zp = pull_hi(z, a.nz, a.W[2]);
+        const int64_t c = (int64_t)z * a.sz + (int64_t)y * a.sy + x;
+        const int64_t src_cell[6] = {
+            (int64_t)z * a.sz + (int64_t)y * a.sy + xm, (int64_t)z * a.sz + (int64_t)y * a.sy + xp,
+            (int64_t)z * a.sz + (int64_t)ym * a.sy + x, (int64_t)z * a.sz + (int64_t)yp * a.sy + x,
+            (int64_t)zm * a.sz + (int64_t)y * a.sy + x, (int64_t)zp * a.sz + (int64_t)y * a.sy + x};
+        T f[27];
+        for (int d = 0; d < 6; ++d)
+            for (int k = 0; k < 4; ++k) f[4 * d + k] = a.src[(4 * d + k) * P + src_cell[d]];
+        for (int k = 0; k < 3; ++k) f[24 + k] = a.src[(24 + k) * P + c];
+        fields3d(f, T(1) / a.eps[c], Ev, Hv);
+    }
+    for (int k = 0; k < 3; ++k) {
+        E[cell * 3 + k] = Ev[k];
+        H[cell * 3 + k] = Hv[k];
+    }
+}
+
+// Copy a dense [z][y][x] array into the pitched eps buffer (any dtype in).
+template <typename Tin, typename T>
+__global__ void k_load_eps(const Tin *in, T *eps, int nx, int ny, int nz, int64_t sy, int64_t sz) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx) return;
+    eps[(int64_t)z * sz + (int64_t)y * sy + x] = (T)in[((int64_t)z * ny + y) * nx + x];
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Device step counter for graph replays (vector store from one lane).
+__global__ void k_set_time(int64_t *t, int64_t value) {
+    if (threadIdx.x == 0) t[0] = value;
+}
+__global__ void k_advance_time(int64_t *t, int64_t by) {
+    if (threadIdx.x == 0) t[0] = t[0] + by;
+}
+
+// ---------------------------------------------------------------------------
+// Near-to-far-field transform: one 256-thread block per observation angle.
+// Scattered phasors X - X_inc on every edge (2-D) / face (3-D) of the box,
+// trapezoid weights, J = n x H, M = -n x E, N = sum w J e^{jk rhat.r'},
+// L = sum w M e^{jk rhat.r'}; reduced with wavefront shuffles + LDS in FP64.
+// out[angle] = (P1re, P1im, P2re, P2im):
+//   2-D TM: P1 = N_z - (rhat x L)_z;  2-D TE: P1 = L_z + (rhat x N)_z;
+//   3-D:    P1 = N_theta + L_phi, P2 = N_phi - L_theta.
+// ---------------------------------------------------------------------------
+struct NtffArgs {
+    const double *acc;      // total-run phasors (nnodes+1) x 12
+    const double *acc_inc;  // incident-run phasors or NULL
+    Box box;
+    int dim, pol;
+    double k;
+    double center[3];
+    double khat[3], ehat[3], bhat[3];   // bhat = khat x ehat (3-D frame)
+    const double *theta;    // radians
+    const double *phi;
+    double *out;
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_ntff(NtffArgs a) {
+    const int ang = blockIdx.x;
+    const double th = a.theta[ang], ph = a.phi[ang];
+    const double ct = cos(th), st = sin(th), cp = cos(ph), sp = sin(ph);
+    double r[3];
+    if (a.dim == 2) {
+        // in-plane: rhat = cos(th) khat + sin(th) (z x khat)
+        r[0] = ct * a.khat[0] - st * a.khat[1];
+        r[1] = ct * a.khat[1] + st * a.khat[0];
+        r[2] = 0.0;
+    } else {
+        for (int k = 0; k < 3; ++k) r[k] = ct * a.khat[k] + st * (cp * a.ehat[k] + sp * a.bhat[k]);
+    }
+    double acc[12];   // N (re,im) x3, L (re,im) x3
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+
+    const Box &b = a.box;
+    const int nseg = a.dim == 2 ? 4 : 6;
+    for (int seg = 0; seg < nseg; ++seg) {
+        const int ax = seg / 2;                     // normal axis
+        const int side = (seg & 1) ? 1 : -1;
+        const int pos = side < 0 ? b.lo[ax] : b.hi[ax];
+        int ua = ax == 0 ? 1 : 0, va = ax == 2 ? 1 : 2;   // in-face axes
+        const int nu = b.hi[ua] - b.lo[ua] + 1;
+        const int nv = a.dim == 2 ? 1 : b.hi[va] - b.lo[va] + 1;
+        const int64_t cnt = (int64_t)nu * nv;
+        for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const int iu = (int)(i % nu), iv = (int)(i / nu);
+            int xyz[3];
+            xyz[ax] = pos;
+            xyz[ua] = b.lo[ua] + iu;
+            if (a.dim == 3) xyz[va] = b.lo[va] + iv;
+            else xyz[2] = 0;
+            double w = (iu == 0 || iu == nu - 1) ? 0.5 : 1.0;
+            if (a.dim == 3) w *= (iv == 0 || iv == nv - 1) ? 0.5 : 1.0;
+            const int64_t node = box_node_index(b, a.dim, xyz[0], xyz[1], xyz[2]);
+            const double *X = a.acc + node * 12;
+            const double *Xi = a.acc_inc ? a.acc_inc + node * 12 : nullptr;
+            double Er[3], Ei[3], Hr[3], Hi[3];
+            for (int k = 0; k < 3; ++k) {
+                Er[k] = X[2 * k] - (Xi ? Xi[2 * k] : 0.0);
+                Ei[k] = X[2 * k + 1] - (Xi ? Xi[2 * k + 1] : 0.0);
+                Hr[k] = X[6 + 2 * k] - (Xi ? Xi[6 + 2 * k] : 0.0);
+                Hi[k] = X[6 + 2 * k + 1] - (Xi ? Xi[6 + 2 * k + 1] : 0.0);
+            }
+            double n[3] = {0, 0, 0};
+            n[ax] = side;
+            // J = n x H, M = -n x E  (complex: real and imaginary parts)
+            double Jr[3], Ji[3], Mr[3], Mi[3];
+            cross3(n, Hr, Jr);
+            cross3(n, Hi, Ji);
+            cross3(n, Er, Mr);
+            cross3(n, Ei, Mi);
+            double rp = 0.0;
+            for (int k = 0; k < 3; ++k) rp += r[k] * ((double)xyz[k] - a.center[k]);
+            double sn, cs;
+            sincos(a.k * rp, &sn, &cs);
+            cs *= w;
+            sn *= w;
+            for (int k = 0; k < 3; ++k) {
+                acc[2 * k] += Jr[k] * cs - Ji[k] * sn;
+                acc[2 * k + 1] += Jr[k] * sn + Ji[k] * cs;
+                acc[6 + 2 * k] += -(Mr[k] * cs - Mi[k] * sn);
+                acc[6 + 2 * k + 1] += -(Mr[k] * sn + Mi[k] * cs);
+            }
+        }
+    }
+    __shared__ double red[4][12];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k < 12; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[12];
+        for (int k = 0; k < 12; ++k) s[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+        // complex vectors N = (s0+is1, s2+is3, s4+is5), L = (s6+is7, ...)
+        double Nr[3] = {s[0], s[2], s[4]}, Ni[3] = {s[1], s[3], s[5]};
+        double Lr[3] = {s[6], s[8], s[10]}, Li[3] = {s[7], s[9], s[11]};
+        double p1r, p1i, p2r = 0.0, p2i = 0.0;
+        if (a.dim == 2) {
+            double rxLr[3], rxLi[3], rxNr[3], rxNi[3];
+            cross3(r, Lr, rxLr);
+            cross3(r, Li, rxLi);
+            cross3(r, Nr, rxNr);
+            cross3(r, Ni, rxNi);
+            if (a.pol == TM) { p1r = Nr[2] - rxLr[2]; p1i = Ni[2] - rxLi[2]; }
+            else { p1r = Lr[2] + rxNr[2]; p1i = Li[2] + rxNi[2]; }
+        } else {
+            double tv[3], pv[3];
+            for (int k = 0; k < 3; ++k) {
+                tv[k] = -st * a.khat[k] + ct * (cp * a.ehat[k] + sp * a.bhat[k]);
+                pv[k] = -sp * a.ehat[k] + cp * a.bhat[k];
+            }
+            double Ntr = 0, Nti = 0, Npr = 0, Npi = 0, Ltr = 0, Lti = 0, Lpr = 0, Lpi = 0;
+            for (int k = 0; k < 3; ++k) {
+                Ntr += Nr[k] * tv[k]; Nti += Ni[k] * tv[k];
+                Npr += Nr[k] * pv[k]; Npi += Ni[k] * pv[k];
+                Ltr += Lr[k] * tv[k]; Lti += Li[k] * tv[k];
+                Lpr += Lr[k] * pv[k]; Lpi += Li[k] * pv[k];
+            }
+            p1r = Ntr + Lpr; p1i = Nti + Lpi;
+            p2r = Npr - Ltr; p2i = Npi - Lti;
+        }
+        a.out[4 * ang + 0] = p1r;
+        a.out[4 * ang + 1] = p1i;
+        a.out[4 * ang + 2] = p2r;
+        a.out[4 * ang + 3] = p2i;
+    }
+}
+
+}  // namespace lbm

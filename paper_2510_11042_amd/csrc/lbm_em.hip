@@ -1,0 +1,584 @@
+// lbm_em.hip -- runtime and C ABI of the gfx950 electromagnetic LBM library.
+//
+// One handle = one scattering instance: reduced-state distributions in two
+// ping-pong buffers (structure of arrays, rows padded to 64 elements), eps_r,
+// plane-wave parameters, the contour DFT accumulators and a device step
+// counter used when step(n) is replayed from a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_em.h"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct ApiError {
+    lbm_em_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(lbm_em_status code, const std::string &msg) { throw ApiError{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(LBM_EM_ENOMEM, std::string(what) + ": out of device memory");
+    fail(LBM_EM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+lbm_em_status guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return LBM_EM_OK;
+    } catch (const ApiError &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return LBM_EM_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return LBM_EM_EDEVICE;
+    }
+}
+
+constexpr int kGraphChunk = 64;   // steps per captured graph
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+void hfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+struct lbm_em {
+    lbm_em_config cfg{};
+    int dim = 2;
+    int nplanes = 11;
+    size_t elem = 4;
+    int64_t sy = 0, sz = 0, plane = 0;  // element strides
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;                        // buf[cur] holds f*(t-1)
+    void *eps = nullptr;
+    int64_t t = 0;
+    hipStream_t stream = nullptr;
+    int bx = 64, by = 4;
+    // source
+    bool src_on = false;
+    lbm_em_plane_wave pw{};
+    double hhat[3] = {0, 0, 0};
+    int period = 0;
+    // contour DFT
+    bool dft_set = false;
+    Box box{};
+    int probe[3] = {0, 0, 0};
+    int64_t nnodes = 0, win0 = 0, winlen = 0;
+    double *acc = nullptr;
+    // graph replay
+    int64_t *t_dev = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // indexed by starting buffer parity
+    int dev = 0;
+};
+
+namespace {
+
+lbm_em *check_handle(lbm_em_handle h) {
+    if (!h) fail(LBM_EM_EINVAL, "null handle");
+    return h;
+}
+
+void select_device(const lbm_em *h) { hip_check(hipSetDevice(h->dev), "hipSetDevice"); }
+
+template <typename T>
+StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
+    StepArgs<T> a{};
+    a.nx = h->cfg.nx;
+    a.ny = h->cfg.ny;
+    a.nz = h->cfg.nz;
+    a.sy = h->sy;
+    a.sz = h->sz;
+    a.plane = h->plane;
+    for (int k = 0; k < 3; ++k) a.W[k] = h->cfg.absorb[k];
+    a.sigma_max = (T)h->cfg.sigma_max;
+    a.src = (const T *)src;
+    a.dst = (T *)dst;
+    a.eps = (const T *)h->eps;
+    a.src_on = h->src_on ? 1 : 0;
+    a.period = h->period > 0 ? h->period : 1;
+    if (h->src_on) {
+        a.amp = h->pw.amplitude;
+        a.t_ramp = h->pw.ramp_periods * (double)h->period;
+        a.inv_lam = 1.0 / h->pw.lambda;
+        for (int k = 0; k < 3; ++k) {
+            a.khat[k] = h->pw.khat[k];
+            a.ehat[k] = h->pw.ehat[k];
+            a.hhat[k] = h->hhat[k];
+            a.rc[k] = h->pw.center[k];
+        }
+    }
+    a.dft_on = h->dft_set ? 1 : 0;
+    a.box = h->box;
+    for (int k = 0; k < 3; ++k) a.probe[k] = h->probe[k];
+    a.nnodes = h->nnodes;
+    a.win0 = h->win0;
+    a.winlen = h->winlen;
+    a.acc = h->acc;
+    return a;
+}
+
+template <typename T>
+void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base,
+                   int64_t t_off, hipStream_t s) {
+    StepArgs<T> a = make_args<T>(h, src, dst);
+    a.t_base = t_base;
+    a.t_off = t_off;
+    dim3 block(h->bx, h->by, 1);
+    dim3 grid((unsigned)((h->cfg.nx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
+              (unsigned)h->cfg.nz);
+    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM>), grid, block, 0, s, a);
+    else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step3d<T>), grid, block, 0, s, a);
+}
+
+void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s) {
+    const void *src = h->buf[parity];
+    void *dst = h->buf[parity ^ 1];
+    if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s);
+    else launch_step_t<double>(h, src, dst, t_base, t_off, s);
+}
+
+void drop_graphs(lbm_em *h) {
+    for (auto &g : h->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Capture kGraphChunk steps (starting from buffer parity p) plus the device
+// step-counter advance into one executable graph.
+hipGraphExec_t build_graph(lbm_em *h, int p) {
+    hipStream_t cs = nullptr;
+    hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        hip_check(e, "hipStreamBeginCapture");
+    }
+    int par = p;
+    for (int k = 0; k < kGraphChunk; ++k) {
+        launch_step(h, par, h->t_dev, k, cs);
+        par ^= 1;
+    }
+    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, cs, h->t_dev, (int64_t)kGraphChunk);
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    hip_check(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(e, "hipGraphInstantiate");
+    return ge;
+}
+
+void do_steps(lbm_em *h, int64_t n) {
+    select_device(h);
+    int64_t chunks = n / kGraphChunk;
+    if (chunks > 0) {
+        if (!h->graph[h->cur]) h->graph[h->cur] = build_graph(h, h->cur);
+        hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, h->stream, h->t_dev, h->t);
+        hip_check(hipGetLastError(), "k_set_time");
+        for (int64_t c = 0; c < chunks; ++c) {
+            hip_check(hipGraphLaunch(h->graph[h->cur], h->stream), "hipGraphLaunch");
+            // kGraphChunk is even: the buffer parity is unchanged
+        }
+        h->t += chunks * kGraphChunk;
+    }
+    for (int64_t k = 0; k < n - chunks * kGraphChunk; ++k) {
+        launch_step(h, h->cur, nullptr, h->t, h->stream);
+        hip_check(hipGetLastError(), "step kernel launch");
+        h->cur ^= 1;
+        h->t += 1;
+    }
+}
+
+void free_handle(lbm_em *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->dev);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    drop_graphs(h);
+    hfree(h->buf[0]);
+    hfree(h->buf[1]);
+    hfree(h->eps);
+    hfree(h->acc);
+    hfree(h->t_dev);
+    delete h;
+}
+
+void check_unit(const double v[3], const char *name) {
+    double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!std::isfinite(n) || std::fabs(n - 1.0) > 1e-9)
+        fail(LBM_EM_EINVAL, std::string(name) + " must be a unit vector");
+}
+
+void sync(const lbm_em *h) { hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize"); }
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_em_last_error(void) { return g_last_error.c_str(); }
+
+lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
+    return guarded([&] {
+        if (!cfg || !out) fail(LBM_EM_EINVAL, "null config or output pointer");
+        const lbm_em_config &c = *cfg;
+        if (c.nx < 3 || c.ny < 3 || c.nz < 1) fail(LBM_EM_EINVAL, "grid must be at least 3 x 3 x 1");
+        if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 31)
+            fail(LBM_EM_EINVAL, "more than 2^31 cells");
+        if (c.pol != LBM_EM_TM && c.pol != LBM_EM_TE && c.pol != LBM_EM_3D)
+            fail(LBM_EM_EINVAL, "pol must be LBM_EM_TM, LBM_EM_TE or LBM_EM_3D");
+        if (c.pol != LBM_EM_3D && c.nz != 1) fail(LBM_EM_EINVAL, "TM/TE runs need nz == 1");
+        if (c.pol == LBM_EM_3D && c.nz < 3) fail(LBM_EM_EINVAL, "3-D runs need nz >= 3");
+        if (c.precision != LBM_EM_FP32 && c.precision != LBM_EM_FP64)
+            fail(LBM_EM_EINVAL, "precision must be LBM_EM_FP32 or LBM_EM_FP64");
+        const int n[3] = {c.nx, c.ny, c.nz};
+        for (int a = 0; a < 3; ++a) {
+            if (c.absorb[a] < 0 || 2 * c.absorb[a] > n[a])
+                fail(LBM_EM_EINVAL, "absorbing width must satisfy 0 <= 2W <= n");
+            if (c.pol != LBM_EM_3D && a == 2 && c.absorb[a] != 0)
+                fail(LBM_EM_EINVAL, "2-D runs are periodic in z (absorb[2] = 0)");
+        }
+        if (!(c.sigma_max >= 0.0 && c.sigma_max <= 1.0)) fail(LBM_EM_EINVAL, "sigma_max must be in [0, 1]");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(LBM_EM_EDEVICE, "no HIP device");
+
+        lbm_em *h = new lbm_em();
+        try {
+            h->cfg = c;
+            hip_check(hipGetDevice(&h->dev), "hipGetDevice");
+            h->dim = c.pol == LBM_EM_3D ? 3 : 2;
+            h->nplanes = c.pol == LBM_EM_3D ? 27 : 11;
+            h->elem = c.precision == LBM_EM_FP32 ? 4 : 8;
+            h->sy = round_up(c.nx, 64);
+            h->sz = h->sy * c.ny;
+            h->plane = h->sz * c.nz;
+            h->stream = (hipStream_t)c.stream;
+            const size_t bytes = (size_t)h->plane * h->nplanes * h->elem;
+            hip_check(hipMalloc(&h->buf[0], bytes), "hipMalloc state");
+            hip_check(hipMalloc(&h->buf[1], bytes), "hipMalloc state");
+            hip_check(hipMalloc(&h->eps, (size_t)h->plane * h->elem), "hipMalloc eps");
+            hip_check(hipMalloc(&h->t_dev, 64), "hipMalloc counter");
+            hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset");
+            hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset");
+            // eps_r = 1 everywhere (padding included)
+            const int64_t ne = h->plane;
+            const unsigned blocks = (unsigned)((ne + 255) / 256);
+            if (h->elem == 4) hipLaunchKernelGGL((k_fill<float>), dim3(blocks), dim3(256), 0, h->stream, (float *)h->eps, ne, 1.0f);
+            else hipLaunchKernelGGL((k_fill<double>), dim3(blocks), dim3(256), 0, h->stream, (double *)h->eps, ne, 1.0);
+            hip_check(hipGetLastError(), "eps init");
+            hip_check(hipStreamSynchronize(h->stream), "sync");
+        } catch (...) {
+            free_handle(h);
+            throw;
+        }
+        *out = h;
+    });
+}
+
+lbm_em_status lbm_em_destroy(lbm_em_handle h) {
+    return guarded([&] {
+        check_handle(h);
+        free_handle(h);
+    });
+}
+
+lbm_em_status lbm_em_set_permittivity(lbm_em_handle hh, const void *eps, int32_t where, int32_t dtype) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!eps) fail(LBM_EM_EINVAL, "null eps");
+        if (dtype != LBM_EM_FP32 && dtype != LBM_EM_FP64) fail(LBM_EM_EINVAL, "dtype must be FP32 or FP64");
+        if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
+        select_device(h);
+        const auto &c = h->cfg;
+        const size_t cells = (size_t)c.nx * c.ny * c.nz;
+        const size_t isz = dtype == LBM_EM_FP32 ? 4 : 8;
+        // validate on a host copy
+        std::vector<char> host(cells * isz);
+        if (where == LBM_EM_HOST) std::memcpy(host.data(), eps, host.size());
+        else {
+            hip_check(hipMemcpyAsync(host.data(), eps, host.size(), hipMemcpyDeviceToHost, h->stream), "eps D2H");
+            sync(h);
+        }
+        for (size_t i = 0; i < cells; ++i) {
+            double v = dtype == LBM_EM_FP32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
+            if (!std::isfinite(v) || v < 1.0) fail(LBM_EM_EINVAL, "eps_r must be finite and >= 1");
+        }
+        void *d_in = nullptr;
+        hip_check(hipMalloc(&d_in, host.size()), "hipMalloc");
+        hip_check(hipMemcpyAsync(d_in, host.data(), host.size(), hipMemcpyHostToDevice, h->stream), "eps H2D");
+        dim3 grid((c.nx + 255) / 256, c.ny, c.nz);
+        if (dtype == LBM_EM_FP32 && h->elem == 4)
+            hipLaunchKernelGGL((k_load_eps<float, float>), grid, dim3(256), 0, h->stream, (const float *)d_in,
+                               (float *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
+        else if (dtype == LBM_EM_FP32)
+            hipLaunchKernelGGL((k_load_eps<float, double>), grid, dim3(256), 0, h->stream, (const float *)d_in,
+                               (double *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
+        else if (h->elem == 4)
+            hipLaunchKernelGGL((k_load_eps<double, float>), grid, dim3(256), 0, h->stream, (const double *)d_in,
+                               (float *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
+        else
+            hipLaunchKernelGGL((k_load_eps<double, double>), grid, dim3(256), 0, h->stream, (const double *)d_in,
+                               (double *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
+        hip_check(hipGetLastError(), "k_load_eps");
+        sync(h);
+        hfree(d_in);
+    });
+}
+
+lbm_em_status lbm_em_set_source(lbm_em_handle hh, const lbm_em_plane_wave *pw) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!pw) fail(LBM_EM_EINVAL, "null plane wave");
+        check_unit(pw->khat, "khat");
+        check_unit(pw->ehat, "ehat");
+        double kd = pw->khat[0] * pw->ehat[0] + pw->khat[1] * pw->ehat[1] + pw->khat[2] * pw->ehat[2];
+        if (std::fabs(kd) > 1e-9) fail(LBM_EM_EINVAL, "ehat must be perpendicular to khat");
+        if (!(pw->lambda > 2.0) || !std::isfinite(pw->lambda)) fail(LBM_EM_EINVAL, "lambda must be > 2 cells");
+        double T = 3.0 * pw->lambda;
+        if (std::fabs(T - std::round(T)) > 1e-9) fail(LBM_EM_EINVAL, "3*lambda must be an integer");
+        if (!(pw->ramp_periods >= 0.0) || !std::isfinite(pw->amplitude)) fail(LBM_EM_EINVAL, "bad ramp / amplitude");
+        if (h->cfg.pol != LBM_EM_3D) {
+            if (std::fabs(pw->khat[2]) > 1e-12) fail(LBM_EM_EINVAL, "2-D runs need khat in the xy plane");
+            if (h->cfg.pol == LBM_EM_TM && std::fabs(std::fabs(pw->ehat[2]) - 1.0) > 1e-12)
+                fail(LBM_EM_EINVAL, "TM needs ehat = +-z");
+            if (h->cfg.pol == LBM_EM_TE && std::fabs(pw->ehat[2]) > 1e-12)
+                fail(LBM_EM_EINVAL, "TE needs ehat in the xy plane");
+        }
+        h->pw = *pw;
+        const double *k = pw->khat, *e = pw->ehat;
+        h->hhat[0] = k[1] * e[2] - k[2] * e[1];
+        h->hhat[1] = k[2] * e[0] - k[0] * e[2];
+        h->hhat[2] = k[0] * e[1] - k[1] * e[0];
+        h->period = (int)std::lround(T);
+        h->src_on = true;
+        drop_graphs(h);
+    });
+}
+
+lbm_em_status lbm_em_set_ntff(lbm_em_handle hh, const int32_t lo[3], const int32_t hi[3],
+                              int64_t window_start, int64_t window_len) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!lo || !hi) fail(LBM_EM_EINVAL, "null box");
+        if (!h->src_on) fail(LBM_EM_ESTATE, "set the source before the contour (the DFT frequency is the source's)");
+        const int n[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz};
+        for (int a = 0; a < h->dim; ++a)
+            if (lo[a] < 1 || hi[a] > n[a] - 2 || hi[a] - lo[a] < 2)
+                fail(LBM_EM_EINVAL, "contour box must lie strictly inside the grid and span >= 3 nodes");
+        if (h->dim == 2 && (lo[2] != 0 || hi[2] != 0)) fail(LBM_EM_EINVAL, "2-D box needs lo[2] = hi[2] = 0");
+        if (window_start < 0 || window_len < 1) fail(LBM_EM_EINVAL, "empty DFT window");
+        select_device(h);
+        for (int a = 0; a < 3; ++a) {
+            h->box.lo[a] = lo[a];
+            h->box.hi[a] = hi[a];
+            h->probe[a] = (lo[a] + hi[a]) / 2;
+        }
+        h->nnodes = box_nodes(h->box, h->dim);
+        h->win0 = window_start;
+        h->winlen = window_len;
+        hfree(h->acc);
+        h->acc = nullptr;
+        const size_t bytes = (size_t)(h->nnodes + 1) * 12 * sizeof(double);
+        hip_check(hipMalloc(&h->acc, bytes), "hipMalloc dft");
+        hip_check(hipMemsetAsync(h->acc, 0, bytes, h->stream), "hipMemset dft");
+        h->dft_set = true;
+        drop_graphs(h);
+    });
+}
+
+lbm_em_status lbm_em_step(lbm_em_handle hh, int64_t n) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (n < 0) fail(LBM_EM_EINVAL, "n must be >= 0");
+        do_steps(h, n);
+    });
+}
+
+lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n) {
+    return guarded([&] {
+        if (!hs || count < 1) fail(LBM_EM_EINVAL, "need at least one handle");
+        if (n < 0) fail(LBM_EM_EINVAL, "n must be >= 0");
+        for (int i = 0; i < count; ++i) check_handle(hs[i]);
+        fail(LBM_EM_EUNSUPPORTED, "step_many is not built yet");
+    });
+}
+
+lbm_em_status lbm_em_time(lbm_em_handle hh, int64_t *t) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!t) fail(LBM_EM_EINVAL, "null output");
+        *t = h->t;
+    });
+}
+
+lbm_em_status lbm_em_get_fields(lbm_em_handle hh, void *E, void *H, int32_t where) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!E || !H) fail(LBM_EM_EINVAL, "null output");
+        if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
+        select_device(h);
+        const auto &c = h->cfg;
+        const size_t bytes = (size_t)c.nx * c.ny * c.nz * 3 * h->elem;
+        void *dE = E, *dH = H;
+        if (where == LBM_EM_HOST) {
+            hip_check(hipMalloc(&dE, bytes), "hipMalloc");
+            hip_check(hipMalloc(&dH, bytes), "hipMalloc");
+        }
+        dim3 block(h->bx, h->by, 1);
+        dim3 grid((c.nx + h->bx - 1) / h->bx, (c.ny + h->by - 1) / h->by, c.nz);
+        if (h->elem == 4) {
+            auto a = make_args<float>(h, h->buf[h->cur], nullptr);
+            if (c.pol == LBM_EM_TM) hipLaunchKernelGGL((k_fields<float, TM>), grid, block, 0, h->stream, a, (float *)dE, (float *)dH);
+            else if (c.pol == LBM_EM_TE) hipLaunchKernelGGL((k_fields<float, TE>), grid, block, 0, h->stream, a, (float *)dE, (float *)dH);
+            else hipLaunchKernelGGL((k_fields<float, D3>), grid, block, 0, h->stream, a, (float *)dE, (float *)dH);
+        } else {
+            auto a = make_args<double>(h, h->buf[h->cur], nullptr);
+            if (c.pol == LBM_EM_TM) hipLaunchKernelGGL((k_fields<double, TM>), grid, block, 0, h->stream, a, (double *)dE, (double *)dH);
+            else if (c.pol == LBM_EM_TE) hipLaunchKernelGGL((k_fields<double, TE>), grid, block, 0, h->stream, a, (double *)dE, (double *)dH);
+            else hipLaunchKernelGGL((k_fields<double, D3>), grid, block, 0, h->stream, a, (double *)dE, (double *)dH);
+        }
+        hip_check(hipGetLastError(), "k_fields");
+        if (where == LBM_EM_HOST) {
+            hip_check(hipMemcpyAsync(E, dE, bytes, hipMemcpyDeviceToHost, h->stream), "D2H");
+            hip_check(hipMemcpyAsync(H, dH, bytes, hipMemcpyDeviceToHost, h->stream), "D2H");
+            sync(h);
+            hfree(dE);
+            hfree(dH);
+        }
+    });
+}
+
+lbm_em_status lbm_em_get_phasors(lbm_em_handle hh, double *out, int32_t *n_nodes) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!n_nodes) fail(LBM_EM_EINVAL, "null n_nodes");
+        if (!h->dft_set) fail(LBM_EM_ESTATE, "no contour set");
+        *n_nodes = (int32_t)h->nnodes;
+        if (!out) return;
+        select_device(h);
+        std::vector<double> raw((size_t)(h->nnodes + 1) * 12);
+        hip_check(hipMemcpyAsync(raw.data(), h->acc, raw.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->stream), "D2H");
+        sync(h);
+        // surface nodes in ascending linear index (z, y, x)
+        const Box &b = h->box;
+        int64_t k = 0;
+        for (int z = b.lo[2]; z <= b.hi[2]; ++z)
+            for (int y = b.lo[1]; y <= b.hi[1]; ++y)
+                for (int x = b.lo[0]; x <= b.hi[0]; ++x) {
+                    if (!on_box(b, h->dim, x, y, z)) continue;
+                    int64_t node = box_node_index(b, h->dim, x, y, z);
+                    std::memcpy(out + k * 12, raw.data() + node * 12, 12 * sizeof(double));
+                    ++k;
+                }
+        std::memcpy(out + k * 12, raw.data() + h->nnodes * 12, 12 * sizeof(double));
+    });
+}
+
+lbm_em_status lbm_em_farfield(lbm_em_handle hh, lbm_em_handle inc, const double *theta_deg,
+                              const double *phi_deg, int32_t n_angles, double *out_S2) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!theta_deg || !out_S2 || n_angles < 1) fail(LBM_EM_EINVAL, "bad angle / output arrays");
+        if (h->dim == 3 && !phi_deg) fail(LBM_EM_EINVAL, "3-D needs phi");
+        if (!h->dft_set) fail(LBM_EM_ESTATE, "no contour set");
+        if (h->t < h->win0 + h->winlen) fail(LBM_EM_ESTATE, "DFT window not completed");
+        if (inc) {
+            if (inc->cfg.nx != h->cfg.nx || inc->cfg.ny != h->cfg.ny || inc->cfg.nz != h->cfg.nz ||
+                inc->cfg.pol != h->cfg.pol || !inc->dft_set)
+                fail(LBM_EM_EINVAL, "incident handle must match grid, polarisation and contour");
+            for (int a = 0; a < 3; ++a)
+                if (inc->box.lo[a] != h->box.lo[a] || inc->box.hi[a] != h->box.hi[a])
+                    fail(LBM_EM_EINVAL, "incident handle has a different contour");
+            if (inc->t < inc->win0 + inc->winlen) fail(LBM_EM_ESTATE, "incident DFT window not completed");
+        }
+        select_device(h);
+        if (inc) sync(inc);
+        std::vector<double> ang(2 * (size_t)n_angles);
+        for (int i = 0; i < n_angles; ++i) {
+            ang[i] = theta_deg[i] * M_PI / 180.0;
+            ang[n_angles + i] = phi_deg ? phi_deg[i] * M_PI / 180.0 : 0.0;
+        }
+        double *d_ang = nullptr, *d_out = nullptr;
+        hip_check(hipMalloc(&d_ang, ang.size() * sizeof(double)), "hipMalloc");
+        hip_check(hipMalloc(&d_out, (size_t)n_angles * 4 * sizeof(double)), "hipMalloc");
+        hip_check(hipMemcpyAsync(d_ang, ang.data(), ang.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 h->stream), "H2D");
+        NtffArgs a{};
+        a.acc = h->acc;
+        a.acc_inc = inc ? inc->acc : nullptr;
+        a.box = h->box;
+        a.dim = h->dim;
+        a.pol = h->cfg.pol;
+        a.k = 2.0 * M_PI / h->pw.lambda;
+        const auto &c = h->cfg;
+        a.center[0] = (c.nx - 1) / 2.0;
+        a.center[1] = (c.ny - 1) / 2.0;
+        a.center[2] = h->dim == 3 ? (c.nz - 1) / 2.0 : 0.0;
+        for (int k = 0; k < 3; ++k) {
+            a.khat[k] = h->pw.khat[k];
+            a.ehat[k] = h->pw.ehat[k];
+            a.bhat[k] = h->hhat[k];
+        }
+        a.theta = d_ang;
+        a.phi = d_ang + n_angles;
+        a.out = d_out;
+        hipLaunchKernelGGL(k_ntff, dim3(n_angles), dim3(256), 0, h->stream, a);
+        hip_check(hipGetLastError(), "k_ntff");
+        std::vector<double> P((size_t)n_angles * 4);
+        hip_check(hipMemcpyAsync(P.data(), d_out, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                  "D2H");
+        // incident amplitude from the probe node
+        double amp = h->pw.amplitude;
+        if (inc) {
+            double pr[12];
+            hip_check(hipMemcpyAsync(pr, inc->acc + inc->nnodes * 12, sizeof pr, hipMemcpyDeviceToHost,
+                                     h->stream), "D2H");
+            sync(h);
+            const double *v = h->cfg.pol == LBM_EM_TE ? pr + 6 : pr;
+            const double *u = h->cfg.pol == LBM_EM_TE ? h->hhat : h->pw.ehat;
+            double re = 0, im = 0;
+            for (int k = 0; k < 3; ++k) {
+                re += u[k] * v[2 * k];
+                im += u[k] * v[2 * k + 1];
+            }
+            amp = std::sqrt(re * re + im * im);
+        }
+        sync(h);
+        hfree(d_ang);
+        hfree(d_out);
+        const double k = a.k;
+        const double kappa = h->dim == 2 ? k * k / (8.0 * M_PI) : k * k * k * k / (16.0 * M_PI * M_PI);
+        for (int i = 0; i < n_angles; ++i) {
+            double p = P[4 * i] * P[4 * i] + P[4 * i + 1] * P[4 * i + 1] + P[4 * i + 2] * P[4 * i + 2] +
+                       P[4 * i + 3] * P[4 * i + 3];
+            out_S2[i] = kappa * p / (amp * amp);
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+"""Thin Python face of the C ABI: one Simulation object per lbm_em handle.
+
+PyTorch is only used for device memory and the stream handed to the
+library (torch.cuda.current_stream() when a device is present); all lattice
+Boltzmann arithmetic runs in liblbm_em.so.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+_POL = {"TM": L.TM, "TE": L.TE, "3D": L.D3}
+_PREC = {"fp32": L.FP32, "fp64": L.FP64}
+
+
+def _current_stream():
+    try:
+        import torch
+    except ImportError:  # pragma: no cover - torch is part of the image
+        return None
+    if torch.cuda.is_available():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return None
+
+
+class Simulation:
+    """One scattering instance on the GPU (see include/lbm_em.h)."""
+
+    def __init__(self, nx, ny, nz=1, pol="TM", precision="fp32", absorb=(0, 0, 0), sigma_max=0.25,
+                 stream=None):
+        self.n = (int(nx), int(ny), int(nz))
+        self.pol = pol
+        self.precision = precision
+        self.dtype = np.float32 if precision == "fp32" else np.float64
+        cfg = L.Config()
+        cfg.nx, cfg.ny, cfg.nz = self.n
+        cfg.pol = _POL[pol]
+        cfg.precision = _PREC[precision]
+        for a in range(3):
+            cfg.absorb[a] = int(absorb[a])
+        cfg.sigma_max = float(sigma_max)
+        cfg.stream = stream if stream is not None else _current_stream()
+        h = C.c_void_p()
+        L.check(L.lib().lbm_em_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._theta_inc = 0.0
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.check(L.lib().lbm_em_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- inputs ----------------------------------------------------------
+    def set_permittivity(self, eps):
+        """eps: numpy array or torch tensor with nx*ny*nz values ([z][y][x])."""
+        size = self.n[0] * self.n[1] * self.n[2]
+        if hasattr(eps, "data_ptr"):  # torch tensor
+            t = eps.contiguous()
+            if t.numel() != size:
+                raise ValueError("eps has the wrong number of values")
+            dt = {4: L.FP32, 8: L.FP64}[t.element_size()]
+            where = L.DEVICE if t.is_cuda else L.HOST
+            L.check(L.lib().lbm_em_set_permittivity(self._h, C.c_void_p(t.data_ptr()), where, dt))
+            return
+        a = np.ascontiguousarray(eps, dtype=np.float64)
+        if a.size != size:
+            raise ValueError("eps has the wrong number of values")
+        L.check(L.lib().lbm_em_set_permittivity(self._h, a.ctypes.data_as(C.c_void_p), L.HOST, L.FP64))
+
+    def set_source(self, lam, khat, ehat, amplitude=1.0, ramp_periods=3.0, center=None):
+        pw = L.PlaneWave()
+        pw.lam = float(lam)
+        for a in range(3):
+            pw.khat[a] = float(khat[a])
+            pw.ehat[a] = float(ehat[a])
+        pw.amplitude = float(amplitude)
+        pw.ramp_periods = float(ramp_periods)
+        c = center if center is not None else [(m - 1) / 2.0 for m in self.n]
+        if self.n[2] == 1 and center is None:
+            c = [c[0], c[1], 0.0]
+        for a in range(3):
+            pw.center[a] = float(c[a])
+        L.check(L.lib().lbm_em_set_source(self._h, C.byref(pw)))
+        self._khat = np.asarray(khat, float)
+        self.lam = float(lam)
+
+    def set_ntff(self, lo, hi, window_start, window_len):
+        lo3 = (C.c_int32 * 3)(*(list(lo) + [0] * (3 - len(lo))))
+        hi3 = (C.c_int32 * 3)(*(list(hi) + [0] * (3 - len(hi))))
+        L.check(L.lib().lbm_em_set_ntff(self._h, lo3, hi3, int(window_start), int(window_len)))
+        self.box = (tuple(lo), tuple(hi))
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n=1):
+        L.check(L.lib().lbm_em_step(self._h, int(n)))
+
+    @property
+    def t(self):
+        v = C.c_int64()
+        L.check(L.lib().lbm_em_time(self._h, C.byref(v)))
+        return v.value
+
+    # -- outputs -----------------------------------------------------------
+    def fields(self):
+        """(E, H) at the current time as numpy arrays (nz, ny, nx, 3)."""
+        shape = (self.n[2], self.n[1], self.n[0], 3)
+        E = np.empty(shape, self.dtype)
+        H = np.empty(shape, self.dtype)
+        L.check(L.lib().lbm_em_get_fields(self._h, E.ctypes.data_as(C.c_void_p),
+                                          H.ctypes.data_as(C.c_void_p), L.HOST))
+        return E, H
+
+    def fields_device(self):
+        """(E, H) as torch CUDA tensors (nz, ny, nx, 3)."""
+        import torch
+
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        shape = (self.n[2], self.n[1], self.n[0], 3)
+        E = torch.empty(shape, dtype=dt, device="cuda")
+        H = torch.empty(shape, dtype=dt, device="cuda")
+        L.check(L.lib().lbm_em_get_fields(self._h, C.c_void_p(E.data_ptr()), C.c_void_p(H.data_ptr()),
+                                          L.DEVICE))
+        return E, H
+
+    def phasors(self):
+        """Contour phasors: (X (p, 6) complex for the surface nodes in
+        ascending linear index, probe (6,) complex)."""
+        n = C.c_int32()
+        L.check(L.lib().lbm_em_get_phasors(self._h, None, C.byref(n)))
+        out = np.zeros((n.value + 1) * 12)
+        L.check(L.lib().lbm_em_get_phasors(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+        out = out.reshape(-1, 12)
+        X = out[:, 0::2] + 1j * out[:, 1::2]
+        return X[:-1], X[-1]
+
+    def farfield(self, theta_deg, phi_deg=None, incident=None):
+        """|S|^2 at angles measured from the incidence direction (2-D: in
+        the plane; 3-D: phi about khat from ehat)."""
+        th = np.ascontiguousarray(theta_deg, dtype=np.float64).ravel()
+        ph = None if phi_deg is None else np.ascontiguousarray(
+            np.broadcast_to(phi_deg, th.shape), dtype=np.float64)
+        out = np.empty(th.size)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        L.check(L.lib().lbm_em_farfield(self._h, incident.handle if incident is not None else None,
+                                        dp(th), dp(ph) if ph is not None else None, th.size, dp(out)))
+        return out
+
+
+def step_many(sims, n):
+    """Advance several Simulations together (one launch per step)."""
+    arr = (C.c_void_p * len(sims))(*[s.handle.value for s in sims])
+    L.check(L.lib().lbm_em_step_many(arr, len(sims), int(n)))

@@ -1,0 +1,221 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars: FP64 library build vs oracle <= 1e-12 (relative to the field scale);
+FP32 library vs oracle <= 1e-4 relative L2 on field snapshots and <= 1e-3
+normalised on |S|^2 (angular intensity).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ntff, run
+from oracle.core import Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_11042_amd import Simulation
+
+    return Simulation
+
+
+def rel_l2(a, b):
+    return float(np.sqrt(np.sum((np.asarray(a, float) - b) ** 2) / np.sum(b ** 2)))
+
+
+def make_pair(Sim, nx, ny, nz, pol, prec, absorb, eps, lam, khat, ehat, ramp=3.0):
+    s = Sim(nx, ny, nz, pol=pol, precision=prec, absorb=absorb, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(eps)
+    s.set_source(lam, khat, ehat, 1.0, ramp)
+    o = Oracle(nx, ny, nz, absorb, W.SIGMA_MAX)
+    o.set_eps(eps)
+    center = [(m - 1) / 2.0 for m in (nx, ny, nz)]
+    if nz == 1:
+        center[2] = 0.0
+    o.set_source(lam, khat, ehat, 1.0, ramp, center)
+    return s, o
+
+
+def compare_fields(s, o, prec, tag):
+    Eg, Hg = s.fields()
+    Eo, Ho = o.fields()
+    scale = max(np.abs(Eo).max(), np.abs(Ho).max())
+    if scale == 0.0:   # source ramp still at zero: both must be exactly zero
+        assert not np.any(Eg) and not np.any(Hg), tag
+        return
+    assert scale > 1e-3 or o.t < 20, "the wave has not entered the domain"
+    if prec == "fp64":
+        err = max(np.abs(Eg - Eo).max(), np.abs(Hg - Ho).max()) / scale
+        say(tag, "fp64 max rel err", err)
+        assert err <= 1e-12, (tag, err)
+    else:
+        err = rel_l2(np.concatenate([Eg.ravel(), Hg.ravel()]), np.concatenate([Eo.ravel(), Ho.ravel()]))
+        say(tag, "fp32 rel L2", err)
+        assert err <= 1e-4, (tag, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("theta,pol", [(0.0, "TM"), (30.0, "TM"), (0.0, "TE"), (30.0, "TE")])
+def test_fresnel_config_fields(gpu, prec, theta, pol):
+    """Planar interface, 256 x 128, eps 2.25 half space, W = 20, lambda = 32,
+    3000 steps (the small configuration at full size)."""
+    case = W.fresnel_case(theta, pol, ny=128)
+    say("fresnel", prec, theta, pol)
+    kh, eh = W.plane_wave_2d(theta, pol)
+    s, o = make_pair(gpu, case.nx, case.ny, 1, pol, prec, case.absorb, case.eps, case.lam, kh, eh)
+    s.step(case.steps)
+    o.step(case.steps)
+    assert s.t == o.t == case.steps
+    compare_fields(s, o, prec, f"fresnel {pol} {theta}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_grid_mixed_boundaries(gpu, prec):
+    """Sizes that leave ragged tiles (67 x 45), x periodic / y absorbing,
+    random dielectric blobs, oblique TE source."""
+    nx, ny = 67, 45
+    rng = np.random.default_rng(11)
+    eps = 1.0 + (rng.random((1, ny, nx)) < 0.15) * rng.uniform(0.5, 3.0, (1, ny, nx))
+    eps[:, :10, :] = 1.0
+    eps[:, -10:, :] = 1.0
+    th = np.deg2rad(70.0)
+    kh = [np.cos(th), np.sin(th), 0.0]
+    eh = [-np.sin(th), np.cos(th), 0.0]
+    say("ragged", prec)
+    s, o = make_pair(gpu, nx, ny, 1, "TE", prec, (0, 9, 0), eps, 10.0, kh, eh, ramp=1.0)
+    for n in (1, 7, 130):     # mixes eager steps and graph chunks
+        s.step(n)
+        o.step(n)
+        compare_fields(s, o, prec, f"ragged t={o.t}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_three_d_sphere_fields(gpu, prec):
+    n = 40
+    case = W.sphere_case(n=n, x_size=3.0, lam=10.0, eps_in=2.25, W=8, steps=260, half=9.5)
+    say("3d", prec)
+    s, o = make_pair(gpu, n, n, n, "3D", prec, (8, 8, 8), case.eps, case.lam, [0, 0, 1.0], [1.0, 0, 0],
+                     ramp=1.0)
+    s.step(case.steps)
+    o.step(case.steps)
+    compare_fields(s, o, prec, "3d sphere")
+
+
+def test_graph_replay_equals_eager(gpu):
+    """step(n) replays captured graphs in 64-step chunks; results must be
+    bit-identical to single eager steps."""
+    case = W.cylinder_case(2.25, "TM", n=128, a=10.0, lam=16.0, W=16, steps=200, half=14.5)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    sims = []
+    for _ in range(2):
+        s = gpu(128, 128, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(case.eps)
+        s.set_source(case.lam, kh, eh)
+        sims.append(s)
+    say("graph vs eager")
+    sims[0].step(200)
+    for _ in range(200):
+        sims[1].step(1)
+    E0, H0 = sims[0].fields()
+    E1, H1 = sims[1].fields()
+    assert np.array_equal(E0, E1) and np.array_equal(H0, H1)
+
+
+def _gpu_case(Sim, case, prec):
+    kh, eh = W.plane_wave_2d(case.theta_deg, case.pol)
+    s = Sim(case.nx, case.ny, 1, pol=case.pol, precision=prec, absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    w0, wl = case.window
+    s.set_ntff(case.box_lo, case.box_hi, w0, wl)
+    s.step(case.steps)
+    return s
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_cylinder_pipeline_phasors_and_intensity(gpu, pol):
+    """Whole path on a small cylinder (192^2, a = 10.5, lambda = 32, 2400
+    steps): contour DFT phasors and |S(theta)|^2 at 0.5 degree resolution
+    against the oracle's DFT + NTFF."""
+    case = W.cylinder_case(2.25, pol, n=192, a=10.5, lam=32.0, W=32, steps=2400, half=19.5)
+    inc_case = W.vacuum_companion(case)
+    say("pipeline", pol)
+    tot_o = run.run_2d(case, W.SIGMA_MAX, W.RAMP_PERIODS)
+    inc_o = run.run_2d(inc_case, W.SIGMA_MAX, W.RAMP_PERIODS)
+    th = np.arange(0, 360, 0.5)
+    S_o = run.intensity_2d(case, tot_o, inc_o, th)
+    for prec, ptol, stol in (("fp64", 1e-11, 1e-10), ("fp32", 1e-4, 1e-3)):
+        tot_g = _gpu_case(gpu, case, prec)
+        inc_g = _gpu_case(gpu, inc_case, prec)
+        X, probe = tot_g.phasors()
+        scale = np.abs(tot_o["phasors"]).max()
+        perr = np.abs(X - tot_o["phasors"]).max() / scale
+        say(pol, prec, "phasor err", perr)
+        assert perr <= ptol
+        assert np.abs(probe - tot_o["probe"]).max() <= ptol * scale
+        S_g = tot_g.farfield(th, incident=inc_g)
+        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
+        say(pol, prec, "|S|^2 normalised rms err", serr)
+        assert serr <= stol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_three_d_pipeline_intensity(gpu, prec):
+    """3-D DFT + NTFF on a small sphere (48^3) against the oracle, in the
+    two scattering planes phi = 0, 90 degrees and phi = 45."""
+    n = 48
+    case = W.sphere_case(n=n, x_size=2.5, lam=12.0, eps_in=2.25, W=8, steps=360, half=8.5)
+    vac = W.sphere_case(n=n, x_size=2.5, lam=12.0, eps_in=1.0, W=8, steps=360, half=8.5)
+    say("3d pipeline", prec)
+    tot_o = run.run_3d(case, W.SIGMA_MAX, 1.0)
+    inc_o = run.run_3d(vac, W.SIGMA_MAX, 1.0)
+    th = np.arange(0, 180.01, 0.5)
+    sims = []
+    for c in (case, vac):
+        s = gpu(n, n, n, pol="3D", precision=prec, absorb=(8, 8, 8), sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(c.eps)
+        s.set_source(c.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+        s.set_ntff(c.box_lo, c.box_hi, *c.window)
+        s.step(c.steps)
+        sims.append(s)
+    for phi in (0.0, 45.0, 90.0):
+        S_o = run.intensity_3d(case, tot_o, inc_o, th, np.full_like(th, phi))
+        S_g = sims[0].farfield(th, np.full_like(th, phi), incident=sims[1])
+        err = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
+        say("3d phi", phi, prec, err)
+        assert err <= (1e-10 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_full_size_cylinder_grid_short_run(gpu, pol):
+    """The 1024^2 cylinder configuration in the launch configuration the
+    benchmark times, for 300 steps (the oracle's full-length run takes
+    minutes): every tile, the layers and the source against the oracle."""
+    case = W.cylinder_case(2.25, pol, n=1024, steps=300)
+    kh, eh = W.plane_wave_2d(0.0, pol)
+    say("full size short", pol)
+    o = Oracle(1024, 1024, 1, case.absorb, W.SIGMA_MAX)
+    o.set_eps(case.eps)
+    o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS, [511.5, 511.5, 0.0])
+    o.step(case.steps)
+    for prec in ("fp32", "fp64"):
+        s = gpu(1024, 1024, 1, pol=pol, precision=prec, absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(case.eps)
+        s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        s.step(case.steps)
+        compare_fields(s, o, prec, f"1024^2 {pol}")
+        s.close()
