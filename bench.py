@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the electromagnetic lattice Boltzmann hot path on one MI355X.
+
+One benchmark step = the whole 2-D circular-cylinder workload: grid 1024 x
+1024, radius 25.5 cells (x = 5), lambda = 32, 32-cell absorbing layer, 8000
+time steps with the last-period contour DFT, for eps_r in {1.5, 2.25, 4.0}
+and TM and TE incidence, plus the eps_r = 1 companion run of each
+polarisation, followed by the near-to-far-field transform at 0.5 degree
+resolution (720 angles) for the six scatterers.  FP32 state and arithmetic,
+FP64 DFT accumulators.  Inputs are resident in device memory before timing.
+
+Reported value: lattice updates per second over the whole step (MLUPS).
+Also reported: the fused step kernel's achieved algorithmic bandwidth
+(92 B per cell update) against the 8 TB/s HBM peak, an extra 3-D sphere
+measurement (384^3, 220 B per update), and the FP64 oracle timed on a
+bounded sample of the same workload on the host cores together with the
+GPU-vs-oracle field error on that sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline (fwd, adjoint, batched) at stated accuracy vs oracle"
+HBM_PEAK_GBS = 8000.0
+BYTES_2D = 11 * 4 * 2 + 4      # reduced 2-D state read + written, eps read (FP32)
+BYTES_3D = 27 * 4 * 2 + 4
+KERNEL_SOURCES = ["paper_2510_11042_amd/csrc/kernels.hpp", "paper_2510_11042_amd/csrc/lbm_em.hip"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(key):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(key)
+    if not rec or rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cylinder_workload(Simulation, W, lbm_steps):
+    sims = []
+    for pol in ("TM", "TE"):
+        for eps_in in (1.0, 1.5, 2.25, 4.0):
+            case = W.cylinder_case(eps_in, pol, n=1024, steps=lbm_steps)
+            if eps_in == 1.0:
+                case = W.vacuum_companion(case)
+            kh, eh = W.plane_wave_2d(0.0, pol)
+            s = Simulation(1024, 1024, 1, pol=pol, precision="fp32", absorb=case.absorb,
+                           sigma_max=W.SIGMA_MAX)
+            s.set_permittivity(case.eps)
+            s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+            s.set_ntff(case.box_lo, case.box_hi, *case.window)
+            sims.append((pol, eps_in, s))
+    return sims
+
+
+def run_workload(sims, lbm_steps, theta, torch, events):
+    """One benchmark step; appends (start, end) event pairs around stepping."""
+    out = {}
+    for pol, eps_in, s in sims:
+        s.reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(lbm_steps)
+        e1.record()
+        events.append((e0, e1, lbm_steps))
+    for pol in ("TM", "TE"):
+        inc = [s for p, e, s in sims if p == pol and e == 1.0][0]
+        for p, e, s in sims:
+            if p == pol and e != 1.0:
+                out[(pol, e)] = s.farfield(theta, incident=inc)
+    return out
+
+
+def sphere_extra(Simulation, W, torch, steps=200):
+    case = W.sphere_case(n=384, steps=steps, with_eps=True)
+    s = Simulation(384, 384, 384, pol="3D", precision="fp32", absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
+    s.step(64)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cells = 384 ** 3
+    res = {"workload": "sphere-384^3-eps2.25-x6-lambda24", "cells": cells, "launches": steps,
+           "ms_per_launch": ms, "MLUPS": cells / (ms * 1e-3) / 1e6,
+           "algorithmic_bytes_per_update": BYTES_3D,
+           "achieved_GBs": cells * BYTES_3D / (ms * 1e-3) / 1e9}
+    res["frac_of_hbm_peak"] = res["achieved_GBs"] / HBM_PEAK_GBS
+    s.close()
+    return res
+
+
+def cpu_baseline(Simulation, W, target_s=20.0):
+    """FP64 oracle on a bounded sample of the benchmark workload (the
+    eps_r = 2.25 TM cylinder at 1024^2, first N steps), timed on the host
+    cores; the GPU runs the same N steps and its fields are compared."""
+    import numpy as np
+
+    from oracle import core as oracle_core
+
+    case = W.cylinder_case(2.25, "TM", n=1024, steps=8000)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    o = oracle_core.Oracle(1024, 1024, 1, case.absorb, W.SIGMA_MAX)
+    o.set_eps(case.eps)
+    o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS, [511.5, 511.5, 0.0])
+    t0 = time.perf_counter()
+    o.step(10)
+    rate = 10 / (time.perf_counter() - t0)
+    n = int(max(20, min(2000, rate * target_s))) - 10
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    total = n + 10
+    s = Simulation(1024, 1024, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    s.step(total)
+    Eg, Hg = s.fields()
+    Eo, Ho = o.fields()
+    num = np.sum((Eg - Eo) ** 2) + np.sum((Hg - Ho) ** 2)
+    den = np.sum(Eo ** 2) + np.sum(Ho ** 2)
+    s.close()
+    return {"value": 1024 * 1024 * n / dt / 1e6, "unit": "MLUPS", "cores": oracle_core.threads(),
+            "kind": "oracle",
+            "sample": f"eps 2.25 TM cylinder 1024^2, steps {10}..{total} of 8000, FP64 literal 42-scalar "
+                      f"scheme, {dt:.1f} s",
+            "gpu_vs_oracle_rel_l2_fields": float(np.sqrt(num / den)), "sample_steps": total}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed benchmark steps")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lbm-steps", type=int, default=8000, help="time steps per solve (workload: 8000)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this implementation runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2510_11042_amd import Simulation
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes 2^30 bytes
+        a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30, "launches": 3}))
+        return 0
+    theta = np.arange(0.0, 360.0, 0.5)
+    sims = cylinder_workload(Simulation, W, args.lbm_steps)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        run_workload(sims, args.lbm_steps, theta, torch, [])
+    torch.cuda.synchronize()
+    events = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = run_workload(sims, args.lbm_steps, theta, torch, events)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    cells = 1024 * 1024
+    updates = len(sims) * cells * args.lbm_steps
+    value = updates / (ms_per_step * 1e-3) / 1e6
+
+    step_ms = sum(a.elapsed_time(b) for a, b, _ in events)
+    launches = sum(n for _, _, n in events)
+    ms_per_launch = step_ms / launches
+    alg_bytes = cells * BYTES_2D
+    achieved = alg_bytes / (ms_per_launch * 1e-3) / 1e9
+    traffic = recorded_traffic("k_step2d_fp32_1024")
+    line = {
+        "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cylinder-1024x1024-a25.5-lambda32-W32-8000steps-eps{1.5,2.25,4.0}x{TM,TE}"
+                               "+vacuum-companions+NTFF720", "instances": len(sims),
+                   "lbm_steps": args.lbm_steps, "cells_per_instance": cells},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step2d<float,TM/TE>", "ms_per_launch": ms_per_launch,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "note": "state 2 x 46 MB + eps 4 MB per instance fits the 256 MB Infinity Cache"},
+    }
+    # the computed intensities must be finite and positive
+    for k, S in res.items():
+        assert np.all(np.isfinite(S)) and S.max() > 0, k
+    if not args.no_extra:
+        line["extra"] = {"sphere_3d": sphere_extra(Simulation, W, torch)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(Simulation, W)
+    for _, _, s in sims:
+        s.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

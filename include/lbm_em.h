@@ -125,6 +125,26 @@ lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
  * bit-identical to lbm_em_step on each handle. */
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);
 
+/* Launch shape of the step kernel: every thread updates vx consecutive
+ * x-cells (vx in {1, 2, 4} for FP32, {1, 2} for FP64), thread blocks are
+ * bx x by threads (64 <= bx*by <= 256, a multiple of the 64-wide wavefront).
+ * The tile only changes speed, never results (each cell's update is
+ * independent of the tiling).  EINVAL for other shapes. */
+lbm_em_status lbm_em_set_tile(lbm_em_handle h, int32_t vx, int32_t bx, int32_t by);
+lbm_em_status lbm_em_get_tile(lbm_em_handle h, int32_t *vx, int32_t *bx, int32_t *by);
+
+/* Time every supported tile on this handle's grid (`launches` launches each,
+ * reading the current state and writing the spare buffer with the DFT off,
+ * so the simulation is not advanced), keep the fastest and verify that it
+ * reproduces the one-cell-per-thread kernel bit for bit (EDEVICE if not).
+ * *best_us (may be NULL) receives the winner's time per launch. */
+lbm_em_status lbm_em_autotune(lbm_em_handle h, int32_t launches, double *best_us);
+
+/* Restart from t = 0: zero the distributions and the DFT accumulators
+ * (stream-ordered, no allocation).  Permittivity, source and contour are
+ * kept. */
+lbm_em_status lbm_em_reset(lbm_em_handle h);
+
 /* Current time step t (number of steps taken). */
 lbm_em_status lbm_em_time(lbm_em_handle h, int64_t *t);
 

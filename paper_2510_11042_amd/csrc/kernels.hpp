@@ -228,48 +228,76 @@ __device__ inline int pull_lo(int x, int n, int W) { return x > 0 ? x - 1 : (W ?
 __device__ inline int pull_hi(int x, int n, int W) { return x < n - 1 ? x + 1 : (W ? n - 1 : 0); }
 
 // ---------------------------------------------------------------------------
-// 2-D fused step: pull + moments + DFT + collision + layer/source + store
+// Vector loads/stores: each thread updates VX consecutive x-cells.  Aligned
+// accesses use VX*sizeof(T)-aligned vectors; the +-x pulls are the same
+// vectors shifted by one element (only element alignment), which gfx950
+// serves with a single dwordx4 / dwordx2 access.
+// ---------------------------------------------------------------------------
+template <typename T, int N> struct Vec;
+template <> struct Vec<float, 4> {
+    typedef float u __attribute__((ext_vector_type(4), aligned(4)));
+    typedef float a __attribute__((ext_vector_type(4), aligned(16)));
+};
+template <> struct Vec<float, 2> {
+    typedef float u __attribute__((ext_vector_type(2), aligned(4)));
+    typedef float a __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <> struct Vec<double, 2> {
+    typedef double u __attribute__((ext_vector_type(2), aligned(8)));
+    typedef double a __attribute__((ext_vector_type(2), aligned(16)));
+};
+
+template <typename T, int N>
+__device__ inline void load_shifted(T (&o)[N], const T *p) {
+    if constexpr (N == 1) {
+        o[0] = p[0];
+    } else {
+        typename Vec<T, N>::u v = *(const typename Vec<T, N>::u *)p;
+#pragma unroll
+        for (int k = 0; k < N; ++k) o[k] = v[k];
+    }
+}
+template <typename T, int N>
+__device__ inline void load_aligned(T (&o)[N], const T *p) {
+    if constexpr (N == 1) {
+        o[0] = p[0];
+    } else {
+        typename Vec<T, N>::a v = *(const typename Vec<T, N>::a *)p;
+#pragma unroll
+        for (int k = 0; k < N; ++k) o[k] = v[k];
+    }
+}
+template <typename T, int N>
+__device__ inline void store_aligned(T *p, const T (&i)[N]) {
+    if constexpr (N == 1) {
+        p[0] = i[0];
+    } else {
+        typename Vec<T, N>::a v;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = i[k];
+        *(typename Vec<T, N>::a *)p = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2-D per-cell update: moments, DFT sample, collision, layer/source blend.
+// f holds the pulled populations on entry and f*(t) on exit.
 // ---------------------------------------------------------------------------
 template <typename T, int POL>
-__global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= a.nx || y >= a.ny) return;
-    const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
-    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
-    const int64_t P = a.plane, row = (int64_t)y * a.sy, c = row + x;
-    const int64_t rm = (int64_t)ym * a.sy, rp = (int64_t)yp * a.sy;
-    const T *s = a.src;
-    T f[11];
-    f[0] = s[0 * P + row + xm];   // +x from x-1
-    f[1] = s[1 * P + row + xp];   // -x from x+1
-    f[2] = s[2 * P + rm + x];     // +y from y-1
-    f[3] = s[3 * P + rp + x];     // -y from y+1
-    f[4] = s[4 * P + row + xm];
-    f[5] = s[5 * P + row + xp];
-    f[6] = s[6 * P + rm + x];
-    f[7] = s[7 * P + rp + x];
-    f[8] = s[8 * P + c];
-    f[9] = s[9 * P + c];
-    f[10] = s[10 * P + c];
-    const T eps = a.eps[c];
+__device__ inline void cell_update2d(const StepArgs<T> &a, int64_t t, int x, int y, T eps, T f[11]) {
     const T inv_eps = T(1) / eps;
     T F[3];
     fields2d<T, POL>(f, eps, inv_eps, F);
-
-    const int64_t t = step_time(a.t_base, a.t_off);
     if (a.dft_on) {
         double E[3] = {0, 0, 0}, H[3] = {0, 0, 0};
         if (POL == TM) { E[2] = F[0]; H[0] = F[1]; H[1] = F[2]; }
         else { E[0] = F[0]; E[1] = F[1]; H[2] = F[2]; }
         dft_accumulate(a, t, 2, x, y, 0, E, H);
     }
-
     T q[11];
     equilibrium2d<T, POL>(F, T(2), q);
 #pragma unroll
     for (int i = 0; i < 11; ++i) f[i] = q[i] - f[i];
-
     const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max),
                        sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max));
     if (sig > T(0)) {
@@ -284,9 +312,84 @@ __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = f[i] - sig * (f[i] - qr[i]);
     }
-    T *d = a.dst;
+}
+
+// ---------------------------------------------------------------------------
+// 2-D fused step: pull + moments + DFT + collision + layer/source + store.
+// Thread (gx, y) updates cells x0 = VX*gx .. x0+VX-1 of row y.
+// ---------------------------------------------------------------------------
+template <typename T, int POL, int VX>
+__global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
+    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x0 >= a.nx || y >= a.ny) return;
+    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
+    const int64_t P = a.plane, row = (int64_t)y * a.sy;
+    const int64_t rm = (int64_t)ym * a.sy, rp = (int64_t)yp * a.sy;
+    const T *s = a.src;
+    const bool full = x0 + VX <= a.nx;
+    const bool inner = full && x0 > 0 && x0 + VX < a.nx;
+    T v[11][VX], e[VX];
+    if (inner) {
+        load_shifted<T, VX>(v[0], s + 0 * P + row + x0 - 1);   // +x from x-1
+        load_shifted<T, VX>(v[4], s + 4 * P + row + x0 - 1);
+        load_shifted<T, VX>(v[1], s + 1 * P + row + x0 + 1);   // -x from x+1
+        load_shifted<T, VX>(v[5], s + 5 * P + row + x0 + 1);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 11; ++i) d[i * P + c] = f[i];
+        for (int k = 0; k < VX; ++k) {
+            const int x = x0 + k < a.nx ? x0 + k : a.nx - 1;
+            const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
+            v[0][k] = s[0 * P + row + xm];
+            v[4][k] = s[4 * P + row + xm];
+            v[1][k] = s[1 * P + row + xp];
+            v[5][k] = s[5 * P + row + xp];
+        }
+    }
+    if (full) {
+        load_aligned<T, VX>(v[2], s + 2 * P + rm + x0);        // +y from y-1
+        load_aligned<T, VX>(v[6], s + 6 * P + rm + x0);
+        load_aligned<T, VX>(v[3], s + 3 * P + rp + x0);        // -y from y+1
+        load_aligned<T, VX>(v[7], s + 7 * P + rp + x0);
+        load_aligned<T, VX>(v[8], s + 8 * P + row + x0);       // z-pair: no move
+        load_aligned<T, VX>(v[9], s + 9 * P + row + x0);
+        load_aligned<T, VX>(v[10], s + 10 * P + row + x0);
+        load_aligned<T, VX>(e, a.eps + row + x0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const int x = x0 + k < a.nx ? x0 + k : a.nx - 1;
+            v[2][k] = s[2 * P + rm + x];
+            v[6][k] = s[6 * P + rm + x];
+            v[3][k] = s[3 * P + rp + x];
+            v[7][k] = s[7 * P + rp + x];
+            v[8][k] = s[8 * P + row + x];
+            v[9][k] = s[9 * P + row + x];
+            v[10][k] = s[10 * P + row + x];
+            e[k] = a.eps[row + x];
+        }
+    }
+    const int64_t t = step_time(a.t_base, a.t_off);
+#pragma unroll
+    for (int k = 0; k < VX; ++k) {
+        T f[11];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) f[i] = v[i][k];
+        cell_update2d<T, POL>(a, t, x0 + k, y, e[k], f);
+#pragma unroll
+        for (int i = 0; i < 11; ++i) v[i][k] = f[i];
+    }
+    T *d = a.dst;
+    if (full) {
+#pragma unroll
+        for (int i = 0; i < 11; ++i) store_aligned<T, VX>(d + i * P + row + x0, v[i]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VX; ++k)
+            if (x0 + k < a.nx)
+#pragma unroll
+                for (int i = 0; i < 11; ++i) d[i * P + row + x0 + k] = v[i][k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -339,44 +442,18 @@ __device__ inline void equilibrium3d(const T E[3], const T H[3], T eps, T scale,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.nx || y >= a.ny) return;
-    const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
-    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
-    const int zm = pull_lo(z, a.nz, a.W[2]), zp = pull_hi(z, a.nz, a.W[2]);
-    const int64_t P = a.plane;
-    const int64_t c = (int64_t)z * a.sz + (int64_t)y * a.sy + x;
-    const int64_t src_cell[6] = {
-        (int64_t)z * a.sz + (int64_t)y * a.sy + xm, (int64_t)z * a.sz + (int64_t)y * a.sy + xp,
-        (int64_t)z * a.sz + (int64_t)ym * a.sy + x, (int64_t)z * a.sz + (int64_t)yp * a.sy + x,
-        (int64_t)zm * a.sz + (int64_t)y * a.sy + x, (int64_t)zp * a.sz + (int64_t)y * a.sy + x};
-    const T *s = a.src;
-    T f[27];
-#pragma unroll
-    for (int d = 0; d < 6; ++d)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) f[4 * d + k] = s[(4 * d + k) * P + src_cell[d]];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) f[24 + k] = s[(24 + k) * P + c];
-    const T eps = a.eps[c];
+__device__ inline void cell_update3d(const StepArgs<T> &a, int64_t t, int x, int y, int z, T eps, T f[27]) {
     const T inv_eps = T(1) / eps;
     T E[3], H[3];
     fields3d(f, inv_eps, E, H);
-
-    const int64_t t = step_time(a.t_base, a.t_off);
     if (a.dft_on) {
         double Ed[3] = {E[0], E[1], E[2]}, Hd[3] = {H[0], H[1], H[2]};
         dft_accumulate(a, t, 3, x, y, z, Ed, Hd);
     }
-
     T q[27];
     equilibrium3d(E, H, eps, T(2), q);
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = q[i] - f[i];
-
     const T sig = fmax(fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max),
                             sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max)),
                        sigma_axis<T>(z, a.nz, a.W[2], a.sigma_max));
@@ -395,9 +472,86 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < 27; ++i) f[i] = f[i] - sig * (f[i] - qr[i]);
     }
-    T *d = a.dst;
+}
+
+template <typename T, int VX>
+__global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
+    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x0 >= a.nx || y >= a.ny) return;
+    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
+    const int zm = pull_lo(z, a.nz, a.W[2]), zp = pull_hi(z, a.nz, a.W[2]);
+    const int64_t P = a.plane;
+    const int64_t base = (int64_t)z * a.sz + (int64_t)y * a.sy;
+    // row start of the source of each direction (x handled separately)
+    const int64_t srow[6] = {base, base, (int64_t)z * a.sz + (int64_t)ym * a.sy,
+                             (int64_t)z * a.sz + (int64_t)yp * a.sy, (int64_t)zm * a.sz + (int64_t)y * a.sy,
+                             (int64_t)zp * a.sz + (int64_t)y * a.sy};
+    const T *s = a.src;
+    const bool full = x0 + VX <= a.nx;
+    const bool inner = full && x0 > 0 && x0 + VX < a.nx;
+    T v[27][VX], e[VX];
+    if (inner) {
 #pragma unroll
-    for (int i = 0; i < 27; ++i) d[i * P + c] = f[i];
+        for (int k = 0; k < 4; ++k) {
+            load_shifted<T, VX>(v[k], s + k * P + base + x0 - 1);          // +x from x-1
+            load_shifted<T, VX>(v[4 + k], s + (4 + k) * P + base + x0 + 1);  // -x from x+1
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            const int x = x0 + j < a.nx ? x0 + j : a.nx - 1;
+            const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k][j] = s[k * P + base + xm];
+                v[4 + k][j] = s[(4 + k) * P + base + xp];
+            }
+        }
+    }
+    if (full) {
+#pragma unroll
+        for (int d = 2; d < 6; ++d)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) load_aligned<T, VX>(v[4 * d + k], s + (4 * d + k) * P + srow[d] + x0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) load_aligned<T, VX>(v[24 + k], s + (24 + k) * P + base + x0);
+        load_aligned<T, VX>(e, a.eps + base + x0);
+    } else {
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            const int x = x0 + j < a.nx ? x0 + j : a.nx - 1;
+#pragma unroll
+            for (int d = 2; d < 6; ++d)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[4 * d + k][j] = s[(4 * d + k) * P + srow[d] + x];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[24 + k][j] = s[(24 + k) * P + base + x];
+            e[j] = a.eps[base + x];
+        }
+    }
+    const int64_t t = step_time(a.t_base, a.t_off);
+#pragma unroll
+    for (int j = 0; j < VX; ++j) {
+        T f[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) f[i] = v[i][j];
+        cell_update3d<T>(a, t, x0 + j, y, z, e[j], f);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) v[i][j] = f[i];
+    }
+    T *d = a.dst;
+    if (full) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) store_aligned<T, VX>(d + i * P + base + x0, v[i]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < VX; ++j)
+            if (x0 + j < a.nx)
+#pragma unroll
+                for (int i = 0; i < 27; ++i) d[i * P + base + x0 + j] = v[i][j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -459,6 +613,13 @@ template <typename T>
 __global__ void k_fill(T *p, int64_t n, T v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Element-wise equality check (autotuner): any mismatch sets *flag = 1.
+template <typename T>
+__global__ void k_compare(const T *a, const T *b, int64_t n, int *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && a[i] != b[i]) flag[0] = 1;
 }
 
 // Device step counter for graph replays (vector store from one lane).

@@ -73,7 +73,7 @@ struct lbm_em {
     void *eps = nullptr;
     int64_t t = 0;
     hipStream_t stream = nullptr;
-    int bx = 64, by = 4;
+    int vx = 1, bx = 128, by = 2;       // cells per thread along x, block shape
     // source
     bool src_on = false;
     lbm_em_plane_wave pw{};
@@ -137,25 +137,41 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     return a;
 }
 
+template <typename T, int VX>
+void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
+    dim3 block(h->bx, h->by, 1);
+    const int gx = (h->cfg.nx + VX - 1) / VX;
+    dim3 grid((unsigned)((gx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
+              (unsigned)h->cfg.nz);
+    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX>), grid, block, 0, s, a);
+    else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE, VX>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step3d<T, VX>), grid, block, 0, s, a);
+}
+
 template <typename T>
 void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base,
-                   int64_t t_off, hipStream_t s) {
+                   int64_t t_off, hipStream_t s, bool dft) {
     StepArgs<T> a = make_args<T>(h, src, dst);
     a.t_base = t_base;
     a.t_off = t_off;
-    dim3 block(h->bx, h->by, 1);
-    dim3 grid((unsigned)((h->cfg.nx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
-              (unsigned)h->cfg.nz);
-    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM>), grid, block, 0, s, a);
-    else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step3d<T>), grid, block, 0, s, a);
+    if (!dft) a.dft_on = 0;
+    if (h->vx == 1) launch_step_vx<T, 1>(a, h, s);
+    else if (h->vx == 2) launch_step_vx<T, 2>(a, h, s);
+    else if constexpr (sizeof(T) == 4) launch_step_vx<T, 4>(a, h, s);
 }
 
-void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s) {
+void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
+                 bool dft = true) {
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
-    if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s);
-    else launch_step_t<double>(h, src, dst, t_base, t_off, s);
+    if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s, dft);
+    else launch_step_t<double>(h, src, dst, t_base, t_off, s, dft);
+}
+
+bool tile_ok(const lbm_em *h, int vx, int bx, int by) {
+    const bool vx_ok = vx == 1 || vx == 2 || (vx == 4 && h->cfg.precision == LBM_EM_FP32);
+    const int th = bx * by;
+    return vx_ok && bx >= 1 && by >= 1 && th >= 64 && th <= 256 && th % 64 == 0;
 }
 
 void drop_graphs(lbm_em *h) {
@@ -424,6 +440,113 @@ lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n
         if (n < 0) fail(LBM_EM_EINVAL, "n must be >= 0");
         for (int i = 0; i < count; ++i) check_handle(hs[i]);
         fail(LBM_EM_EUNSUPPORTED, "step_many is not built yet");
+    });
+}
+
+lbm_em_status lbm_em_set_tile(lbm_em_handle hh, int32_t vx, int32_t bx, int32_t by) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!tile_ok(h, vx, bx, by))
+            fail(LBM_EM_EINVAL, "tile: vx in {1,2} (FP64) or {1,2,4} (FP32), 64 <= bx*by <= 256, bx*by % 64 == 0");
+        h->vx = vx;
+        h->bx = bx;
+        h->by = by;
+        drop_graphs(h);
+    });
+}
+
+lbm_em_status lbm_em_get_tile(lbm_em_handle hh, int32_t *vx, int32_t *bx, int32_t *by) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!vx || !bx || !by) fail(LBM_EM_EINVAL, "null output");
+        *vx = h->vx;
+        *bx = h->bx;
+        *by = h->by;
+    });
+}
+
+lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_us) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (launches < 1) fail(LBM_EM_EINVAL, "launches must be >= 1");
+        select_device(h);
+        static const int shapes[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 2}, {128, 1}, {64, 1}, {16, 16}};
+        const int vxs[] = {1, 2, 4};
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        const int keep[3] = {h->vx, h->bx, h->by};
+        int best[3] = {keep[0], keep[1], keep[2]};
+        float best_ms = 1e30f;
+        // Timed launches read the current buffer and write the spare one with
+        // the DFT off: the simulation state is not changed.
+        for (int vx : vxs)
+            for (auto &sh : shapes) {
+                if (!tile_ok(h, vx, sh[0], sh[1])) continue;
+                h->vx = vx;
+                h->bx = sh[0];
+                h->by = sh[1];
+                launch_step(h, h->cur, nullptr, h->t, h->stream, false);
+                hip_check(hipEventRecord(e0, h->stream), "hipEventRecord");
+                for (int i = 0; i < launches; ++i) launch_step(h, h->cur, nullptr, h->t, h->stream, false);
+                hip_check(hipEventRecord(e1, h->stream), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best[0] = vx;
+                    best[1] = sh[0];
+                    best[2] = sh[1];
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        // The winner must reproduce the one-cell-per-thread kernel bit for bit.
+        const size_t n = (size_t)h->plane * h->nplanes;
+        void *ref = nullptr;
+        int *flag = nullptr;
+        hip_check(hipMalloc(&ref, n * h->elem), "hipMalloc");
+        hip_check(hipMalloc(&flag, sizeof(int)), "hipMalloc");
+        hip_check(hipMemsetAsync(flag, 0, sizeof(int), h->stream), "hipMemset");
+        h->vx = 1; h->bx = 64; h->by = 4;
+        launch_step(h, h->cur, nullptr, h->t, h->stream, false);
+        hip_check(hipMemcpyAsync(ref, h->buf[h->cur ^ 1], n * h->elem, hipMemcpyDeviceToDevice, h->stream), "copy");
+        h->vx = best[0]; h->bx = best[1]; h->by = best[2];
+        launch_step(h, h->cur, nullptr, h->t, h->stream, false);
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        if (h->elem == 4)
+            hipLaunchKernelGGL((k_compare<float>), dim3(blocks), dim3(256), 0, h->stream, (const float *)ref,
+                               (const float *)h->buf[h->cur ^ 1], (int64_t)n, flag);
+        else
+            hipLaunchKernelGGL((k_compare<double>), dim3(blocks), dim3(256), 0, h->stream, (const double *)ref,
+                               (const double *)h->buf[h->cur ^ 1], (int64_t)n, flag);
+        int differs = 0;
+        hip_check(hipMemcpyAsync(&differs, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream), "D2H");
+        sync(h);
+        hfree(ref);
+        hfree(flag);
+        if (differs) {
+            h->vx = keep[0]; h->bx = keep[1]; h->by = keep[2];
+            fail(LBM_EM_EDEVICE, "autotune: tiled kernel differs from the reference kernel");
+        }
+        drop_graphs(h);
+        if (best_us) *best_us = 1e3 * best_ms / launches;
+    });
+}
+
+lbm_em_status lbm_em_reset(lbm_em_handle hh) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        select_device(h);
+        const size_t bytes = (size_t)h->plane * h->nplanes * h->elem;
+        hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset state");
+        hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset state");
+        if (h->acc)
+            hip_check(hipMemsetAsync(h->acc, 0, (size_t)(h->nnodes + 1) * 12 * sizeof(double), h->stream),
+                      "hipMemset dft");
+        h->t = 0;
+        h->cur = 0;
     });
 }
 

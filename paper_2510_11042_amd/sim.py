@@ -5,6 +5,8 @@ library (torch.cuda.current_stream() when a device is present); all lattice
 Boltzmann arithmetic runs in liblbm_em.so.
 """
 import ctypes as C
+import json
+import os
 
 import numpy as np
 
@@ -105,6 +107,41 @@ class Simulation:
     def step(self, n=1):
         L.check(L.lib().lbm_em_step(self._h, int(n)))
 
+    def set_tile(self, vx, bx, by):
+        L.check(L.lib().lbm_em_set_tile(self._h, int(vx), int(bx), int(by)))
+
+    def get_tile(self):
+        v, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.lib().lbm_em_get_tile(self._h, C.byref(v), C.byref(b), C.byref(c)))
+        return v.value, b.value, c.value
+
+    def autotune(self, launches=20, cache=None):
+        """Pick the fastest verified tile for this grid (see lbm_em_autotune).
+        With a cache file (JSON; default $LBM_EM_TUNE_CACHE) a stored choice
+        for the same arch / layout / precision / grid is reused."""
+        cache = cache or os.environ.get("LBM_EM_TUNE_CACHE")
+        key = _tune_key(self)
+        table = {}
+        if cache and os.path.exists(cache):
+            table = json.load(open(cache))
+            if key in table:
+                self.set_tile(*table[key]["tile"])
+                return table[key]
+        us = C.c_double()
+        L.check(L.lib().lbm_em_autotune(self._h, int(launches), C.byref(us)))
+        rec = {"tile": list(self.get_tile()), "us_per_launch": us.value}
+        if cache:
+            table[key] = rec
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            tmp = cache + ".tmp"
+            json.dump(table, open(tmp, "w"), indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return rec
+
+    def reset(self):
+        """Back to t = 0 with zero fields (inputs kept)."""
+        L.check(L.lib().lbm_em_reset(self._h))
+
     @property
     def t(self):
         v = C.c_int64()
@@ -155,6 +192,16 @@ class Simulation:
         L.check(L.lib().lbm_em_farfield(self._h, incident.handle if incident is not None else None,
                                         dp(th), dp(ph) if ph is not None else None, th.size, dp(out)))
         return out
+
+
+def _tune_key(sim):
+    try:
+        import torch
+
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # pragma: no cover
+        arch = "unknown"
+    return f"{arch}/{sim.pol}/{sim.precision}/{sim.n[0]}x{sim.n[1]}x{sim.n[2]}"
 
 
 def step_many(sims, n):

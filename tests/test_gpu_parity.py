@@ -219,3 +219,64 @@ def test_full_size_cylinder_grid_short_run(gpu, pol):
         s.step(case.steps)
         compare_fields(s, o, prec, f"1024^2 {pol}")
         s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_every_tile_gives_identical_results(gpu, dim):
+    """The tile (cells per thread, block shape) changes speed only: each
+    cell's update is independent of it, so results are bit-identical."""
+    if dim == 2:
+        n = (83, 70, 1)
+        case = W.cylinder_case(2.25, "TE", n=83, a=9.0, lam=12.0, W=10, steps=150, half=13.0)
+        eps, pol, absorb = case.eps[:, :70, :], "TE", (10, 10, 0)
+        kh, eh = W.plane_wave_2d(20.0, "TE")
+        tiles = [(1, 64, 4), (2, 64, 4), (4, 64, 4), (4, 256, 1), (2, 32, 8), (4, 16, 16), (1, 128, 1)]
+    else:
+        n = (36, 30, 28)
+        eps = W.sphere_case(n=36, x_size=2.0, lam=9.0, eps_in=2.25, W=6, steps=90, half=8.5).eps[:28, :30, :]
+        pol, absorb = "3D", (6, 6, 6)
+        kh, eh = [0, 0, 1.0], [1.0, 0, 0]
+        tiles = [(1, 64, 4), (2, 64, 4), (4, 64, 4), (4, 32, 2), (2, 256, 1)]
+    ref = None
+    for prec in ("fp32", "fp64"):
+        ref = None
+        for vx, bx, by in tiles:
+            if prec == "fp64" and vx == 4:
+                continue
+            say("tile", dim, prec, vx, bx, by)
+            s = gpu(*n, pol=pol, precision=prec, absorb=absorb, sigma_max=W.SIGMA_MAX)
+            s.set_permittivity(eps)
+            s.set_source(9.0 if dim == 3 else 12.0, kh, eh, 1.0, 1.0)
+            s.set_tile(vx, bx, by)
+            assert s.get_tile() == (vx, bx, by)
+            s.step(90 if dim == 3 else 150)
+            E, H = s.fields()
+            if ref is None:
+                ref = (E, H)
+            else:
+                assert np.array_equal(E, ref[0]) and np.array_equal(H, ref[1]), (vx, bx, by)
+            s.close()
+
+
+def test_autotune_verifies_and_does_not_advance(gpu):
+    from paper_2510_11042_amd import LbmEmError
+
+    case = W.cylinder_case(2.25, "TM", n=256, a=12.0, lam=16.0, W=16, steps=120, half=18.5)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    sims = []
+    for tune in (False, True):
+        s = gpu(256, 256, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(case.eps)
+        s.set_source(case.lam, kh, eh)
+        s.step(60)
+        if tune:
+            rec = s.autotune(launches=5)
+            say("autotune", rec)
+            assert s.t == 60
+        s.step(60)
+        sims.append(s)
+    assert np.array_equal(sims[0].fields()[0], sims[1].fields()[0])
+    with pytest.raises(LbmEmError):
+        sims[0].set_tile(3, 64, 4)
+    with pytest.raises(LbmEmError):
+        sims[0].set_tile(1, 100, 1)
