@@ -46,6 +46,7 @@ typedef enum {
 } lbm_em_status;
 
 typedef struct lbm_em *lbm_em_handle;
+typedef struct lbm_em_batch_s *lbm_em_batch;
 
 /* Field layout of a handle.  2-D runs are D3Q7 on nz == 1 with z streaming the
  * identity; TM carries (E_z, H_x, H_y) -- E along the invariant axis, the
@@ -119,11 +120,33 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_
  * replayed from a captured HIP graph in chunks. */
 lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
 
-/* Advance `count` handles n steps together: one launch per step covers all
- * instances (a flattened tile worklist).  All handles must share precision,
- * polarisation and stream and be at the same time step.  Results are
- * bit-identical to lbm_em_step on each handle. */
+/* Advance `count` 2-D handles n steps together: one persistent launch per
+ * step covers all instances (a flattened (instance, tile) work list that a
+ * chip-sized grid strides over).  All handles must share polarisation,
+ * precision, stream and device and be at the same time step; each keeps
+ * its own grid size, permittivity, source and contour.  Results are
+ * bit-identical to lbm_em_step on each handle.  Uses the tile of hs[0].
+ * EUNSUPPORTED for 3-D handles.  (One-shot form of the batch calls below.) */
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);
+
+/* A reusable batch: snapshots the handles' settings (source, contour, tile;
+ * permittivity values may still change through set_permittivity) and
+ * replays lbm_em_batch_step from captured HIP graphs.  Instances are packed
+ * in order into groups whose state (two buffers + eps) fits a cache budget
+ * (default 192 MiB, inside the 256 MB Infinity Cache); batch_step advances
+ * each group the n steps in turn, one persistent launch per step per group.
+ * The handles must not be destroyed, re-configured or stepped on their own
+ * while the batch is used (ESTATE if their time steps diverge). */
+lbm_em_status lbm_em_batch_create(const lbm_em_handle *hs, int32_t count, lbm_em_batch *out);
+lbm_em_status lbm_em_batch_step(lbm_em_batch b, int64_t n);
+/* Thread blocks of each persistent launch (default 32 per CU, capped at the
+ * number of work items of the group). */
+lbm_em_status lbm_em_batch_set_grid(lbm_em_batch b, int32_t grid);
+/* Cache budget for grouping in bytes; 0 = all instances in one group. */
+lbm_em_status lbm_em_batch_set_cache_budget(lbm_em_batch b, int64_t bytes);
+/* Number of groups of the current plan. */
+lbm_em_status lbm_em_batch_groups(lbm_em_batch b, int32_t *groups);
+lbm_em_status lbm_em_batch_destroy(lbm_em_batch b);
 
 /* Launch shape of the step kernel: every thread updates vx consecutive
  * x-cells (vx in {1, 2, 4} for FP32, {1, 2} for FP64), thread blocks are

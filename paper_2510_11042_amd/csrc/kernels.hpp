@@ -319,9 +319,7 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, int64_t t, int x, int
 // Thread (gx, y) updates cells x0 = VX*gx .. x0+VX-1 of row y.
 // ---------------------------------------------------------------------------
 template <typename T, int POL, int VX>
-__global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
-    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+__device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, int64_t t) {
     if (x0 >= a.nx || y >= a.ny) return;
     const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
     const int64_t P = a.plane, row = (int64_t)y * a.sy;
@@ -369,7 +367,6 @@ __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
             e[k] = a.eps[row + x];
         }
     }
-    const int64_t t = step_time(a.t_base, a.t_off);
 #pragma unroll
     for (int k = 0; k < VX; ++k) {
         T f[11];
@@ -389,6 +386,36 @@ __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
             if (x0 + k < a.nx)
 #pragma unroll
                 for (int i = 0; i < 11; ++i) d[i * P + row + x0 + k] = v[i][k];
+    }
+}
+
+template <typename T, int POL, int VX>
+__global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
+    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    step2d_cells<T, POL, VX>(a, x0, y, step_time(a.t_base, a.t_off));
+}
+
+// Batched persistent step: one launch advances many 2-D instances of
+// different sizes.  The work list is every (instance, tile) pair, tiles of
+// bx*VX x by cells, instances one after another; a grid sized to the chip
+// strides over it.  tile_first[i] is the first work item of instance i,
+// tile_inst[w] the instance of work item w.  Per-instance arguments live in
+// device memory; the step index is shared.
+template <typename T, int POL, int VX>
+__global__ void __launch_bounds__(256) k_step2d_batch(const StepArgs<T> *__restrict__ descs,
+                                                      const int *__restrict__ tile_inst,
+                                                      const int *__restrict__ tile_first, int ntiles,
+                                                      const int64_t *t_base, int64_t t_off) {
+    const int64_t t = step_time(t_base, t_off);
+    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+        const int inst = tile_inst[w];
+        const StepArgs<T> &a = descs[inst];
+        const int local = w - tile_first[inst];
+        const int tx = local % a.tiles_x, ty = local / a.tiles_x;
+        const int x0 = (tx * (int)blockDim.x + (int)threadIdx.x) * VX;
+        const int y = ty * (int)blockDim.y + (int)threadIdx.y;
+        step2d_cells<T, POL, VX>(a, x0, y, t);
     }
 }
 

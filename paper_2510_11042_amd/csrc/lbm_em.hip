@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -89,6 +90,30 @@ struct lbm_em {
     int64_t *t_dev = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // indexed by starting buffer parity
     int dev = 0;
+};
+
+// A batch: several 2-D handles advanced by one persistent launch per step.
+// Instances are packed, in order, into groups whose state fits a cache
+// budget (the 256 MB Infinity Cache by default); each group is advanced the
+// requested number of steps before the next one, so a group's working set
+// stays cache resident.  Instances are independent, so the grouping does
+// not change any result.
+struct BatchGroup {
+    int first = 0, count = 0;              // instance range
+    void *descs[2] = {nullptr, nullptr};   // StepArgs per instance, for buffer parity 0 / 1
+    int *tile_inst = nullptr, *tile_first = nullptr;
+    int ntiles = 0, grid = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+struct lbm_em_batch_s {
+    std::vector<lbm_em *> hs;
+    std::vector<BatchGroup> groups;
+    int pol = 0, precision = 0, vx = 1, bx = 128, by = 2;
+    int64_t *t_dev = nullptr;
+    hipStream_t stream = nullptr;
+    int dev = 0, cus = 1, grid_override = 0;
+    int64_t budget = 0;
 };
 
 namespace {
@@ -227,6 +252,209 @@ void do_steps(lbm_em *h, int64_t n) {
         hip_check(hipGetLastError(), "step kernel launch");
         h->cur ^= 1;
         h->t += 1;
+    }
+}
+
+int64_t handle_bytes(const lbm_em *h) { return (int64_t)h->plane * (2 * h->nplanes + 1) * (int64_t)h->elem; }
+
+template <typename T>
+void fill_group(lbm_em_batch_s *b, BatchGroup &g) {
+    std::vector<int> first;
+    for (int par = 0; par < 2; ++par) {
+        std::vector<StepArgs<T>> d(g.count);
+        for (int i = 0; i < g.count; ++i) {
+            const lbm_em *h = b->hs[g.first + i];
+            d[i] = make_args<T>(h, h->buf[par], h->buf[par ^ 1]);
+            d[i].tiles_x = ((h->cfg.nx + b->vx - 1) / b->vx + b->bx - 1) / b->bx;
+            d[i].tiles_y = (h->cfg.ny + b->by - 1) / b->by;
+        }
+        if (par == 0) {
+            int acc = 0;
+            for (auto &x : d) {
+                first.push_back(acc);
+                acc += x.tiles_x * x.tiles_y;
+            }
+            g.ntiles = acc;
+        }
+        hip_check(hipMalloc(&g.descs[par], d.size() * sizeof(StepArgs<T>)), "hipMalloc batch");
+        hip_check(hipMemcpyAsync(g.descs[par], d.data(), d.size() * sizeof(StepArgs<T>), hipMemcpyHostToDevice,
+                                 b->stream), "H2D batch");
+    }
+    std::vector<int> inst(g.ntiles);
+    for (int i = 0; i < g.count; ++i) {
+        const int end = i + 1 < g.count ? first[i + 1] : g.ntiles;
+        for (int w = first[i]; w < end; ++w) inst[w] = i;
+    }
+    hip_check(hipMalloc(&g.tile_inst, inst.size() * sizeof(int)), "hipMalloc batch");
+    hip_check(hipMalloc(&g.tile_first, first.size() * sizeof(int)), "hipMalloc batch");
+    hip_check(hipMemcpyAsync(g.tile_inst, inst.data(), inst.size() * sizeof(int), hipMemcpyHostToDevice, b->stream),
+              "H2D batch");
+    hip_check(hipMemcpyAsync(g.tile_first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
+                             b->stream), "H2D batch");
+    g.grid = std::min(g.ntiles, b->grid_override > 0 ? b->grid_override : b->cus * 32);
+}
+
+template <typename T, int VX>
+void launch_batch_vx(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
+                     hipStream_t s) {
+    dim3 block(b->bx, b->by, 1);
+    const StepArgs<T> *d = (const StepArgs<T> *)g.descs[par];
+    if (b->pol == LBM_EM_TM)
+        hipLaunchKernelGGL((k_step2d_batch<T, TM, VX>), dim3(g.grid), block, 0, s, d, g.tile_inst, g.tile_first,
+                           g.ntiles, t_base, t_off);
+    else
+        hipLaunchKernelGGL((k_step2d_batch<T, TE, VX>), dim3(g.grid), block, 0, s, d, g.tile_inst, g.tile_first,
+                           g.ntiles, t_base, t_off);
+}
+
+void launch_batch(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
+                  hipStream_t s) {
+    if (b->precision == LBM_EM_FP32) {
+        if (b->vx == 1) launch_batch_vx<float, 1>(b, g, par, t_base, t_off, s);
+        else if (b->vx == 2) launch_batch_vx<float, 2>(b, g, par, t_base, t_off, s);
+        else launch_batch_vx<float, 4>(b, g, par, t_base, t_off, s);
+    } else {
+        if (b->vx == 1) launch_batch_vx<double, 1>(b, g, par, t_base, t_off, s);
+        else launch_batch_vx<double, 2>(b, g, par, t_base, t_off, s);
+    }
+}
+
+void free_groups(lbm_em_batch_s *b) {
+    for (auto &g : b->groups) {
+        for (auto &ge : g.graph)
+            if (ge) (void)hipGraphExecDestroy(ge);
+        hfree(g.descs[0]);
+        hfree(g.descs[1]);
+        hfree(g.tile_inst);
+        hfree(g.tile_first);
+    }
+    b->groups.clear();
+}
+
+void free_batch(lbm_em_batch_s *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->dev);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    else (void)hipDeviceSynchronize();
+    free_groups(b);
+    hfree(b->t_dev);
+    delete b;
+}
+
+// (Re)build the groups for the current cache budget and grid setting.
+void plan_batch(lbm_em_batch_s *b) {
+    if (b->stream) hip_check(hipStreamSynchronize(b->stream), "sync");
+    free_groups(b);
+    const int n = (int)b->hs.size();
+    int i = 0;
+    while (i < n) {
+        BatchGroup g;
+        g.first = i;
+        int64_t bytes = 0;
+        do {
+            bytes += handle_bytes(b->hs[i]);
+            ++i;
+        } while (i < n && (b->budget <= 0 || bytes + handle_bytes(b->hs[i]) <= b->budget));
+        g.count = i - g.first;
+        b->groups.push_back(g);
+        if (b->precision == LBM_EM_FP32) fill_group<float>(b, b->groups.back());
+        else fill_group<double>(b, b->groups.back());
+    }
+    hip_check(hipStreamSynchronize(b->stream), "sync");
+}
+
+lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
+    if (!hs || count < 1) fail(LBM_EM_EINVAL, "need at least one handle");
+    lbm_em *h0 = check_handle(hs[0]);
+    for (int i = 0; i < count; ++i) {
+        lbm_em *h = check_handle(hs[i]);
+        if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "batched stepping supports 2-D (TM/TE) handles");
+        if (h->cfg.pol != h0->cfg.pol || h->cfg.precision != h0->cfg.precision)
+            fail(LBM_EM_EINVAL, "batched handles must share polarisation and precision");
+        if (h->stream != h0->stream || h->dev != h0->dev) fail(LBM_EM_EINVAL, "batched handles must share stream and device");
+        if (h->t != h0->t || h->cur != h0->cur) fail(LBM_EM_ESTATE, "batched handles must be at the same time step");
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) fail(LBM_EM_EINVAL, "a handle appears twice in the batch");
+    }
+    select_device(h0);
+    lbm_em_batch_s *b = new lbm_em_batch_s();
+    try {
+        b->dev = h0->dev;
+        b->stream = h0->stream;
+        b->pol = h0->cfg.pol;
+        b->precision = h0->cfg.precision;
+        b->vx = h0->vx;
+        b->bx = h0->bx;
+        b->by = h0->by;
+        b->budget = (int64_t)192 << 20;
+        for (int i = 0; i < count; ++i) b->hs.push_back(hs[i]);
+        hip_check(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev), "attribute");
+        b->cus = std::max(1, b->cus);
+        hip_check(hipMalloc(&b->t_dev, 64), "hipMalloc batch");
+        plan_batch(b);
+    } catch (...) {
+        free_batch(b);
+        throw;
+    }
+    return b;
+}
+
+hipGraphExec_t build_batch_graph(lbm_em_batch_s *b, const BatchGroup &grp, int p) {
+    hipStream_t cs = nullptr;
+    hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        hip_check(e, "hipStreamBeginCapture");
+    }
+    int par = p;
+    for (int k = 0; k < kGraphChunk; ++k) {
+        launch_batch(b, grp, par, b->t_dev, k, cs);
+        par ^= 1;
+    }
+    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, cs, b->t_dev, (int64_t)kGraphChunk);
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    hip_check(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(e, "hipGraphInstantiate");
+    return ge;
+}
+
+void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
+    lbm_em *h0 = b->hs[0];
+    for (auto *h : b->hs)
+        if (h->t != h0->t || h->cur != h0->cur)
+            fail(LBM_EM_ESTATE, "batched handles were stepped separately since the batch was made");
+    (void)hipSetDevice(b->dev);
+    const int64_t t_start = h0->t;
+    const int cur_start = h0->cur;
+    int64_t t = t_start;
+    int cur = cur_start;
+    for (auto &g : b->groups) {
+        t = t_start;
+        cur = cur_start;
+        int64_t chunks = use_graph ? n / kGraphChunk : 0;
+        if (chunks > 0) {
+            if (!g.graph[cur]) g.graph[cur] = build_batch_graph(b, g, cur);
+            hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, b->stream, b->t_dev, t);
+            hip_check(hipGetLastError(), "k_set_time");
+            for (int64_t c = 0; c < chunks; ++c) hip_check(hipGraphLaunch(g.graph[cur], b->stream), "hipGraphLaunch");
+            t += chunks * kGraphChunk;
+        }
+        for (int64_t k = 0; k < n - chunks * kGraphChunk; ++k) {
+            launch_batch(b, g, cur, nullptr, t, b->stream);
+            hip_check(hipGetLastError(), "batch kernel launch");
+            cur ^= 1;
+            t += 1;
+        }
+    }
+    for (auto *h : b->hs) {
+        h->t = t;
+        h->cur = cur;
     }
 }
 
@@ -436,10 +664,62 @@ lbm_em_status lbm_em_step(lbm_em_handle hh, int64_t n) {
 
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n) {
     return guarded([&] {
-        if (!hs || count < 1) fail(LBM_EM_EINVAL, "need at least one handle");
         if (n < 0) fail(LBM_EM_EINVAL, "n must be >= 0");
-        for (int i = 0; i < count; ++i) check_handle(hs[i]);
-        fail(LBM_EM_EUNSUPPORTED, "step_many is not built yet");
+        lbm_em_batch_s *b = make_batch(hs, count);
+        try {
+            batch_steps(b, n, false);
+        } catch (...) {
+            free_batch(b);
+            throw;
+        }
+        free_batch(b);
+    });
+}
+
+lbm_em_status lbm_em_batch_create(const lbm_em_handle *hs, int32_t count, lbm_em_batch *out) {
+    return guarded([&] {
+        if (!out) fail(LBM_EM_EINVAL, "null output");
+        *out = make_batch(hs, count);
+    });
+}
+
+lbm_em_status lbm_em_batch_step(lbm_em_batch b, int64_t n) {
+    return guarded([&] {
+        if (!b) fail(LBM_EM_EINVAL, "null batch");
+        if (n < 0) fail(LBM_EM_EINVAL, "n must be >= 0");
+        batch_steps(b, n, true);
+    });
+}
+
+lbm_em_status lbm_em_batch_set_grid(lbm_em_batch b, int32_t grid) {
+    return guarded([&] {
+        if (!b) fail(LBM_EM_EINVAL, "null batch");
+        if (grid < 1) fail(LBM_EM_EINVAL, "grid must be >= 1");
+        b->grid_override = grid;
+        plan_batch(b);
+    });
+}
+
+lbm_em_status lbm_em_batch_set_cache_budget(lbm_em_batch b, int64_t bytes) {
+    return guarded([&] {
+        if (!b) fail(LBM_EM_EINVAL, "null batch");
+        if (bytes < 0) fail(LBM_EM_EINVAL, "budget must be >= 0");
+        b->budget = bytes;
+        plan_batch(b);
+    });
+}
+
+lbm_em_status lbm_em_batch_groups(lbm_em_batch b, int32_t *groups) {
+    return guarded([&] {
+        if (!b || !groups) fail(LBM_EM_EINVAL, "null argument");
+        *groups = (int32_t)b->groups.size();
+    });
+}
+
+lbm_em_status lbm_em_batch_destroy(lbm_em_batch b) {
+    return guarded([&] {
+        if (!b) fail(LBM_EM_EINVAL, "null batch");
+        free_batch(b);
     });
 }
 

@@ -205,6 +205,45 @@ def _tune_key(sim):
 
 
 def step_many(sims, n):
-    """Advance several Simulations together (one launch per step)."""
+    """Advance several 2-D Simulations together (one launch per step)."""
     arr = (C.c_void_p * len(sims))(*[s.handle.value for s in sims])
     L.check(L.lib().lbm_em_step_many(arr, len(sims), int(n)))
+
+
+class Batch:
+    """Reusable batch of 2-D Simulations stepped by one persistent launch
+    per time step, replayed from captured HIP graphs."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.handle.value for s in self.sims])
+        b = C.c_void_p()
+        L.check(L.lib().lbm_em_batch_create(arr, len(self.sims), C.byref(b)))
+        self._b = b
+
+    def step(self, n=1):
+        L.check(L.lib().lbm_em_batch_step(self._b, int(n)))
+
+    def set_grid(self, blocks):
+        L.check(L.lib().lbm_em_batch_set_grid(self._b, int(blocks)))
+
+    def set_cache_budget(self, nbytes):
+        """Group instances so each group's state fits nbytes (0: one group)."""
+        L.check(L.lib().lbm_em_batch_set_cache_budget(self._b, int(nbytes)))
+
+    @property
+    def groups(self):
+        g = C.c_int32()
+        L.check(L.lib().lbm_em_batch_groups(self._b, C.byref(g)))
+        return g.value
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            L.check(L.lib().lbm_em_batch_destroy(self._b))
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

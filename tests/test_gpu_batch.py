@@ -1,0 +1,117 @@
+"""Batched persistent stepping: many uneven 2-D instances advanced by one
+launch per step must reproduce individually stepped handles bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_11042_amd as P
+
+    return P
+
+
+def _make(P, case, prec, tile=None):
+    kh, eh = W.plane_wave_2d(case.theta_deg, case.pol)
+    s = P.Simulation(case.nx, case.ny, 1, pol=case.pol, precision=prec, absorb=case.absorb,
+                     sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    s.set_source(case.lam, kh, eh, 1.0, 1.0)
+    if case.box_lo is not None:
+        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+    if tile:
+        s.set_tile(*tile)
+    return s
+
+
+def _cases(seed, count, steps):
+    """Seeded uneven scatterers (circle / hexagon, eps, size, lambda, angle)
+    shrunk so the test stays small."""
+    out = []
+    sides = [160, 128, 96, 112, 144, 80, 136]
+    for i, c in enumerate(W.batch_cases(count, seed=seed, W=12, steps=steps)):
+        n = int(min(c.nx, sides[i % len(sides)]))
+        lam = float(min(c.lam, 24.0))
+        a = min(c.radius, n / 6)
+        half = np.ceil(a) + 6.5
+        cc = W.cylinder_case(c.eps_in, "TM", n=n, a=a, lam=lam, W=12, steps=steps, half=half,
+                             theta_deg=c.theta_deg, shape=c.shape)
+        out.append(cc)
+    # one non-square grid too
+    extra = W.cylinder_case(3.0, "TM", n=96, a=10.0, lam=12.0, W=12, steps=steps, half=16.5)
+    extra.eps = extra.eps[:, :80, :]
+    extra.ny = 80
+    extra.box_lo, extra.box_hi = (31, 23, 0), (64, 56, 0)
+    out.append(extra)
+    return out
+
+
+@pytest.mark.parametrize("prec,tile", [("fp32", None), ("fp32", (4, 64, 4)), ("fp64", (2, 128, 2))])
+def test_batch_equals_individual(lib, prec, tile):
+    steps = 200                                    # 3 graph chunks + 8 eager steps
+    cases = _cases(251011042, 6, steps)
+    say("batch", prec, tile, [c.nx for c in cases])
+    solo = [_make(lib, c, prec, tile) for c in cases]
+    for s in solo:
+        s.step(steps)
+    grouped = [_make(lib, c, prec, tile) for c in cases]
+    b = lib.Batch(grouped)
+    b.step(130)
+    b.set_cache_budget(3 << 20)          # several groups from here on
+    assert b.groups > 1
+    b.step(70)
+    for s, g in zip(solo, grouped):
+        assert g.t == s.t == steps
+        Es, Hs = s.fields()
+        Eg, Hg = g.fields()
+        assert np.array_equal(Es, Eg) and np.array_equal(Hs, Hg)
+        Xs, ps = s.phasors()
+        Xg, pg = g.phasors()
+        assert np.array_equal(Xs, Xg) and np.array_equal(ps, pg)
+    b.close()
+
+
+def test_step_many_and_grid_size(lib):
+    cases = _cases(7, 3, 90)
+    say("step_many")
+    solo = [_make(lib, c, "fp32") for c in cases]
+    for s in solo:
+        s.step(90)
+    grouped = [_make(lib, c, "fp32") for c in cases]
+    lib.step_many(grouped, 40)
+    b = lib.Batch(grouped)
+    b.set_grid(7)                                   # few blocks: each strides over many tiles
+    b.step(50)
+    for s, g in zip(solo, grouped):
+        assert np.array_equal(s.fields()[0], g.fields()[0])
+
+
+def test_batch_rejects_mismatched_handles(lib):
+    from paper_2510_11042_amd import LbmEmError
+
+    c = _cases(3, 2, 200)
+    a = _make(lib, c[0], "fp32")
+    b = _make(lib, c[1], "fp64")
+    with pytest.raises(LbmEmError):
+        lib.Batch([a, b])
+    d = _make(lib, c[1], "fp32")
+    d.step(1)
+    with pytest.raises(LbmEmError):
+        lib.step_many([a, d], 1)
+    with pytest.raises(LbmEmError):
+        lib.step_many([a, a], 1)
