@@ -196,6 +196,36 @@ lbm_em_status lbm_em_get_phasors(lbm_em_handle h, double *out, int32_t *n_nodes)
 lbm_em_status lbm_em_farfield(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
                               const double *phi_deg, int32_t n_angles, double *out_S2);
 
+/* ---------------------------------------------------------------------
+ * Inverse design: gradient of a far-field objective with respect to eps_r
+ * in a design rectangle, by the discrete adjoint of the step (2-D TM/TE).
+ *
+ *   J(eps) = sum_a weight[a] |S(theta_a)|^2
+ *
+ * with |S|^2 as lbm_em_farfield computes it against `incident` (2-D:
+ * Eq. S2D of section 2.3 after the transform of section 2.4).  The design
+ * rectangle [dlo, dhi] (inclusive, cells) must lie strictly inside the
+ * contour box and outside the absorbing layer.
+ * --------------------------------------------------------------------- */
+/* Store the objective (angles in degrees from khat, weights; weight = NULL
+ * means 1), the design rectangle and the checkpoint spacing (0: ceil(sqrt(n))
+ * steps).  The incident handle must stay alive and completed. */
+lbm_em_status lbm_em_adjoint_setup(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
+                                   const double *weight, int32_t n_angles, const int32_t dlo[2],
+                                   const int32_t dhi[2], int32_t checkpoint_every);
+
+/* Restart the handle at t = 0, run n steps keeping a full-state checkpoint
+ * every K steps (K from adjoint_setup; memory ceil(n/K) states), evaluate J
+ * into *J_out (host).  n must cover the DFT window.  Synchronises. */
+lbm_em_status lbm_em_forward_checkpointed(lbm_em_handle h, int64_t n, double *J_out);
+
+/* dJ/deps_r for the design rectangle, (dhi-dlo+1) row-major doubles [y][x],
+ * on the host or device.  Segment by segment in reverse: restore the
+ * checkpoint, recompute the segment (recording dE/deps of the design cells),
+ * then run the adjoint step backwards over it.  Cost ~2 forward passes.
+ * Afterwards the handle is back at t = 0 with zero fields.  Synchronises. */
+lbm_em_status lbm_em_backward(lbm_em_handle h, double *grad_eps, int32_t where);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *lbm_em_last_error(void);
 

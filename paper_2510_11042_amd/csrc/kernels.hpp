@@ -113,6 +113,11 @@ struct StepArgs {
     int64_t win0, winlen;
     double *acc;                // (nnodes + 1) x 6 x (re, im)
     int tiles_x, tiles_y;       // tile grid of the launch (3-D: per z slab)
+    // inverse design: record d = dE/deps (at fixed pulled populations) for
+    // the cells of the design rectangle [dlo, dhi] into hist[t - hist_t0]
+    T *hist;
+    int dlo[2], dhi[2];
+    int64_t hist_t0;
 };
 
 template <typename T>
@@ -293,6 +298,18 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, int64_t t, int x, int
         if (POL == TM) { E[2] = F[0]; H[0] = F[1]; H[1] = F[2]; }
         else { E[0] = F[0]; E[1] = F[1]; H[2] = F[2]; }
         dft_accumulate(a, t, 2, x, y, 0, E, H);
+    }
+    if (a.hist && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
+        // E = (sum of the E-carrying populations + (6 eps - 4) z-pair)/eps,
+        // so dE/deps = (6 zpair - E)/eps at fixed populations
+        const int64_t dw = a.dhi[0] - a.dlo[0] + 1, dh = a.dhi[1] - a.dlo[1] + 1;
+        const int64_t cell = (int64_t)(y - a.dlo[1]) * dw + (x - a.dlo[0]);
+        T *h = a.hist + (t - a.hist_t0) * dw * dh * (POL == TM ? 1 : 2);
+        if (POL == TM) h[cell] = (T(6) * f[8] - F[0]) * inv_eps;
+        else {
+            h[2 * cell] = (T(6) * f[8] - F[0]) * inv_eps;
+            h[2 * cell + 1] = (T(6) * f[9] - F[1]) * inv_eps;
+        }
     }
     T q[11];
     equilibrium2d<T, POL>(F, T(2), q);
@@ -579,6 +596,219 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
 #pragma unroll
                 for (int i = 0; i < 27; ++i) d[i * P + base + x0 + j] = v[i][j];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the 2-D step (inverse design).
+//
+// Forward, per step t:  s(t) = Pi x(t) (pull with the open-boundary clamp),
+// F(t) = L s(t) (fields), x(t+1) = K s(t) + source, K = (1 - sigma)(2 Q L - I)
+// (Q: fields -> equilibria).  For an objective J(F) the adjoint
+// mu(t) = dJ/ds(t) obeys  mu(t) = K^T lambda(t+1) + L^T dJ/dF(t),
+// lambda(t) = Pi^T mu(t), and  dJ/deps = sum_t lambda(t+1) . (dK/deps) s(t).
+// The buffer holds mu; one adjoint launch per step reverse-pulls mu(t+1)
+// (population i from r + c_i; a face node whose forward pull was clamped
+// also keeps its own value), accumulates the gradient, applies K^T and adds
+// the objective's source at contour nodes inside the DFT window.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdjArgs {
+    int nx, ny;
+    int64_t sy, plane;
+    int W[2];
+    T sigma_max;
+    const T *__restrict__ src;   // mu(t+1)
+    T *__restrict__ dst;         // mu(t)
+    const T *__restrict__ eps;
+    int64_t t;
+    // objective source: G (complex, per contour node and component c of
+    // Ex..Hz) so that dJ/dF_c(t) = 2 Re(G_c (2/winlen) e^{-j omega t})
+    Box box;
+    int64_t win0, winlen;
+    int period;
+    const double *G;             // (nnodes) x 6 x (re, im)
+    // gradient
+    const T *hist;               // d for this step, design rectangle
+    double *grad;                // design rectangle, accumulated
+    int dlo[2], dhi[2];
+};
+
+// L^T u for the 11 reduced scalars (u: TM (Ez, Hx, Hy), TE (Ex, Ey, Hz)).
+template <typename T, int POL>
+__device__ inline void fields2d_T(const T u[3], T eps, T inv_eps, T o[11]) {
+    const T re = (T(6) * eps - T(4)) * inv_eps;
+    if (POL == TM) {
+        const T e = u[0] * inv_eps;
+        o[0] = e - u[2]; o[1] = e + u[2]; o[2] = e + u[1]; o[3] = e - u[1];
+        o[4] = o[5] = u[1];
+        o[6] = o[7] = u[2];
+        o[8] = re * u[0]; o[9] = T(2) * u[1]; o[10] = T(2) * u[2];
+    } else {
+        const T ex = u[0] * inv_eps, ey = u[1] * inv_eps;
+        o[0] = ex; o[1] = ex; o[2] = ex - u[2]; o[3] = ex + u[2];
+        o[4] = ey + u[2]; o[5] = ey - u[2]; o[6] = ey; o[7] = ey;
+        o[8] = re * u[0]; o[9] = re * u[1]; o[10] = T(2) * u[2];
+    }
+}
+
+// Q^T l: the equilibrium map transposed (fields <- 11 scalars).
+template <typename T, int POL>
+__device__ inline void equilibrium2d_T(const T l[11], T u[3]) {
+    const T c = T(1) / T(6);
+    if (POL == TM) {
+        u[0] = c * (l[0] + l[1] + l[2] + l[3] + l[8]);
+        u[1] = c * (l[2] - l[3] + l[4] + l[5] + l[9]);
+        u[2] = c * (-l[0] + l[1] + l[6] + l[7] + l[10]);
+    } else {
+        u[0] = c * (l[0] + l[1] + l[2] + l[3] + l[8]);
+        u[1] = c * (l[4] + l[5] + l[6] + l[7] + l[9]);
+        u[2] = c * (-l[2] + l[3] + l[4] - l[5] + l[10]);
+    }
+}
+
+template <typename T, int POL>
+__global__ void __launch_bounds__(256) k_adjoint2d(AdjArgs<T> a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
+    const int64_t P = a.plane, row = (int64_t)y * a.sy, c = row + x;
+    const T *m = a.src;
+    T l[11];
+    // +x populations (forward pull from x-1): adjoint from x+1
+    {
+        const bool in = x + 1 < a.nx || a.W[0] == 0;
+        const int xs = x + 1 < a.nx ? x + 1 : 0;
+        const bool self = a.W[0] && x == 0;
+        for (int i : {0, 4}) l[i] = (in ? m[i * P + row + xs] : T(0)) + (self ? m[i * P + c] : T(0));
+    }
+    {   // -x populations: adjoint from x-1
+        const bool in = x > 0 || a.W[0] == 0;
+        const int xs = x > 0 ? x - 1 : a.nx - 1;
+        const bool self = a.W[0] && x == a.nx - 1;
+        for (int i : {1, 5}) l[i] = (in ? m[i * P + row + xs] : T(0)) + (self ? m[i * P + c] : T(0));
+    }
+    {   // +y populations: adjoint from y+1
+        const bool in = y + 1 < a.ny || a.W[1] == 0;
+        const int ys = y + 1 < a.ny ? y + 1 : 0;
+        const bool self = a.W[1] && y == 0;
+        for (int i : {2, 6}) l[i] = (in ? m[i * P + (int64_t)ys * a.sy + x] : T(0)) + (self ? m[i * P + c] : T(0));
+    }
+    {   // -y populations: adjoint from y-1
+        const bool in = y > 0 || a.W[1] == 0;
+        const int ys = y > 0 ? y - 1 : a.ny - 1;
+        const bool self = a.W[1] && y == a.ny - 1;
+        for (int i : {3, 7}) l[i] = (in ? m[i * P + (int64_t)ys * a.sy + x] : T(0)) + (self ? m[i * P + c] : T(0));
+    }
+    l[8] = m[8 * P + c];
+    l[9] = m[9 * P + c];
+    l[10] = m[10 * P + c];
+
+    const T eps = a.eps[c];
+    const T inv_eps = T(1) / eps;
+    T u[3];
+    equilibrium2d_T<T, POL>(l, u);
+    // gradient: lambda . dK/deps s = 2 (Q^T lambda)_E . dE/deps
+    if (a.hist && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
+        const int64_t dw = a.dhi[0] - a.dlo[0] + 1;
+        const int64_t cell = (int64_t)(y - a.dlo[1]) * dw + (x - a.dlo[0]);
+        double g;
+        if (POL == TM) g = 2.0 * (double)u[0] * (double)a.hist[cell];
+        else g = 2.0 * ((double)u[0] * (double)a.hist[2 * cell] + (double)u[1] * (double)a.hist[2 * cell + 1]);
+        a.grad[cell] += g;
+    }
+    // K^T lambda = (1 - sigma)(2 L^T Q^T lambda - lambda)
+    T o[11];
+    fields2d_T<T, POL>(u, eps, inv_eps, o);
+    const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max), sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max));
+#pragma unroll
+    for (int i = 0; i < 11; ++i) l[i] = (T(1) - sig) * (T(2) * o[i] - l[i]);
+    // objective source L^T dJ/dF at contour nodes inside the DFT window
+    if (a.G && a.t >= a.win0 && a.t < a.win0 + a.winlen && on_box(a.box, 2, x, y, 0)) {
+        const int64_t node = box_node_index(a.box, 2, x, y, 0);
+        const double ph = 2.0 * M_PI * (double)(a.t % a.period) / (double)a.period;
+        const double sc = 2.0 / (double)a.winlen;
+        const double cr = sc * cos(ph), ci = -sc * sin(ph);
+        const double *g = a.G + node * 12;
+        double dF[6];
+        for (int k = 0; k < 6; ++k) dF[k] = 2.0 * (g[2 * k] * cr - g[2 * k + 1] * ci);
+        T v[3];
+        if (POL == TM) { v[0] = (T)dF[2]; v[1] = (T)dF[3]; v[2] = (T)dF[4]; }
+        else { v[0] = (T)dF[0]; v[1] = (T)dF[1]; v[2] = (T)dF[5]; }
+        T q[11];
+        fields2d_T<T, POL>(v, eps, inv_eps, q);
+#pragma unroll
+        for (int i = 0; i < 11; ++i) l[i] += q[i];
+    }
+    T *d = a.dst;
+#pragma unroll
+    for (int i = 0; i < 11; ++i) d[i * P + c] = l[i];
+}
+
+// Objective weights for the adjoint source.  J = sum_a w_a kappa |P_a|^2
+// with P_a the complex far-field combination of angle a (k_ntff output,
+// scattered phasors); per unique contour node p and component c:
+//   G_{p,c} = sum_a w_a kappa conj(P_a) dP_a/dX_{p,c},
+// dP/dX from the same edge integrals as k_ntff (trapezoid weights, one
+// contribution per edge containing the node).  One thread per node.
+struct AdjWeightArgs {
+    Box box;
+    int pol;
+    double k, kappa;
+    double center[3], khat[3];
+    const double *theta;   // radians, relative to khat
+    const double *w;
+    const double *P;       // (n_angles) x 4 (P1 re, im, P2 re, im)
+    int n_angles;
+    int64_t nnodes;
+    double *G;             // (nnodes) x 6 x (re, im)
+};
+
+__global__ void k_adjoint_weights2d(AdjWeightArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.nnodes) return;
+    const Box &b = a.box;
+    // recover the node's coordinates from its unique index
+    const int64_t nbx = b.hi[0] - b.lo[0] + 1, nby = b.hi[1] - b.lo[1] + 1;
+    int x, y;
+    if (p < nbx) { x = b.lo[0] + (int)p; y = b.lo[1]; }
+    else if (p < 2 * nbx) { x = b.lo[0] + (int)(p - nbx); y = b.hi[1]; }
+    else if (p < 2 * nbx + nby - 2) { x = b.lo[0]; y = b.lo[1] + 1 + (int)(p - 2 * nbx); }
+    else { x = b.hi[0]; y = b.lo[1] + 1 + (int)(p - 2 * nbx - (nby - 2)); }
+    double G[12];
+    for (int k = 0; k < 12; ++k) G[k] = 0.0;
+    for (int seg = 0; seg < 4; ++seg) {
+        const int ax = seg / 2;
+        const int side = (seg & 1) ? 1 : -1;
+        const int pos = side < 0 ? b.lo[ax] : b.hi[ax];
+        const int xy[2] = {x, y};
+        if (xy[ax] != pos) continue;                 // node not on this edge
+        const int ua = 1 - ax;
+        const bool end = xy[ua] == b.lo[ua] || xy[ua] == b.hi[ua];
+        const double wn = end ? 0.5 : 1.0;
+        double n[2] = {0, 0};
+        n[ax] = side;
+        for (int ia = 0; ia < a.n_angles; ++ia) {
+            const double th = a.theta[ia];
+            const double ct = cos(th), st = sin(th);
+            const double r0 = ct * a.khat[0] - st * a.khat[1], r1 = ct * a.khat[1] + st * a.khat[0];
+            const double rp = r0 * ((double)x - a.center[0]) + r1 * ((double)y - a.center[1]);
+            double sn, cs;
+            sincos(a.k * rp, &sn, &cs);
+            // conj(P) * w * kappa * wn * e^{j k r.r'}
+            const double pr = a.P[4 * ia], pi = -a.P[4 * ia + 1];
+            const double sc = a.w[ia] * a.kappa * wn;
+            const double zr = sc * (pr * cs - pi * sn), zi = sc * (pr * sn + pi * cs);
+            const double rn = r0 * n[0] + r1 * n[1];
+            double coef[6] = {0, 0, 0, 0, 0, 0};   // dP/dX_c per unit phase factor
+            if (a.pol == TM) { coef[2] = -rn; coef[3] = -n[1]; coef[4] = n[0]; }
+            else { coef[0] = n[1]; coef[1] = -n[0]; coef[5] = -rn; }
+            for (int c = 0; c < 6; ++c) {
+                G[2 * c] += zr * coef[c];
+                G[2 * c + 1] += zi * coef[c];
+            }
+        }
+    }
+    for (int k = 0; k < 12; ++k) a.G[p * 12 + k] = G[k];
 }
 
 // ---------------------------------------------------------------------------

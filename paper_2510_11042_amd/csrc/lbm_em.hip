@@ -90,6 +90,17 @@ struct lbm_em {
     int64_t *t_dev = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // indexed by starting buffer parity
     int dev = 0;
+    // inverse design (adjoint)
+    bool adj_set = false;
+    lbm_em *adj_inc = nullptr;
+    std::vector<double> adj_theta, adj_w;           // radians from khat, weights
+    int dlo[2] = {0, 0}, dhi[2] = {0, 0};
+    int ck_every = 0, nck = 0, ck_k = 0;
+    int64_t adj_T = 0;
+    void *ck = nullptr;                              // nck checkpoints of the state
+    size_t ck_bytes = 0;
+    double *adj_P = nullptr;                         // far-field combinations at adj_theta
+    double adj_kappa = 0.0;
 };
 
 // A batch: several 2-D handles advanced by one persistent launch per step.
@@ -124,6 +135,8 @@ lbm_em *check_handle(lbm_em_handle h) {
 }
 
 void select_device(const lbm_em *h) { hip_check(hipSetDevice(h->dev), "hipSetDevice"); }
+
+void sync(const lbm_em *h) { hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize"); }
 
 template <typename T>
 StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
@@ -175,22 +188,30 @@ void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
 
 template <typename T>
 void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base,
-                   int64_t t_off, hipStream_t s, bool dft) {
+                   int64_t t_off, hipStream_t s, bool dft, void *hist, int64_t hist_t0) {
     StepArgs<T> a = make_args<T>(h, src, dst);
     a.t_base = t_base;
     a.t_off = t_off;
     if (!dft) a.dft_on = 0;
+    if (hist) {
+        a.hist = (T *)hist;
+        a.hist_t0 = hist_t0;
+        for (int k = 0; k < 2; ++k) {
+            a.dlo[k] = h->dlo[k];
+            a.dhi[k] = h->dhi[k];
+        }
+    }
     if (h->vx == 1) launch_step_vx<T, 1>(a, h, s);
     else if (h->vx == 2) launch_step_vx<T, 2>(a, h, s);
     else if constexpr (sizeof(T) == 4) launch_step_vx<T, 4>(a, h, s);
 }
 
 void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
-                 bool dft = true) {
+                 bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
-    if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s, dft);
-    else launch_step_t<double>(h, src, dst, t_base, t_off, s, dft);
+    if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
+    else launch_step_t<double>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
 }
 
 bool tile_ok(const lbm_em *h, int vx, int bx, int by) {
@@ -458,6 +479,109 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
     }
 }
 
+// Far-field combinations P (4 doubles per angle, device) for angles given
+// in radians; returns the incident amplitude used for normalisation.
+double farfield_P(lbm_em *h, lbm_em *inc, const double *theta_rad, const double *phi_rad, int n, double *d_P) {
+    std::vector<double> ang(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        ang[i] = theta_rad[i];
+        ang[n + i] = phi_rad ? phi_rad[i] : 0.0;
+    }
+    double *d_ang = nullptr;
+    hip_check(hipMalloc(&d_ang, ang.size() * sizeof(double)), "hipMalloc");
+    hip_check(hipMemcpyAsync(d_ang, ang.data(), ang.size() * sizeof(double), hipMemcpyHostToDevice, h->stream), "H2D");
+    NtffArgs a{};
+    a.acc = h->acc;
+    a.acc_inc = inc ? inc->acc : nullptr;
+    a.box = h->box;
+    a.dim = h->dim;
+    a.pol = h->cfg.pol;
+    a.k = 2.0 * M_PI / h->pw.lambda;
+    const auto &c = h->cfg;
+    a.center[0] = (c.nx - 1) / 2.0;
+    a.center[1] = (c.ny - 1) / 2.0;
+    a.center[2] = h->dim == 3 ? (c.nz - 1) / 2.0 : 0.0;
+    for (int k = 0; k < 3; ++k) {
+        a.khat[k] = h->pw.khat[k];
+        a.ehat[k] = h->pw.ehat[k];
+        a.bhat[k] = h->hhat[k];
+    }
+    a.theta = d_ang;
+    a.phi = d_ang + n;
+    a.out = d_P;
+    hipLaunchKernelGGL(k_ntff, dim3(n), dim3(256), 0, h->stream, a);
+    hip_check(hipGetLastError(), "k_ntff");
+    double amp = h->pw.amplitude;
+    if (inc) {
+        double pr[12];
+        hip_check(hipMemcpyAsync(pr, inc->acc + inc->nnodes * 12, sizeof pr, hipMemcpyDeviceToHost, h->stream), "D2H");
+        sync(h);
+        const double *v = h->cfg.pol == LBM_EM_TE ? pr + 6 : pr;
+        const double *u = h->cfg.pol == LBM_EM_TE ? h->hhat : h->pw.ehat;
+        double re = 0, im = 0;
+        for (int k = 0; k < 3; ++k) {
+            re += u[k] * v[2 * k];
+            im += u[k] * v[2 * k + 1];
+        }
+        amp = std::sqrt(re * re + im * im);
+    }
+    sync(h);
+    hfree(d_ang);
+    return amp;
+}
+
+void check_incident(const lbm_em *h, const lbm_em *inc) {
+    if (inc->cfg.nx != h->cfg.nx || inc->cfg.ny != h->cfg.ny || inc->cfg.nz != h->cfg.nz ||
+        inc->cfg.pol != h->cfg.pol || !inc->dft_set)
+        fail(LBM_EM_EINVAL, "incident handle must match grid, polarisation and contour");
+    for (int a = 0; a < 3; ++a)
+        if (inc->box.lo[a] != h->box.lo[a] || inc->box.hi[a] != h->box.hi[a])
+            fail(LBM_EM_EINVAL, "incident handle has a different contour");
+    if (inc->t < inc->win0 + inc->winlen) fail(LBM_EM_ESTATE, "incident DFT window not completed");
+}
+
+void reset_state(lbm_em *h) {
+    const size_t bytes = (size_t)h->plane * h->nplanes * h->elem;
+    hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset state");
+    hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset state");
+    if (h->acc)
+        hip_check(hipMemsetAsync(h->acc, 0, (size_t)(h->nnodes + 1) * 12 * sizeof(double), h->stream), "hipMemset dft");
+    h->t = 0;
+    h->cur = 0;
+}
+
+template <typename T>
+void launch_adjoint(const lbm_em *h, const void *src, void *dst, int64_t t, const void *hist, double *grad,
+                    const double *G) {
+    AdjArgs<T> a{};
+    a.nx = h->cfg.nx;
+    a.ny = h->cfg.ny;
+    a.sy = h->sy;
+    a.plane = h->plane;
+    a.W[0] = h->cfg.absorb[0];
+    a.W[1] = h->cfg.absorb[1];
+    a.sigma_max = (T)h->cfg.sigma_max;
+    a.src = (const T *)src;
+    a.dst = (T *)dst;
+    a.eps = (const T *)h->eps;
+    a.t = t;
+    a.box = h->box;
+    a.win0 = h->win0;
+    a.winlen = h->winlen;
+    a.period = h->period;
+    a.G = G;
+    a.hist = (const T *)hist;
+    a.grad = grad;
+    for (int k = 0; k < 2; ++k) {
+        a.dlo[k] = h->dlo[k];
+        a.dhi[k] = h->dhi[k];
+    }
+    dim3 block(64, 4, 1);
+    dim3 grid((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, 1);
+    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_adjoint2d<T, TM>), grid, block, 0, h->stream, a);
+    else hipLaunchKernelGGL((k_adjoint2d<T, TE>), grid, block, 0, h->stream, a);
+}
+
 void free_handle(lbm_em *h) {
     if (!h) return;
     (void)hipSetDevice(h->dev);
@@ -469,6 +593,8 @@ void free_handle(lbm_em *h) {
     hfree(h->eps);
     hfree(h->acc);
     hfree(h->t_dev);
+    hfree(h->ck);
+    hfree(h->adj_P);
     delete h;
 }
 
@@ -478,7 +604,6 @@ void check_unit(const double v[3], const char *name) {
         fail(LBM_EM_EINVAL, std::string(name) + " must be a unit vector");
 }
 
-void sync(const lbm_em *h) { hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize"); }
 
 }  // namespace
 
@@ -819,14 +944,7 @@ lbm_em_status lbm_em_reset(lbm_em_handle hh) {
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         select_device(h);
-        const size_t bytes = (size_t)h->plane * h->nplanes * h->elem;
-        hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset state");
-        hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset state");
-        if (h->acc)
-            hip_check(hipMemsetAsync(h->acc, 0, (size_t)(h->nnodes + 1) * 12 * sizeof(double), h->stream),
-                      "hipMemset dft");
-        h->t = 0;
-        h->cur = 0;
+        reset_state(h);
     });
 }
 
@@ -910,71 +1028,22 @@ lbm_em_status lbm_em_farfield(lbm_em_handle hh, lbm_em_handle inc, const double 
         if (h->dim == 3 && !phi_deg) fail(LBM_EM_EINVAL, "3-D needs phi");
         if (!h->dft_set) fail(LBM_EM_ESTATE, "no contour set");
         if (h->t < h->win0 + h->winlen) fail(LBM_EM_ESTATE, "DFT window not completed");
-        if (inc) {
-            if (inc->cfg.nx != h->cfg.nx || inc->cfg.ny != h->cfg.ny || inc->cfg.nz != h->cfg.nz ||
-                inc->cfg.pol != h->cfg.pol || !inc->dft_set)
-                fail(LBM_EM_EINVAL, "incident handle must match grid, polarisation and contour");
-            for (int a = 0; a < 3; ++a)
-                if (inc->box.lo[a] != h->box.lo[a] || inc->box.hi[a] != h->box.hi[a])
-                    fail(LBM_EM_EINVAL, "incident handle has a different contour");
-            if (inc->t < inc->win0 + inc->winlen) fail(LBM_EM_ESTATE, "incident DFT window not completed");
-        }
+        if (inc) check_incident(h, inc);
         select_device(h);
         if (inc) sync(inc);
-        std::vector<double> ang(2 * (size_t)n_angles);
+        std::vector<double> th(n_angles), ph(n_angles);
         for (int i = 0; i < n_angles; ++i) {
-            ang[i] = theta_deg[i] * M_PI / 180.0;
-            ang[n_angles + i] = phi_deg ? phi_deg[i] * M_PI / 180.0 : 0.0;
+            th[i] = theta_deg[i] * M_PI / 180.0;
+            ph[i] = phi_deg ? phi_deg[i] * M_PI / 180.0 : 0.0;
         }
-        double *d_ang = nullptr, *d_out = nullptr;
-        hip_check(hipMalloc(&d_ang, ang.size() * sizeof(double)), "hipMalloc");
+        double *d_out = nullptr;
         hip_check(hipMalloc(&d_out, (size_t)n_angles * 4 * sizeof(double)), "hipMalloc");
-        hip_check(hipMemcpyAsync(d_ang, ang.data(), ang.size() * sizeof(double), hipMemcpyHostToDevice,
-                                 h->stream), "H2D");
-        NtffArgs a{};
-        a.acc = h->acc;
-        a.acc_inc = inc ? inc->acc : nullptr;
-        a.box = h->box;
-        a.dim = h->dim;
-        a.pol = h->cfg.pol;
-        a.k = 2.0 * M_PI / h->pw.lambda;
-        const auto &c = h->cfg;
-        a.center[0] = (c.nx - 1) / 2.0;
-        a.center[1] = (c.ny - 1) / 2.0;
-        a.center[2] = h->dim == 3 ? (c.nz - 1) / 2.0 : 0.0;
-        for (int k = 0; k < 3; ++k) {
-            a.khat[k] = h->pw.khat[k];
-            a.ehat[k] = h->pw.ehat[k];
-            a.bhat[k] = h->hhat[k];
-        }
-        a.theta = d_ang;
-        a.phi = d_ang + n_angles;
-        a.out = d_out;
-        hipLaunchKernelGGL(k_ntff, dim3(n_angles), dim3(256), 0, h->stream, a);
-        hip_check(hipGetLastError(), "k_ntff");
+        const double amp = farfield_P(h, inc, th.data(), ph.data(), n_angles, d_out);
         std::vector<double> P((size_t)n_angles * 4);
-        hip_check(hipMemcpyAsync(P.data(), d_out, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream),
-                  "D2H");
-        // incident amplitude from the probe node
-        double amp = h->pw.amplitude;
-        if (inc) {
-            double pr[12];
-            hip_check(hipMemcpyAsync(pr, inc->acc + inc->nnodes * 12, sizeof pr, hipMemcpyDeviceToHost,
-                                     h->stream), "D2H");
-            sync(h);
-            const double *v = h->cfg.pol == LBM_EM_TE ? pr + 6 : pr;
-            const double *u = h->cfg.pol == LBM_EM_TE ? h->hhat : h->pw.ehat;
-            double re = 0, im = 0;
-            for (int k = 0; k < 3; ++k) {
-                re += u[k] * v[2 * k];
-                im += u[k] * v[2 * k + 1];
-            }
-            amp = std::sqrt(re * re + im * im);
-        }
+        hip_check(hipMemcpyAsync(P.data(), d_out, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");
         sync(h);
-        hfree(d_ang);
         hfree(d_out);
-        const double k = a.k;
+        const double k = 2.0 * M_PI / h->pw.lambda;
         const double kappa = h->dim == 2 ? k * k / (8.0 * M_PI) : k * k * k * k / (16.0 * M_PI * M_PI);
         for (int i = 0; i < n_angles; ++i) {
             double p = P[4 * i] * P[4 * i] + P[4 * i + 1] * P[4 * i + 1] + P[4 * i + 2] * P[4 * i + 2] +
@@ -984,4 +1053,173 @@ lbm_em_status lbm_em_farfield(lbm_em_handle hh, lbm_em_handle inc, const double 
     });
 }
 
+lbm_em_status lbm_em_adjoint_setup(lbm_em_handle hh, lbm_em_handle inc, const double *theta_deg,
+                                   const double *weight, int32_t n_angles, const int32_t dlo[2],
+                                   const int32_t dhi[2], int32_t checkpoint_every) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "the adjoint supports 2-D (TM/TE) handles");
+        if (!inc) fail(LBM_EM_EINVAL, "the objective needs the incident (eps = 1) companion handle");
+        if (!theta_deg || n_angles < 1) fail(LBM_EM_EINVAL, "need at least one angle");
+        if (!dlo || !dhi) fail(LBM_EM_EINVAL, "null design rectangle");
+        if (!h->dft_set || !h->src_on) fail(LBM_EM_ESTATE, "set the source and contour first");
+        if (checkpoint_every < 0) fail(LBM_EM_EINVAL, "checkpoint_every must be >= 0");
+        const int n[2] = {h->cfg.nx, h->cfg.ny};
+        for (int a = 0; a < 2; ++a) {
+            if (dlo[a] > dhi[a] || dlo[a] < 0 || dhi[a] >= n[a]) fail(LBM_EM_EINVAL, "design rectangle outside the grid");
+            if (dlo[a] <= h->box.lo[a] || dhi[a] >= h->box.hi[a])
+                fail(LBM_EM_EINVAL, "design rectangle must lie strictly inside the contour box");
+            const int W = h->cfg.absorb[a];
+            if (W && (dlo[a] < W || dhi[a] >= n[a] - W)) fail(LBM_EM_EINVAL, "design rectangle overlaps the layer");
+        }
+        h->adj_inc = check_handle(inc);
+        h->adj_theta.assign(n_angles, 0.0);
+        h->adj_w.assign(n_angles, 1.0);
+        for (int i = 0; i < n_angles; ++i) {
+            h->adj_theta[i] = theta_deg[i] * M_PI / 180.0;
+            if (weight) h->adj_w[i] = weight[i];
+        }
+        for (int a = 0; a < 2; ++a) {
+            h->dlo[a] = dlo[a];
+            h->dhi[a] = dhi[a];
+        }
+        h->ck_every = checkpoint_every;
+        h->adj_T = 0;
+        h->adj_set = true;
+    });
+}
+
+lbm_em_status lbm_em_forward_checkpointed(lbm_em_handle hh, int64_t n, double *J_out) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!h->adj_set) fail(LBM_EM_ESTATE, "call lbm_em_adjoint_setup first");
+        if (!J_out) fail(LBM_EM_EINVAL, "null J_out");
+        if (n < h->win0 + h->winlen) fail(LBM_EM_EINVAL, "n must cover the DFT window");
+        check_incident(h, h->adj_inc);
+        select_device(h);
+        reset_state(h);
+        const int K = h->ck_every > 0 ? h->ck_every : (int)std::ceil(std::sqrt((double)n));
+        const int nck = (int)((n + K - 1) / K);
+        const size_t sb = (size_t)h->plane * h->nplanes * h->elem;
+        if (h->ck_bytes < sb * nck) {
+            hfree(h->ck);
+            h->ck = nullptr;
+            h->ck_bytes = 0;
+            hip_check(hipMalloc(&h->ck, sb * nck), "hipMalloc checkpoints");
+            h->ck_bytes = sb * nck;
+        }
+        h->nck = nck;
+        h->ck_k = K;
+        for (int k = 0; k < nck; ++k) {
+            hip_check(hipMemcpyAsync((char *)h->ck + sb * k, h->buf[h->cur], sb, hipMemcpyDeviceToDevice, h->stream),
+                      "checkpoint");
+            do_steps(h, std::min<int64_t>(K, n - (int64_t)k * K));
+        }
+        const int na = (int)h->adj_theta.size();
+        hfree(h->adj_P);
+        h->adj_P = nullptr;
+        hip_check(hipMalloc(&h->adj_P, (size_t)na * 4 * sizeof(double)), "hipMalloc");
+        const double amp = farfield_P(h, h->adj_inc, h->adj_theta.data(), nullptr, na, h->adj_P);
+        std::vector<double> P((size_t)na * 4);
+        hip_check(hipMemcpyAsync(P.data(), h->adj_P, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");
+        sync(h);
+        const double k = 2.0 * M_PI / h->pw.lambda;
+        h->adj_kappa = k * k / (8.0 * M_PI) / (amp * amp);
+        double J = 0.0;
+        for (int i = 0; i < na; ++i)
+            J += h->adj_w[i] * h->adj_kappa * (P[4 * i] * P[4 * i] + P[4 * i + 1] * P[4 * i + 1]);
+        h->adj_T = n;
+        *J_out = J;
+    });
+}
+
+lbm_em_status lbm_em_backward(lbm_em_handle hh, double *grad_eps, int32_t where) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!h->adj_set || h->adj_T == 0 || h->t != h->adj_T)
+            fail(LBM_EM_ESTATE, "call lbm_em_forward_checkpointed (and nothing else) first");
+        if (!grad_eps) fail(LBM_EM_EINVAL, "null gradient output");
+        if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
+        select_device(h);
+        const int64_t T = h->adj_T;
+        const int K = h->ck_k, nck = h->nck;
+        const int ncomp = h->cfg.pol == LBM_EM_TM ? 1 : 2;
+        const int64_t dcells = (int64_t)(h->dhi[0] - h->dlo[0] + 1) * (h->dhi[1] - h->dlo[1] + 1);
+        const size_t sb = (size_t)h->plane * h->nplanes * h->elem;
+        void *abuf[2] = {nullptr, nullptr};
+        void *hist = nullptr;
+        double *grad = nullptr, *G = nullptr;
+        try {
+            hip_check(hipMalloc(&abuf[0], sb), "hipMalloc adjoint");
+            hip_check(hipMalloc(&abuf[1], sb), "hipMalloc adjoint");
+            hip_check(hipMalloc(&hist, (size_t)K * dcells * ncomp * h->elem), "hipMalloc history");
+            hip_check(hipMalloc(&grad, dcells * sizeof(double)), "hipMalloc gradient");
+            hip_check(hipMalloc(&G, (size_t)h->nnodes * 12 * sizeof(double)), "hipMalloc weights");
+            hip_check(hipMemsetAsync(abuf[0], 0, sb, h->stream), "hipMemset");
+            hip_check(hipMemsetAsync(abuf[1], 0, sb, h->stream), "hipMemset");
+            hip_check(hipMemsetAsync(grad, 0, dcells * sizeof(double), h->stream), "hipMemset");
+            // adjoint source weights from the forward far field
+            const int na = (int)h->adj_theta.size();
+            double *d_tw = nullptr;
+            std::vector<double> tw(2 * (size_t)na);
+            for (int i = 0; i < na; ++i) {
+                tw[i] = h->adj_theta[i];
+                tw[na + i] = h->adj_w[i];
+            }
+            hip_check(hipMalloc(&d_tw, tw.size() * sizeof(double)), "hipMalloc");
+            hip_check(hipMemcpyAsync(d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice, h->stream), "H2D");
+            AdjWeightArgs wa{};
+            wa.box = h->box;
+            wa.pol = h->cfg.pol;
+            wa.k = 2.0 * M_PI / h->pw.lambda;
+            wa.kappa = h->adj_kappa;
+            wa.center[0] = (h->cfg.nx - 1) / 2.0;
+            wa.center[1] = (h->cfg.ny - 1) / 2.0;
+            for (int k = 0; k < 3; ++k) wa.khat[k] = h->pw.khat[k];
+            wa.theta = d_tw;
+            wa.w = d_tw + na;
+            wa.P = h->adj_P;
+            wa.n_angles = na;
+            wa.nnodes = h->nnodes;
+            wa.G = G;
+            hipLaunchKernelGGL(k_adjoint_weights2d, dim3((unsigned)((h->nnodes + 255) / 256)), dim3(256), 0, h->stream, wa);
+            hip_check(hipGetLastError(), "k_adjoint_weights2d");
+            int ap = 0;
+            for (int k = nck - 1; k >= 0; --k) {
+                const int64_t t0 = (int64_t)k * K, t1 = std::min<int64_t>(t0 + K, T);
+                // recompute the segment from its checkpoint, recording dE/deps
+                hip_check(hipMemcpyAsync(h->buf[0], (char *)h->ck + sb * k, sb, hipMemcpyDeviceToDevice, h->stream),
+                          "restore");
+                int cur = 0;
+                for (int64_t t = t0; t < t1; ++t) {
+                    launch_step(h, cur, nullptr, t, h->stream, false, hist, t0);
+                    hip_check(hipGetLastError(), "recompute");
+                    cur ^= 1;
+                }
+                // reverse sweep over the segment
+                for (int64_t t = t1 - 1; t >= t0; --t) {
+                    const char *hs = (const char *)hist + (size_t)(t - t0) * dcells * ncomp * h->elem;
+                    if (h->elem == 4) launch_adjoint<float>(h, abuf[ap], abuf[ap ^ 1], t, hs, grad, G);
+                    else launch_adjoint<double>(h, abuf[ap], abuf[ap ^ 1], t, hs, grad, G);
+                    hip_check(hipGetLastError(), "adjoint step");
+                    ap ^= 1;
+                }
+            }
+            hip_check(hipMemcpyAsync(grad_eps, grad, dcells * sizeof(double),
+                                     where == LBM_EM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream),
+                      "gradient copy");
+            sync(h);
+            hfree(d_tw);
+        } catch (...) {
+            hfree(abuf[0]); hfree(abuf[1]); hfree(hist); hfree(grad); hfree(G);
+            throw;
+        }
+        hfree(abuf[0]); hfree(abuf[1]); hfree(hist); hfree(grad); hfree(G);
+        // the recompute used the state buffers: start over
+        reset_state(h);
+        h->adj_T = 0;
+    });
+}
+
 }  // extern "C"
+

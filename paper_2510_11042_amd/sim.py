@@ -181,6 +181,39 @@ class Simulation:
         X = out[:, 0::2] + 1j * out[:, 1::2]
         return X[:-1], X[-1]
 
+    # -- inverse design ----------------------------------------------------
+    def adjoint_setup(self, incident, theta_deg, dlo, dhi, weights=None, checkpoint_every=0):
+        """Objective J = sum_a w_a |S(theta_a)|^2 against `incident`, design
+        rectangle [dlo, dhi] (inclusive cell coordinates (x, y))."""
+        th = np.ascontiguousarray(theta_deg, dtype=np.float64).ravel()
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64).ravel()
+        lo = (C.c_int32 * 2)(*dlo)
+        hi = (C.c_int32 * 2)(*dhi)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        L.check(L.lib().lbm_em_adjoint_setup(self._h, incident.handle, dp(th), dp(w) if w is not None else None,
+                                             th.size, lo, hi, int(checkpoint_every)))
+        self._design = (tuple(dlo), tuple(dhi))
+        self._incident = incident
+
+    def forward_checkpointed(self, n):
+        J = C.c_double()
+        L.check(L.lib().lbm_em_forward_checkpointed(self._h, int(n), C.byref(J)))
+        return J.value
+
+    def backward(self, device=False):
+        """dJ/deps over the design rectangle, shape (ny_d, nx_d), float64."""
+        (x0, y0), (x1, y1) = self._design
+        shape = (y1 - y0 + 1, x1 - x0 + 1)
+        if device:
+            import torch
+
+            g = torch.empty(shape, dtype=torch.float64, device="cuda")
+            L.check(L.lib().lbm_em_backward(self._h, C.c_void_p(g.data_ptr()), L.DEVICE))
+            return g
+        g = np.empty(shape)
+        L.check(L.lib().lbm_em_backward(self._h, g.ctypes.data_as(C.c_void_p), L.HOST))
+        return g
+
     def farfield(self, theta_deg, phi_deg=None, incident=None):
         """|S|^2 at angles measured from the incidence direction (2-D: in
         the plane; 3-D: phi about khat from ehat)."""
@@ -247,3 +280,32 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def far_field_objective():
+    """torch.autograd.Function computing J(eps_design) = sum_a w_a |S(theta_a)|^2
+    for a Simulation prepared with adjoint_setup; the gradient comes from the
+    library's discrete adjoint (lbm_em_backward)."""
+    import torch
+
+    class FarFieldIntensity(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, eps_design, sim, eps_full, steps):
+            (x0, y0), (x1, y1) = sim._design
+            full = eps_full.detach().clone().to(torch.float64)
+            full.view(-1, full.shape[-2], full.shape[-1])[0, y0:y1 + 1, x0:x1 + 1] = eps_design.detach().to(
+                torch.float64)
+            sim.set_permittivity(full)
+            J = sim.forward_checkpointed(steps)
+            ctx.sim = sim
+            ctx.dev = eps_design.device
+            ctx.dtype = eps_design.dtype
+            return torch.tensor(J, dtype=torch.float64, device=eps_design.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g = ctx.sim.backward(device=ctx.dev.type == "cuda")
+            g = torch.as_tensor(g, device=ctx.dev, dtype=torch.float64) * gJ
+            return g.to(ctx.dtype), None, None, None
+
+    return FarFieldIntensity

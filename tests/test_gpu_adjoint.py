@@ -1,0 +1,146 @@
+"""Inverse design on the GPU: the library's discrete adjoint against the
+FP64 oracle adjoint, against central finite differences, and the
+checkpoint spacing (recompute must be bit-identical)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_11042_amd as P
+
+    return P
+
+
+def _tiny_case():
+    n = 40
+    case = W.cylinder_case(2.25, "TM", n=n, a=4.0, lam=8.0, W=8, steps=260, half=9.5)
+    rng = np.random.default_rng(7)
+    eps = np.ones((1, n, n))
+    eps[0, 16:24, 16:24] = rng.uniform(1.0, 4.0, (8, 8))
+    case.eps = eps
+    return case
+
+
+def _pair(P, case, prec, ramp, eps=None, theta=None, design=None, ck=0):
+    kh, eh = W.plane_wave_2d(case.theta_deg, case.pol)
+    out = []
+    for e in (np.ones_like(case.eps), case.eps if eps is None else eps):
+        s = P.Simulation(case.nx, case.ny, 1, pol=case.pol, precision=prec, absorb=case.absorb,
+                         sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(e)
+        s.set_source(case.lam, kh, eh, 1.0, ramp)
+        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+        out.append(s)
+    inc, tot = out
+    inc.step(case.steps)
+    tot.adjoint_setup(inc, theta, design[0], design[1], checkpoint_every=ck)
+    return inc, tot
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_adjoint_matches_oracle_adjoint(P, pol):
+    from oracle.adjoint import FarFieldObjective
+
+    case = _tiny_case()
+    case.pol = pol
+    th = np.arange(10.0, 20.01, 0.5)
+    say("oracle adjoint", pol)
+    obj = FarFieldObjective(case, th, sigma_max=W.SIGMA_MAX, ramp_periods=1.0)
+    J_o, g_o = obj.value_and_gradient(case.eps)
+    g_o = g_o[0, 16:24, 16:24]
+    for prec, tol in (("fp64", 1e-9), ("fp32", 2e-3)):
+        inc, tot = _pair(P, case, prec, 1.0, theta=th, design=((16, 16), (23, 23)))
+        J = tot.forward_checkpointed(case.steps)
+        g = tot.backward()
+        jerr = abs(J - J_o) / J_o
+        gerr = np.abs(g - g_o).max() / np.abs(g_o).max()
+        say(pol, prec, "J", J, J_o, "rel", jerr, "grad err", gerr)
+        assert jerr <= tol and gerr <= tol
+
+
+def test_checkpoint_spacing_is_bit_identical(P):
+    case = _tiny_case()
+    th = np.arange(10.0, 20.01, 0.5)
+    grads = []
+    for ck in (1, 7, 0, 260):
+        inc, tot = _pair(P, case, "fp32", 1.0, theta=th, design=((16, 16), (23, 23)), ck=ck)
+        J = tot.forward_checkpointed(case.steps)
+        grads.append((J, tot.backward()))
+        say("checkpoint", ck, J)
+    for J, g in grads[1:]:
+        assert J == grads[0][0] and np.array_equal(g, grads[0][1])
+
+
+def test_autograd_function(P):
+    import torch
+
+    case = _tiny_case()
+    th = np.arange(10.0, 20.01, 0.5)
+    inc, tot = _pair(P, case, "fp64", 1.0, theta=th, design=((16, 16), (23, 23)))
+    F = P.far_field_objective()
+    full = torch.tensor(case.eps, dtype=torch.float64, device="cuda")
+    d = full[0, 16:24, 16:24].clone().requires_grad_(True)
+    J = F.apply(d, tot, full, case.steps)
+    J.backward()
+    inc2, tot2 = _pair(P, case, "fp64", 1.0, theta=th, design=((16, 16), (23, 23)))
+    J2 = tot2.forward_checkpointed(case.steps)
+    g2 = tot2.backward()
+    assert abs(J.item() - J2) <= 1e-14 * J2
+    assert np.allclose(d.grad.cpu().numpy(), g2, rtol=0, atol=1e-14 * np.abs(g2).max())
+
+
+def _fd(P, case, eps, th, design, cells, h, steps):
+    """Central differences of J with the FP64 library build."""
+    inc, tot = _pair(P, case, "fp64", W.RAMP_PERIODS, eps=eps, theta=th, design=design)
+    out = []
+    for (y, x) in cells:
+        vals = []
+        for sgn in (1, -1):
+            e = eps.copy()
+            e[0, y, x] += sgn * h
+            tot.set_permittivity(e)
+            vals.append(tot.forward_checkpointed(steps))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out)
+
+
+def test_design_gradient_vs_finite_differences_full_size(P):
+    """The inverse-design configuration at full size: 1024^2, lambda = 32,
+    TM, normal incidence, centred 128^2 design region with eps ~ U[1, 4]
+    (seed 11042), J = sum of |S|^2 over 10..20 degrees, 6000 steps with
+    sqrt(N) checkpoints; adjoint gradient (FP32 and FP64) against FP64
+    central differences (h = 1e-4) on 32 cells drawn with seed 2510."""
+    eps, (x0, y0) = W.design_region(1024, 128, seed=11042)
+    case = W.cylinder_case(1.0, "TM", n=1024, steps=6000, half=72.5)
+    case.eps = eps
+    th = np.arange(10.0, 20.01, 0.5)
+    design = ((x0, y0), (x0 + 127, y0 + 127))
+    rng = np.random.default_rng(2510)
+    cells = [(int(y0 + a), int(x0 + b)) for a, b in rng.integers(0, 128, (32, 2))]
+    say("full size fd", len(cells))
+    fd = _fd(P, case, eps, th, design, cells, 1e-4, case.steps)
+    scale = np.abs(fd).max()
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-3)):
+        inc, tot = _pair(P, case, prec, W.RAMP_PERIODS, eps=eps, theta=th, design=design)
+        J = tot.forward_checkpointed(case.steps)
+        g = tot.backward()
+        ga = np.array([g[y - y0, x - x0] for y, x in cells])
+        err = np.abs(ga - fd).max() / scale
+        say(prec, "J", J, "max |adj - fd| / max|fd|", err)
+        assert err <= tol
