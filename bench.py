@@ -70,7 +70,9 @@ def cylinder_workload(Simulation, W, lbm_steps):
 
 
 def run_workload(sims, lbm_steps, theta, torch, events):
-    """One benchmark step; appends (start, end) event pairs around stepping."""
+    """One benchmark step; appends (start, end) event pairs around stepping.
+    Runs too short for the wave to reach the scatterer (profiling) skip the
+    far field."""
     out = {}
     for pol, eps_in, s in sims:
         s.reset()
@@ -80,7 +82,7 @@ def run_workload(sims, lbm_steps, theta, torch, events):
         s.step(lbm_steps)
         e1.record()
         events.append((e0, e1, lbm_steps))
-    for pol in ("TM", "TE"):
+    for pol in ("TM", "TE") if lbm_steps >= 2000 else ():
         inc = [s for p, e, s in sims if p == pol and e == 1.0][0]
         for p, e, s in sims:
             if p == pol and e != 1.0:
@@ -109,6 +111,107 @@ def sphere_extra(Simulation, W, torch, steps=200):
     res["frac_of_hbm_peak"] = res["achieved_GBs"] / HBM_PEAK_GBS
     s.close()
     return res
+
+
+def batched_extra(P, W, torch, steps=6000):
+    """64 seeded uneven instances (circle/hexagon, eps, size, lambda, angle),
+    6000 steps: one Batch (persistent launch per step, graph replay) against
+    the same instances stepped one after another."""
+    cases = W.batch_cases(64, steps=steps)
+    sims = []
+    for c in cases:
+        kh, eh = W.plane_wave_2d(c.theta_deg, c.pol)
+        s = P.Simulation(c.nx, c.ny, 1, pol=c.pol, precision="fp32", absorb=c.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(c.eps)
+        s.set_source(c.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        s.set_ntff(c.box_lo, c.box_hi, *c.window)
+        sims.append(s)
+    cells = sum(c.nx * c.ny for c in cases)
+    for s in sims:
+        s.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.reset()
+        s.step(steps)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    b = P.Batch(sims)
+    for s in sims:
+        s.reset()
+    b.step(64)
+    for s in sims:
+        s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    res = {"workload": "64 seeded 2-D scatterers, sides 256-448, 6000 steps", "cells": cells,
+           "groups": b.groups, "MLUPS": cells * steps / t_batch / 1e6,
+           "single_instance_MLUPS": cells * steps / t_single / 1e6,
+           "algorithmic_GBs": cells * steps * BYTES_2D / t_batch / 1e9}
+    res["batched_over_single"] = res["MLUPS"] / res["single_instance_MLUPS"]
+    b.close()
+    for s in sims:
+        s.close()
+    return res
+
+
+def adjoint_extra(P, W, torch, steps=6000):
+    """Inverse design at 1024^2: J = sum |S|^2 over 10..20 degrees, 128^2
+    design region; cost of the checkpointed forward and of the backward
+    against a plain forward of the same length."""
+    import numpy as np
+
+    eps, (x0, y0) = W.design_region(1024, 128, seed=11042)
+    case = W.cylinder_case(1.0, "TM", n=1024, steps=steps, half=72.5)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    sims = []
+    for e in (np.ones_like(eps), eps):
+        s = P.Simulation(1024, 1024, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(e)
+        s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+        sims.append(s)
+    inc, tot = sims
+    inc.step(steps)
+    tot.adjoint_setup(inc, np.arange(10.0, 20.01, 0.5), (x0, y0), (x0 + 127, y0 + 127))
+    tot.forward_checkpointed(steps)
+    tot.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot.reset()
+    tot.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J = tot.forward_checkpointed(steps)
+    t_ck = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = tot.backward()
+    t_bwd = time.perf_counter() - t0
+    cells = 1024 * 1024
+    res = {"workload": "inverse design 1024^2, 128^2 design, 6000 steps, J = sum |S|^2 10..20 deg",
+           "J": J, "grad_norm": float(np.linalg.norm(g)), "forward_s": t_fwd, "forward_checkpointed_s": t_ck,
+           "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+           "gradient_MLUPS": cells * steps / (t_ck + t_bwd) / 1e6,
+           "checkpoints": int(np.ceil(steps / np.ceil(np.sqrt(steps))))}
+    for s in sims:
+        s.close()
+    return res
+
+
+def copy_ceiling(P):
+    """The library's plain 16-byte-per-thread copy of 2 x 2 GiB: a measured
+    bandwidth ceiling (read + written bytes)."""
+    import ctypes as C
+
+    from paper_2510_11042_amd import _lib
+
+    g = C.c_double()
+    _lib.check(_lib.lib().lbm_em_copy_bandwidth(2 ** 31, 10, C.byref(g)))
+    return g.value
 
 
 def cpu_baseline(Simulation, W, target_s=20.0):
@@ -156,6 +259,8 @@ def main():
     ap.add_argument("--lbm-steps", type=int, default=8000, help="time steps per solve (workload: 8000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extras", default="copy,sphere,batched,adjoint",
+                    help="comma list of extra measurements to run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -172,13 +277,16 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        # a plain copy kernel of known size: reads and writes 2^30 bytes
-        a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 2 ** 30, "copy_bytes_written": 2 ** 30, "launches": 3}))
+        # the library's plain copy kernel k_copy16 on 2^30 bytes (read and
+        # written once per launch), 1 warm-up + 3 timed launches
+        import ctypes as C
+
+        from paper_2510_11042_amd import _lib
+
+        g = C.c_double()
+        _lib.check(_lib.lib().lbm_em_copy_bandwidth(2 ** 30, 3, C.byref(g)))
+        print(json.dumps({"kernel": "k_copy16", "bytes_read_per_launch": 2 ** 30,
+                          "bytes_written_per_launch": 2 ** 30, "launches": 4, "GBs": g.value}))
         return 0
     theta = np.arange(0.0, 360.0, 0.5)
     sims = cylinder_workload(Simulation, W, args.lbm_steps)
@@ -220,7 +328,18 @@ def main():
     for k, S in res.items():
         assert np.all(np.isfinite(S)) and S.max() > 0, k
     if not args.no_extra:
-        line["extra"] = {"sphere_3d": sphere_extra(Simulation, W, torch)}
+        import paper_2510_11042_amd as P
+
+        want = set(args.extras.split(","))
+        line["extra"] = {}
+        if "copy" in want:
+            line["roofline"]["measured_copy_GBs"] = copy_ceiling(P)
+        if "sphere" in want:
+            line["extra"]["sphere_3d"] = sphere_extra(Simulation, W, torch)
+        if "batched" in want:
+            line["extra"]["batched"] = batched_extra(P, W, torch)
+        if "adjoint" in want:
+            line["extra"]["adjoint"] = adjoint_extra(P, W, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(Simulation, W)
     for _, _, s in sims:

@@ -192,7 +192,7 @@ lbm_em_status lbm_em_get_phasors(lbm_em_handle h, double *out, int32_t *n_nodes)
  * n_angles; out_S2 receives |S|^2 (2-D: k r |E_s|^2/|E_i|^2, Eq. S2D; 3-D:
  * k^2 r^2 |E_s|^2/|E_i|^2, Eq. S3D).  incident = NULL: no subtraction and
  * normalisation by the source amplitude.  ESTATE if the DFT window has not
- * been completed.  Synchronises. */
+ * been completed or the incident probe amplitude is zero.  Synchronises. */
 lbm_em_status lbm_em_farfield(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
                               const double *phi_deg, int32_t n_angles, double *out_S2);
 
@@ -225,6 +225,12 @@ lbm_em_status lbm_em_forward_checkpointed(lbm_em_handle h, int64_t n, double *J_
  * then run the adjoint step backwards over it.  Cost ~2 forward passes.
  * Afterwards the handle is back at t = 0 with zero fields.  Synchronises. */
 lbm_em_status lbm_em_backward(lbm_em_handle h, double *grad_eps, int32_t where);
+
+/* Measurement helper: bandwidth of a plain 16-byte-per-thread device copy
+ * of `bytes` (multiple of 16), averaged over `reps` launches on the null
+ * stream, counting bytes read + written.  Allocates and frees two buffers
+ * of `bytes`.  The measured ceiling the step kernels are compared with. */
+lbm_em_status lbm_em_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *lbm_em_last_error(void);

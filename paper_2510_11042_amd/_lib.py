@@ -22,7 +22,7 @@ EXPORTS = [
     "lbm_em_batch_set_grid", "lbm_em_batch_set_cache_budget", "lbm_em_batch_groups", "lbm_em_batch_destroy", "lbm_em_set_tile", "lbm_em_get_tile", "lbm_em_autotune",
     "lbm_em_reset", "lbm_em_time", "lbm_em_get_fields",
     "lbm_em_get_phasors", "lbm_em_farfield", "lbm_em_adjoint_setup", "lbm_em_forward_checkpointed",
-    "lbm_em_backward", "lbm_em_last_error",
+    "lbm_em_backward", "lbm_em_copy_bandwidth", "lbm_em_last_error",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]
         sig["lbm_em_forward_checkpointed"] = [H, C.c_int64, C.POINTER(C.c_double)]
         sig["lbm_em_backward"] = [H, C.c_void_p, C.c_int32]
+        sig["lbm_em_copy_bandwidth"] = [C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args

@@ -872,6 +872,13 @@ __global__ void k_fill(T *p, int64_t n, T v) {
     if (i < n) p[i] = v;
 }
 
+// Plain streaming copy, 16 bytes per thread (measured bandwidth ceiling and
+// counter calibration).
+__global__ void __launch_bounds__(256) k_copy16(const float4 *__restrict__ a, float4 *__restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
 // Element-wise equality check (autotuner): any mismatch sets *flag = 1.
 template <typename T>
 __global__ void k_compare(const T *a, const T *b, int64_t n, int *flag) {

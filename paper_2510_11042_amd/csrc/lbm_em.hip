@@ -1039,6 +1039,10 @@ lbm_em_status lbm_em_farfield(lbm_em_handle hh, lbm_em_handle inc, const double 
         double *d_out = nullptr;
         hip_check(hipMalloc(&d_out, (size_t)n_angles * 4 * sizeof(double)), "hipMalloc");
         const double amp = farfield_P(h, inc, th.data(), ph.data(), n_angles, d_out);
+        if (!(amp > 0.0)) {
+            hfree(d_out);
+            fail(LBM_EM_ESTATE, "incident amplitude at the probe node is zero (the wave has not arrived)");
+        }
         std::vector<double> P((size_t)n_angles * 4);
         hip_check(hipMemcpyAsync(P.data(), d_out, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");
         sync(h);
@@ -1120,6 +1124,7 @@ lbm_em_status lbm_em_forward_checkpointed(lbm_em_handle hh, int64_t n, double *J
         h->adj_P = nullptr;
         hip_check(hipMalloc(&h->adj_P, (size_t)na * 4 * sizeof(double)), "hipMalloc");
         const double amp = farfield_P(h, h->adj_inc, h->adj_theta.data(), nullptr, na, h->adj_P);
+        if (!(amp > 0.0)) fail(LBM_EM_ESTATE, "incident amplitude at the probe node is zero (the wave has not arrived)");
         std::vector<double> P((size_t)na * 4);
         hip_check(hipMemcpyAsync(P.data(), h->adj_P, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");
         sync(h);
@@ -1221,5 +1226,44 @@ lbm_em_status lbm_em_backward(lbm_em_handle hh, double *grad_eps, int32_t where)
     });
 }
 
+lbm_em_status lbm_em_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs) {
+    return guarded([&] {
+        if (bytes < 16 || bytes % 16 != 0 || reps < 1 || !gbs) fail(LBM_EM_EINVAL, "bytes must be a positive multiple of 16");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(LBM_EM_EDEVICE, "no HIP device");
+        void *a = nullptr, *b = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        try {
+            hip_check(hipMalloc(&a, bytes), "hipMalloc");
+            hip_check(hipMalloc(&b, bytes), "hipMalloc");
+            hip_check(hipMemset(a, 0, bytes), "hipMemset");
+            const int64_t n = bytes / 16;
+            const unsigned blocks = (unsigned)((n + 255) / 256);
+            hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(256), 0, nullptr, (const float4 *)a, (float4 *)b, n);
+            hip_check(hipEventCreate(&e0), "hipEventCreate");
+            hip_check(hipEventCreate(&e1), "hipEventCreate");
+            hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
+            for (int r = 0; r < reps; ++r)
+                hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(256), 0, nullptr, (const float4 *)a, (float4 *)b, n);
+            hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+        } catch (...) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            hfree(a);
+            hfree(b);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        hfree(a);
+        hfree(b);
+    });
+}
+
 }  // extern "C"
+
 
