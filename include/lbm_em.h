@@ -56,7 +56,7 @@ enum { LBM_EM_FP32 = 0, LBM_EM_FP64 = 1 };
 enum { LBM_EM_HOST = 0, LBM_EM_DEVICE = 1 };
 
 typedef struct {
-    int32_t nx, ny, nz;     /* cells; nz must be 1 for TM/TE                        */
+    int32_t nx, ny, nz;     /* cells (>= 1); nz must be 1 for TM/TE, >= 3 for 3-D     */
     int32_t pol;            /* LBM_EM_TM, LBM_EM_TE or LBM_EM_3D                     */
     int32_t precision;      /* LBM_EM_FP32 (storage and arithmetic) or LBM_EM_FP64   */
     int32_t absorb[3];      /* absorbing-layer width W per axis, 0 = periodic axis;
@@ -156,11 +156,22 @@ lbm_em_status lbm_em_batch_destroy(lbm_em_batch b);
 lbm_em_status lbm_em_set_tile(lbm_em_handle h, int32_t vx, int32_t bx, int32_t by);
 lbm_em_status lbm_em_get_tile(lbm_em_handle h, int32_t *vx, int32_t *bx, int32_t *by);
 
-/* Time every supported tile on this handle's grid (`launches` launches each,
- * reading the current state and writing the spare buffer with the DFT off,
- * so the simulation is not advanced), keep the fastest and verify that it
- * reproduces the one-cell-per-thread kernel bit for bit (EDEVICE if not).
- * *best_us (may be NULL) receives the winner's time per launch. */
+/* Time steps per launch of lbm_em_step: 1, or 2 for 2-D handles (two
+ * steps fused through LDS: the state is read and written once per two
+ * steps; bit-identical results; the 2-D default).  tile_x x tile_y is the
+ * two-step kernel's output tile, one of 64x16, 64x8, 64x4, 32x16, 32x8,
+ * 16x16 (0 x 0 keeps the current one).  EUNSUPPORTED for 2 on 3-D handles.
+ * get_fusion's tile outputs may be NULL. */
+lbm_em_status lbm_em_set_fusion(lbm_em_handle h, int32_t steps_per_launch, int32_t tile_x, int32_t tile_y);
+lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y);
+
+/* Time every supported launch shape on this handle's grid -- one step per
+ * launch with every tile, and (2-D) two steps per launch with every
+ * two-step tile -- `launches` launches each, reading the current state and
+ * writing the spare buffer with the DFT off, so the simulation is not
+ * advanced; keep the fastest per time step and verify that it reproduces
+ * one-cell-per-thread single steps bit for bit (EDEVICE if not).
+ * *best_us (may be NULL) receives the winner's time per step. */
 lbm_em_status lbm_em_autotune(lbm_em_handle h, int32_t launches, double *best_us);
 
 /* Restart from t = 0: zero the distributions and the DFT accumulators

@@ -75,6 +75,8 @@ struct lbm_em {
     int64_t t = 0;
     hipStream_t stream = nullptr;
     int vx = 1, bx = 128, by = 2;       // cells per thread along x, block shape
+    int fuse = 1;                       // time steps per launch (1, or 2 in 2-D)
+    int ftx = 64, fty = 16;             // output tile of the two-step kernel
     // source
     bool src_on = false;
     lbm_em_plane_wave pw{};
@@ -214,6 +216,43 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
     else launch_step_t<double>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
 }
 
+// Two steps in one launch (2-D): reads src, writes f*(t+1) to dst.
+template <typename T, int POL>
+void launch_step2_pol(const StepArgs<T> &a, int tx, int ty, hipStream_t s) {
+    dim3 grid((unsigned)((a.nx + tx - 1) / tx), (unsigned)((a.ny + ty - 1) / ty), 1);
+#define LBM_X2(TX, TY) \
+    if (tx == TX && ty == TY) { hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(256), 0, s, a); return; }
+    LBM_X2(64, 16) LBM_X2(64, 8) LBM_X2(64, 4) LBM_X2(32, 16) LBM_X2(32, 8) LBM_X2(16, 16)
+#undef LBM_X2
+    fail(LBM_EM_EINVAL, "unsupported two-step tile");
+}
+
+template <typename T>
+void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base, int64_t t_off,
+                    hipStream_t s, bool dft) {
+    StepArgs<T> a = make_args<T>(h, src, dst);
+    a.t_base = t_base;
+    a.t_off = t_off;
+    if (!dft) a.dft_on = 0;
+    if (h->cfg.pol == LBM_EM_TM) launch_step2_pol<T, TM>(a, h->ftx, h->fty, s);
+    else launch_step2_pol<T, TE>(a, h->ftx, h->fty, s);
+}
+
+void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
+                  bool dft = true) {
+    const void *src = h->buf[parity];
+    void *dst = h->buf[parity ^ 1];
+    if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft);
+    else launch_step2_t<double>(h, src, dst, t_base, t_off, s, dft);
+}
+
+bool fused_tile_ok(int tx, int ty) {
+    static const int ok[][2] = {{64, 16}, {64, 8}, {64, 4}, {32, 16}, {32, 8}, {16, 16}};
+    for (auto &o : ok)
+        if (o[0] == tx && o[1] == ty) return true;
+    return false;
+}
+
 bool tile_ok(const lbm_em *h, int vx, int bx, int by) {
     const bool vx_ok = vx == 1 || vx == 2 || (vx == 4 && h->cfg.precision == LBM_EM_FP32);
     const int th = bx * by;
@@ -240,9 +279,16 @@ hipGraphExec_t build_graph(lbm_em *h, int p) {
         hip_check(e, "hipStreamBeginCapture");
     }
     int par = p;
-    for (int k = 0; k < kGraphChunk; ++k) {
-        launch_step(h, par, h->t_dev, k, cs);
-        par ^= 1;
+    if (h->fuse == 2) {
+        for (int k = 0; k < kGraphChunk; k += 2) {
+            launch_step2(h, par, h->t_dev, k, cs);
+            par ^= 1;
+        }
+    } else {
+        for (int k = 0; k < kGraphChunk; ++k) {
+            launch_step(h, par, h->t_dev, k, cs);
+            par ^= 1;
+        }
     }
     hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, cs, h->t_dev, (int64_t)kGraphChunk);
     e = hipStreamEndCapture(cs, &g);
@@ -264,11 +310,21 @@ void do_steps(lbm_em *h, int64_t n) {
         hip_check(hipGetLastError(), "k_set_time");
         for (int64_t c = 0; c < chunks; ++c) {
             hip_check(hipGraphLaunch(h->graph[h->cur], h->stream), "hipGraphLaunch");
-            // kGraphChunk is even: the buffer parity is unchanged
+            // a chunk flips the buffers an even number of times (32 fused
+            // or 64 single launches): the parity is unchanged
         }
         h->t += chunks * kGraphChunk;
     }
-    for (int64_t k = 0; k < n - chunks * kGraphChunk; ++k) {
+    int64_t rest = n - chunks * kGraphChunk;
+    if (h->fuse == 2) {
+        for (; rest >= 2; rest -= 2) {
+            launch_step2(h, h->cur, nullptr, h->t, h->stream);
+            hip_check(hipGetLastError(), "fused step kernel launch");
+            h->cur ^= 1;
+            h->t += 2;
+        }
+    }
+    for (int64_t k = 0; k < rest; ++k) {
         launch_step(h, h->cur, nullptr, h->t, h->stream);
         hip_check(hipGetLastError(), "step kernel launch");
         h->cur ^= 1;
@@ -615,7 +671,7 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
     return guarded([&] {
         if (!cfg || !out) fail(LBM_EM_EINVAL, "null config or output pointer");
         const lbm_em_config &c = *cfg;
-        if (c.nx < 3 || c.ny < 3 || c.nz < 1) fail(LBM_EM_EINVAL, "grid must be at least 3 x 3 x 1");
+        if (c.nx < 1 || c.ny < 1 || c.nz < 1) fail(LBM_EM_EINVAL, "grid sizes must be >= 1");
         if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 31)
             fail(LBM_EM_EINVAL, "more than 2^31 cells");
         if (c.pol != LBM_EM_TM && c.pol != LBM_EM_TE && c.pol != LBM_EM_3D)
@@ -626,8 +682,8 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             fail(LBM_EM_EINVAL, "precision must be LBM_EM_FP32 or LBM_EM_FP64");
         const int n[3] = {c.nx, c.ny, c.nz};
         for (int a = 0; a < 3; ++a) {
-            if (c.absorb[a] < 0 || 2 * c.absorb[a] > n[a])
-                fail(LBM_EM_EINVAL, "absorbing width must satisfy 0 <= 2W <= n");
+            if (c.absorb[a] < 0 || 2 * c.absorb[a] > n[a] || (c.absorb[a] > 0 && n[a] < 2))
+                fail(LBM_EM_EINVAL, "absorbing width must satisfy 0 <= 2W <= n (and n >= 2 when W > 0)");
             if (c.pol != LBM_EM_3D && a == 2 && c.absorb[a] != 0)
                 fail(LBM_EM_EINVAL, "2-D runs are periodic in z (absorb[2] = 0)");
         }
@@ -642,6 +698,11 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             h->dim = c.pol == LBM_EM_3D ? 3 : 2;
             h->nplanes = c.pol == LBM_EM_3D ? 27 : 11;
             h->elem = c.precision == LBM_EM_FP32 ? 4 : 8;
+            if (h->dim == 2) {
+                h->fuse = 2;
+                h->ftx = c.precision == LBM_EM_FP32 ? 64 : 32;
+                h->fty = 16;
+            }
             h->sy = round_up(c.nx, 64);
             h->sz = h->sy * c.ny;
             h->plane = h->sz * c.nz;
@@ -860,6 +921,32 @@ lbm_em_status lbm_em_set_tile(lbm_em_handle hh, int32_t vx, int32_t bx, int32_t 
     });
 }
 
+lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int32_t tile_x, int32_t tile_y) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (steps_per_launch != 1 && steps_per_launch != 2) fail(LBM_EM_EINVAL, "steps_per_launch must be 1 or 2");
+        if (steps_per_launch == 2 && h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "two steps per launch is 2-D only");
+        if (steps_per_launch == 2 && (tile_x || tile_y)) {
+            if (!fused_tile_ok(tile_x, tile_y))
+                fail(LBM_EM_EINVAL, "two-step tile must be 64x16, 64x8, 64x4, 32x16, 32x8 or 16x16");
+            h->ftx = tile_x;
+            h->fty = tile_y;
+        }
+        h->fuse = steps_per_launch;
+        drop_graphs(h);
+    });
+}
+
+lbm_em_status lbm_em_get_fusion(lbm_em_handle hh, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!steps_per_launch) fail(LBM_EM_EINVAL, "null output");
+        *steps_per_launch = h->fuse;
+        if (tile_x) *tile_x = h->ftx;
+        if (tile_y) *tile_y = h->fty;
+    });
+}
+
 lbm_em_status lbm_em_get_tile(lbm_em_handle hh, int32_t *vx, int32_t *bx, int32_t *by) {
     return guarded([&] {
         lbm_em *h = check_handle(hh);
@@ -875,68 +962,99 @@ lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_u
         lbm_em *h = check_handle(hh);
         if (launches < 1) fail(LBM_EM_EINVAL, "launches must be >= 1");
         select_device(h);
+        struct Cand { int fuse, a, b, c; };   // fuse 1: (vx, bx, by); fuse 2: (tx, ty)
+        std::vector<Cand> cands;
         static const int shapes[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 2}, {128, 1}, {64, 1}, {16, 16}};
-        const int vxs[] = {1, 2, 4};
+        for (int vx : {1, 2, 4})
+            for (auto &sh : shapes)
+                if (tile_ok(h, vx, sh[0], sh[1])) cands.push_back({1, vx, sh[0], sh[1]});
+        if (h->dim == 2) {
+            static const int ft[][2] = {{64, 16}, {64, 8}, {64, 4}, {32, 16}, {32, 8}, {16, 16}};
+            for (auto &f : ft) cands.push_back({2, f[0], f[1], 0});
+        }
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
-        const int keep[3] = {h->vx, h->bx, h->by};
-        int best[3] = {keep[0], keep[1], keep[2]};
-        float best_ms = 1e30f;
+        const lbm_em keep = *h;
+        auto apply = [&](const Cand &c) {
+            h->fuse = c.fuse;
+            if (c.fuse == 1) { h->vx = c.a; h->bx = c.b; h->by = c.c; }
+            else { h->ftx = c.a; h->fty = c.b; }
+        };
         // Timed launches read the current buffer and write the spare one with
         // the DFT off: the simulation state is not changed.
-        for (int vx : vxs)
-            for (auto &sh : shapes) {
-                if (!tile_ok(h, vx, sh[0], sh[1])) continue;
-                h->vx = vx;
-                h->bx = sh[0];
-                h->by = sh[1];
-                launch_step(h, h->cur, nullptr, h->t, h->stream, false);
-                hip_check(hipEventRecord(e0, h->stream), "hipEventRecord");
-                for (int i = 0; i < launches; ++i) launch_step(h, h->cur, nullptr, h->t, h->stream, false);
-                hip_check(hipEventRecord(e1, h->stream), "hipEventRecord");
-                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                float ms = 0.f;
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best[0] = vx;
-                    best[1] = sh[0];
-                    best[2] = sh[1];
-                }
+        auto launch = [&]() {
+            if (h->fuse == 2) launch_step2(h, h->cur, nullptr, h->t, h->stream, false);
+            else launch_step(h, h->cur, nullptr, h->t, h->stream, false);
+        };
+        Cand best = cands[0];
+        double best_per_step = 1e30;
+        for (const Cand &c : cands) {
+            apply(c);
+            launch();
+            hip_check(hipEventRecord(e0, h->stream), "hipEventRecord");
+            for (int i = 0; i < launches; ++i) launch();
+            hip_check(hipEventRecord(e1, h->stream), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            const double per_step = (double)ms / launches / c.fuse;
+            if (per_step < best_per_step) {
+                best_per_step = per_step;
+                best = c;
             }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        // The winner must reproduce the one-cell-per-thread kernel bit for bit.
+        // The winner must reproduce one-cell-per-thread single steps bit for
+        // bit (after one launch: one step, or two for the fused kernel).
         const size_t n = (size_t)h->plane * h->nplanes;
         void *ref = nullptr;
         int *flag = nullptr;
-        hip_check(hipMalloc(&ref, n * h->elem), "hipMalloc");
-        hip_check(hipMalloc(&flag, sizeof(int)), "hipMalloc");
-        hip_check(hipMemsetAsync(flag, 0, sizeof(int), h->stream), "hipMemset");
-        h->vx = 1; h->bx = 64; h->by = 4;
-        launch_step(h, h->cur, nullptr, h->t, h->stream, false);
-        hip_check(hipMemcpyAsync(ref, h->buf[h->cur ^ 1], n * h->elem, hipMemcpyDeviceToDevice, h->stream), "copy");
-        h->vx = best[0]; h->bx = best[1]; h->by = best[2];
-        launch_step(h, h->cur, nullptr, h->t, h->stream, false);
-        const unsigned blocks = (unsigned)((n + 255) / 256);
-        if (h->elem == 4)
-            hipLaunchKernelGGL((k_compare<float>), dim3(blocks), dim3(256), 0, h->stream, (const float *)ref,
-                               (const float *)h->buf[h->cur ^ 1], (int64_t)n, flag);
-        else
-            hipLaunchKernelGGL((k_compare<double>), dim3(blocks), dim3(256), 0, h->stream, (const double *)ref,
-                               (const double *)h->buf[h->cur ^ 1], (int64_t)n, flag);
-        int differs = 0;
-        hip_check(hipMemcpyAsync(&differs, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream), "D2H");
-        sync(h);
-        hfree(ref);
-        hfree(flag);
-        if (differs) {
-            h->vx = keep[0]; h->bx = keep[1]; h->by = keep[2];
-            fail(LBM_EM_EDEVICE, "autotune: tiled kernel differs from the reference kernel");
+        try {
+            hip_check(hipMalloc(&ref, n * h->elem), "hipMalloc");
+            hip_check(hipMalloc(&flag, sizeof(int)), "hipMalloc");
+            hip_check(hipMemsetAsync(flag, 0, sizeof(int), h->stream), "hipMemset");
+            h->fuse = 1; h->vx = 1; h->bx = 64; h->by = 4;
+            if (best.fuse == 1) {
+                launch_step(h, h->cur, nullptr, h->t, h->stream, false);
+                hip_check(hipMemcpyAsync(ref, h->buf[h->cur ^ 1], n * h->elem, hipMemcpyDeviceToDevice, h->stream), "copy");
+            } else if (h->elem == 4) {
+                launch_step_t<float>(h, h->buf[h->cur], h->buf[h->cur ^ 1], nullptr, h->t, h->stream, false, nullptr, 0);
+                launch_step_t<float>(h, h->buf[h->cur ^ 1], ref, nullptr, h->t + 1, h->stream, false, nullptr, 0);
+            } else {
+                launch_step_t<double>(h, h->buf[h->cur], h->buf[h->cur ^ 1], nullptr, h->t, h->stream, false, nullptr, 0);
+                launch_step_t<double>(h, h->buf[h->cur ^ 1], ref, nullptr, h->t + 1, h->stream, false, nullptr, 0);
+            }
+            apply(best);
+            launch();
+            const unsigned blocks = (unsigned)((n + 255) / 256);
+            if (h->elem == 4)
+                hipLaunchKernelGGL((k_compare<float>), dim3(blocks), dim3(256), 0, h->stream, (const float *)ref,
+                                   (const float *)h->buf[h->cur ^ 1], (int64_t)n, flag);
+            else
+                hipLaunchKernelGGL((k_compare<double>), dim3(blocks), dim3(256), 0, h->stream, (const double *)ref,
+                                   (const double *)h->buf[h->cur ^ 1], (int64_t)n, flag);
+            int differs = 0;
+            hip_check(hipMemcpyAsync(&differs, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream), "D2H");
+            sync(h);
+            hfree(ref);
+            hfree(flag);
+            ref = nullptr;
+            flag = nullptr;
+            if (differs) fail(LBM_EM_EDEVICE, "autotune: tuned kernel differs from the reference kernel");
+        } catch (...) {
+            hfree(ref);
+            hfree(flag);
+            h->fuse = keep.fuse; h->vx = keep.vx; h->bx = keep.bx; h->by = keep.by;
+            h->ftx = keep.ftx; h->fty = keep.fty;
+            throw;
         }
+        // the shape family that did not win keeps its previous setting
+        if (best.fuse == 2) { h->vx = keep.vx; h->bx = keep.bx; h->by = keep.by; }
+        else { h->ftx = keep.ftx; h->fty = keep.fty; }
         drop_graphs(h);
-        if (best_us) *best_us = 1e3 * best_ms / launches;
+        if (best_us) *best_us = 1e3 * best_per_step;
     });
 }
 

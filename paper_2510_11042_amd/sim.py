@@ -110,6 +110,20 @@ class Simulation:
     def set_tile(self, vx, bx, by):
         L.check(L.lib().lbm_em_set_tile(self._h, int(vx), int(bx), int(by)))
 
+    def set_fusion(self, steps_per_launch, tile=(0, 0)):
+        """Time steps per launch (1, or 2 in 2-D) and the two-step tile."""
+        L.check(L.lib().lbm_em_set_fusion(self._h, int(steps_per_launch), int(tile[0]), int(tile[1])))
+
+    def get_fusion(self):
+        v, tx, ty = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.lib().lbm_em_get_fusion(self._h, C.byref(v), C.byref(tx), C.byref(ty)))
+        return v.value
+
+    def get_fusion_tile(self):
+        v, tx, ty = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.lib().lbm_em_get_fusion(self._h, C.byref(v), C.byref(tx), C.byref(ty)))
+        return tx.value, ty.value
+
     def get_tile(self):
         v, b, c = C.c_int32(), C.c_int32(), C.c_int32()
         L.check(L.lib().lbm_em_get_tile(self._h, C.byref(v), C.byref(b), C.byref(c)))
@@ -126,10 +140,13 @@ class Simulation:
             table = json.load(open(cache))
             if key in table:
                 self.set_tile(*table[key]["tile"])
+                if self.n[2] == 1:
+                    self.set_fusion(table[key]["fusion"], table[key]["fusion_tile"])
                 return table[key]
         us = C.c_double()
         L.check(L.lib().lbm_em_autotune(self._h, int(launches), C.byref(us)))
-        rec = {"tile": list(self.get_tile()), "us_per_launch": us.value}
+        rec = {"tile": list(self.get_tile()), "fusion": self.get_fusion(),
+               "fusion_tile": list(self.get_fusion_tile()), "us_per_step": us.value}
         if cache:
             table[key] = rec
             os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)

@@ -42,7 +42,9 @@ def test_errors_are_status_codes_without_device():
     st = L.lbm_em_create(C.byref(cfg), C.byref(h))
     assert st == _lib.EDEVICE
     assert b"device" in L.lbm_em_last_error()
-    cfg.nx = 1
+    cfg.nx = 0
+    assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EINVAL
+    cfg.nx, cfg.absorb[0] = 16, 9            # 2W > n
     assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EINVAL
     assert L.lbm_em_create(None, C.byref(h)) == _lib.EINVAL
     assert L.lbm_em_step(None, 1) == _lib.EINVAL
