@@ -451,16 +451,12 @@ __global__ void __launch_bounds__(256) k_step2d_batch(const StepArgs<T> *__restr
 // ring) and written once.
 // ---------------------------------------------------------------------------
 template <typename T, int POL, int TX, int TY>
-__global__ void __launch_bounds__(256) k_step2d_x2(StepArgs<T> a) {
+__device__ inline void step2d_x2_tile(const StepArgs<T> &a, T (&lds)[8][TY + 2][TX + 2], int x0, int y0,
+                                      int64_t t) {
     constexpr int EX = TX + 2, EY = TY + 2;
     constexpr int NI = TX * TY / 256;             // tile cells per thread
     constexpr int NR = 2 * EX + 2 * TY;           // ring cells
     static_assert(TX * TY % 256 == 0 && NR <= 256, "tile shape");
-    // only the 8 streaming planes are exchanged through LDS; the z-pair and
-    // eps of a thread's own cells stay in its registers between the steps
-    __shared__ T lds[8][EY][EX];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int64_t t = step_time(a.t_base, a.t_off);
     const int64_t P = a.plane;
     const T *s = a.src;
     const int tid = threadIdx.x;
@@ -557,6 +553,51 @@ __global__ void __launch_bounds__(256) k_step2d_x2(StepArgs<T> a) {
         cell_update2d<T, POL>(a, t + 1, x, y, ep[it], f);
 #pragma unroll
         for (int p = 0; p < 11; ++p) d[p * P + c] = f[p];
+    }
+}
+
+template <typename T, int POL, int TX, int TY>
+__global__ void __launch_bounds__(256) k_step2d_x2(StepArgs<T> a) {
+    // only the 8 streaming planes are exchanged through LDS; the z-pair and
+    // eps of a thread's own cells stay in its registers between the steps
+    __shared__ T lds[8][TY + 2][TX + 2];
+    step2d_x2_tile<T, POL, TX, TY>(a, lds, blockIdx.x * TX, blockIdx.y * TY, step_time(a.t_base, a.t_off));
+}
+
+// One step on the two-step kernel's tiles (batched; a trailing odd step).
+template <typename T, int POL, int TX, int TY>
+__global__ void __launch_bounds__(256) k_step2d_tile_batch(const StepArgs<T> *__restrict__ descs,
+                                                           const int *__restrict__ tile_inst,
+                                                           const int *__restrict__ tile_first, int ntiles,
+                                                           const int64_t *t_base, int64_t t_off) {
+    const int64_t t = step_time(t_base, t_off);
+    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+        const int inst = tile_inst[w];
+        const StepArgs<T> &a = descs[inst];
+        const int local = w - tile_first[inst];
+        const int x0 = (local % a.tiles_x) * TX, y0 = (local / a.tiles_x) * TY;
+        for (int i = threadIdx.x; i < TX * TY; i += blockDim.x)
+            step2d_cells<T, POL, 1>(a, x0 + i % TX, y0 + i / TX, t);
+    }
+}
+
+// Batched form of the two-step kernel: a chip-sized grid strides over the
+// (instance, tile) work list (tiles of TX x TY cells); a barrier separates
+// consecutive tiles of a block because they share the LDS tile.
+template <typename T, int POL, int TX, int TY>
+__global__ void __launch_bounds__(256) k_step2d_x2_batch(const StepArgs<T> *__restrict__ descs,
+                                                         const int *__restrict__ tile_inst,
+                                                         const int *__restrict__ tile_first, int ntiles,
+                                                         const int64_t *t_base, int64_t t_off) {
+    __shared__ T lds[8][TY + 2][TX + 2];
+    const int64_t t = step_time(t_base, t_off);
+    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+        const int inst = tile_inst[w];
+        const StepArgs<T> &a = descs[inst];
+        const int local = w - tile_first[inst];
+        const int tx = local % a.tiles_x, ty = local / a.tiles_x;
+        step2d_x2_tile<T, POL, TX, TY>(a, lds, tx * TX, ty * TY, t);
+        __syncthreads();
     }
 }
 

@@ -123,6 +123,7 @@ struct lbm_em_batch_s {
     std::vector<lbm_em *> hs;
     std::vector<BatchGroup> groups;
     int pol = 0, precision = 0, vx = 1, bx = 128, by = 2;
+    int fuse = 1, ftx = 64, fty = 16;   // two steps per launch with this tile
     int64_t *t_dev = nullptr;
     hipStream_t stream = nullptr;
     int dev = 0, cus = 1, grid_override = 0;
@@ -342,8 +343,13 @@ void fill_group(lbm_em_batch_s *b, BatchGroup &g) {
         for (int i = 0; i < g.count; ++i) {
             const lbm_em *h = b->hs[g.first + i];
             d[i] = make_args<T>(h, h->buf[par], h->buf[par ^ 1]);
-            d[i].tiles_x = ((h->cfg.nx + b->vx - 1) / b->vx + b->bx - 1) / b->bx;
-            d[i].tiles_y = (h->cfg.ny + b->by - 1) / b->by;
+            if (b->fuse == 2) {
+                d[i].tiles_x = (h->cfg.nx + b->ftx - 1) / b->ftx;
+                d[i].tiles_y = (h->cfg.ny + b->fty - 1) / b->fty;
+            } else {
+                d[i].tiles_x = ((h->cfg.nx + b->vx - 1) / b->vx + b->bx - 1) / b->bx;
+                d[i].tiles_y = (h->cfg.ny + b->by - 1) / b->by;
+            }
         }
         if (par == 0) {
             int acc = 0;
@@ -384,8 +390,40 @@ void launch_batch_vx(const lbm_em_batch_s *b, const BatchGroup &g, int par, cons
                            g.ntiles, t_base, t_off);
 }
 
+template <typename T, int POL>
+void launch_batch_x2_pol(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
+                         hipStream_t s, bool two) {
+    const StepArgs<T> *d = (const StepArgs<T> *)g.descs[par];
+#define LBM_X2B(TX, TY)                                                                                        \
+    if (b->ftx == TX && b->fty == TY) {                                                                         \
+        if (two)                                                                                                \
+            hipLaunchKernelGGL((k_step2d_x2_batch<T, POL, TX, TY>), dim3(g.grid), dim3(256), 0, s, d, g.tile_inst, \
+                               g.tile_first, g.ntiles, t_base, t_off);                                         \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_step2d_tile_batch<T, POL, TX, TY>), dim3(g.grid), dim3(256), 0, s, d,        \
+                               g.tile_inst, g.tile_first, g.ntiles, t_base, t_off);                            \
+        return;                                                                                                \
+    }
+    LBM_X2B(64, 16) LBM_X2B(64, 8) LBM_X2B(64, 4) LBM_X2B(32, 16) LBM_X2B(32, 8) LBM_X2B(16, 16)
+#undef LBM_X2B
+    fail(LBM_EM_EINVAL, "unsupported two-step tile");
+}
+
+// One launch of the batch.  With fused tiles (b->fuse == 2) `steps` is 2
+// (two-step kernel) or 1 (a single step on the same tiles).
 void launch_batch(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
-                  hipStream_t s) {
+                  hipStream_t s, int steps = 0) {
+    if (b->fuse == 2) {
+        const bool two = steps != 1;
+        if (b->precision == LBM_EM_FP32) {
+            if (b->pol == LBM_EM_TM) launch_batch_x2_pol<float, TM>(b, g, par, t_base, t_off, s, two);
+            else launch_batch_x2_pol<float, TE>(b, g, par, t_base, t_off, s, two);
+        } else {
+            if (b->pol == LBM_EM_TM) launch_batch_x2_pol<double, TM>(b, g, par, t_base, t_off, s, two);
+            else launch_batch_x2_pol<double, TE>(b, g, par, t_base, t_off, s, two);
+        }
+        return;
+    }
     if (b->precision == LBM_EM_FP32) {
         if (b->vx == 1) launch_batch_vx<float, 1>(b, g, par, t_base, t_off, s);
         else if (b->vx == 2) launch_batch_vx<float, 2>(b, g, par, t_base, t_off, s);
@@ -463,6 +501,9 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
         b->vx = h0->vx;
         b->bx = h0->bx;
         b->by = h0->by;
+        b->fuse = h0->fuse;
+        b->ftx = h0->ftx;
+        b->fty = h0->fty;
         b->budget = (int64_t)192 << 20;
         for (int i = 0; i < count; ++i) b->hs.push_back(hs[i]);
         hip_check(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev), "attribute");
@@ -486,7 +527,7 @@ hipGraphExec_t build_batch_graph(lbm_em_batch_s *b, const BatchGroup &grp, int p
         hip_check(e, "hipStreamBeginCapture");
     }
     int par = p;
-    for (int k = 0; k < kGraphChunk; ++k) {
+    for (int k = 0; k < kGraphChunk; k += b->fuse) {
         launch_batch(b, grp, par, b->t_dev, k, cs);
         par ^= 1;
     }
@@ -522,11 +563,14 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
             for (int64_t c = 0; c < chunks; ++c) hip_check(hipGraphLaunch(g.graph[cur], b->stream), "hipGraphLaunch");
             t += chunks * kGraphChunk;
         }
-        for (int64_t k = 0; k < n - chunks * kGraphChunk; ++k) {
-            launch_batch(b, g, cur, nullptr, t, b->stream);
+        int64_t rest = n - chunks * kGraphChunk;
+        while (rest > 0) {
+            const int adv = (b->fuse == 2 && rest >= 2) ? 2 : 1;   // a trailing odd step runs alone
+            launch_batch(b, g, cur, nullptr, t, b->stream, adv);
             hip_check(hipGetLastError(), "batch kernel launch");
             cur ^= 1;
-            t += 1;
+            t += adv;
+            rest -= adv;
         }
     }
     for (auto *h : b->hs) {

@@ -26,7 +26,7 @@ def lib():
     return P
 
 
-def _make(P, case, prec, tile=None):
+def _make(P, case, prec, tile=None, fuse=2):
     kh, eh = W.plane_wave_2d(case.theta_deg, case.pol)
     s = P.Simulation(case.nx, case.ny, 1, pol=case.pol, precision=prec, absorb=case.absorb,
                      sigma_max=W.SIGMA_MAX)
@@ -36,6 +36,7 @@ def _make(P, case, prec, tile=None):
         s.set_ntff(case.box_lo, case.box_hi, *case.window)
     if tile:
         s.set_tile(*tile)
+    s.set_fusion(fuse)
     return s
 
 
@@ -61,20 +62,21 @@ def _cases(seed, count, steps):
     return out
 
 
-@pytest.mark.parametrize("prec,tile", [("fp32", None), ("fp32", (4, 64, 4)), ("fp64", (2, 128, 2))])
-def test_batch_equals_individual(lib, prec, tile):
-    steps = 200                                    # 3 graph chunks + 8 eager steps
+@pytest.mark.parametrize("prec,tile,fuse", [("fp32", None, 2), ("fp32", (4, 64, 4), 1), ("fp64", (2, 128, 2), 1),
+                                             ("fp64", None, 2)])
+def test_batch_equals_individual(lib, prec, tile, fuse):
+    steps = 200                  # graph chunks, eager pairs and a trailing odd step
     cases = _cases(251011042, 6, steps)
-    say("batch", prec, tile, [c.nx for c in cases])
-    solo = [_make(lib, c, prec, tile) for c in cases]
+    say("batch", prec, tile, fuse, [c.nx for c in cases])
+    solo = [_make(lib, c, prec, tile, 1) for c in cases]
     for s in solo:
         s.step(steps)
-    grouped = [_make(lib, c, prec, tile) for c in cases]
+    grouped = [_make(lib, c, prec, tile, fuse) for c in cases]
     b = lib.Batch(grouped)
-    b.step(130)
+    b.step(131)
     b.set_cache_budget(3 << 20)          # several groups from here on
     assert b.groups > 1
-    b.step(70)
+    b.step(69)
     for s, g in zip(solo, grouped):
         assert g.t == s.t == steps
         Es, Hs = s.fields()
