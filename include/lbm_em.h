@@ -84,11 +84,15 @@ typedef struct {
 /* Create a handle: allocates the distributions (reduced exact state: 11
  * scalars per cell in 2-D, 27 in 3-D, two buffers), eps_r (initialised to 1)
  * and zeroes the state (t = 0).  *out is set only on success.
+ * Rows are padded to a multiple of 64 cells; one plane (padded nx * ny * nz
+ * values) must stay below 4 GiB, as the kernels address a plane with 32-bit
+ * byte offsets (FP32 up to 2^30 cells, e.g. 1024^3 or 32768^2).
  * Errors: EINVAL for bad sizes / pointers, EDEVICE without a HIP device,
  * ENOMEM when device memory runs out. */
 lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out);
 
-/* Release all device memory of the handle (synchronises its stream). */
+/* Release all device memory of the handle (synchronises its stream).
+ * ESTATE while the handle belongs to a batch (destroy the batch first). */
 lbm_em_status lbm_em_destroy(lbm_em_handle h);
 
 /* Set eps_r(x) (paper section 2.1: it enters the rest equilibrium and
@@ -101,7 +105,9 @@ lbm_em_status lbm_em_set_permittivity(lbm_em_handle h, const void *eps, int32_t 
 /* Set the incident plane wave (see lbm_em_plane_wave).  EINVAL if khat or
  * ehat is not a unit vector, not perpendicular, 3*lambda is not integral,
  * or the polarisation does not match the handle (TM: ehat = +-z; TE/TM:
- * khat_z = 0). */
+ * khat_z = 0), or the ramp exceeds 1e7 steps; ESTATE while the handle
+ * belongs to a batch.  The phase factors are tabulated once here (FP64, per
+ * period step and per grid line), so the step kernels evaluate no sine. */
 lbm_em_status lbm_em_set_source(lbm_em_handle h, const lbm_em_plane_wave *pw);
 
 /* Record E and H phasors on the surface of the node box [lo, hi] (inclusive
@@ -110,7 +116,8 @@ lbm_em_status lbm_em_set_source(lbm_em_handle h, const lbm_em_plane_wave *pw);
  * window_start + window_len):  X += (2/window_len) F(t) exp(-j omega t)
  * (section 2.4, "one period of the steady-state oscillation").  Clears the
  * accumulators.  EINVAL if the box is not strictly inside the grid, is
- * thinner than 3 nodes, or the window is empty. */
+ * thinner than 3 nodes, or the window is empty; ESTATE before the source is
+ * set or while the handle belongs to a batch. */
 lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_t hi[3],
                               int64_t window_start, int64_t window_len);
 

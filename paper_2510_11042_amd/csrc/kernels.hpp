@@ -38,6 +38,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
 #include <stdint.h>
 
 namespace lbm {
@@ -94,17 +97,21 @@ struct StepArgs {
     int nx, ny, nz;
     int64_t sy, sz, plane;      // element strides: row, slab, plane
     int W[3];                   // absorbing width per axis, 0 = periodic
+    T inv_w[3];                 // 1 / W (0 on a periodic axis)
     T sigma_max;
     const T *__restrict__ src;  // f*(t-1), nplanes planes
     T *__restrict__ dst;        // f*(t)
     const T *__restrict__ eps;
     const int64_t *t_base;      // graph replay: t = *t_base + t_off; else NULL
     int64_t t_off;
-    // plane-wave source
+    // plane-wave source (phase tables: see plane_wave)
     int src_on;
     int period;                 // T = 3 lambda steps
-    double amp, t_ramp, inv_lam;
-    double khat[3], ehat[3], hhat[3], rc[3];
+    double amp, t_ramp;
+    double ehat[3], hhat[3];
+    const double *ramp;         // g(t) for t < t_ramp
+    const double2 *wave_t;      // e^{2 pi j k / T}, k < T
+    const double2 *wave_x, *wave_y, *wave_z;   // e^{2 pi j u_a} per column / row / slab
     // running DFT on the contour box + probe node
     int dft_on;
     Box box;
@@ -120,14 +127,17 @@ struct StepArgs {
     int64_t hist_t0;
 };
 
+// Layer strength at coordinate x of an axis of n cells with a layer of W
+// cells at each end: sigma_max (d / W)^2 at depth d (1 .. W), 0 inside.
+// inv_w = 1 / W (0 on a periodic axis) comes precomputed from the host.
 template <typename T>
-__device__ inline T sigma_axis(int x, int n, int W, T smax) {
-    if (W <= 0) return T(0);
+__device__ inline T sigma_axis(int x, int n, int W, T inv_w, T smax) {
     int d = 0;
-    if (x < W) d = W - x;
-    else if (x >= n - W) d = x - (n - W) + 1;
-    if (d == 0) return T(0);
-    T u = T(d) / T(W);
+    if (W > 0) {
+        if (x < W) d = W - x;
+        else if (x >= n - W) d = x - (n - W) + 1;
+    }
+    const T u = T(d) * inv_w;
     return smax * u * u;
 }
 
@@ -135,21 +145,53 @@ __device__ inline int64_t step_time(const int64_t *t_base, int64_t t_off) {
     return (t_base ? *t_base : 0) + t_off;
 }
 
-// Incident plane-wave value w = g(t) E0 sin(omega t - k khat.(r - rc)) at a
-// cell; the phase is reduced exactly with t mod T (T integral) in FP64.
+// Per-step quantities shared by every cell of a launch (or of one work item
+// of a batched launch), formed once from the step index t.
+//
+// Source: the incident value w = g(t) E0 sin(omega t - k khat.(r - rc)) at
+// a cell.  With tau = (t mod T) / T and u = khat.(r - rc) / lambda split per
+// axis as u = u_x(x) + u_y(y) + u_z(z),
+//   w = g E0 sin(2 pi tau) cos(2 pi u) - g E0 cos(2 pi tau) sin(2 pi u),
+// where e^{2 pi j u} is the product of per-axis factors.  Every factor comes
+// from FP64 tables the host fills when the source is set (each phase reduced
+// modulo one period first), so a cell pays two or three gathers and a few
+// multiplies instead of an FP64 sine.
+// DFT: inside the window, the factor (2 / winlen) e^{-j omega t}.
+struct StepConst {
+    int64_t t;
+    double gs, gc;      // g(t) E0 sin(2 pi tau), g(t) E0 cos(2 pi tau)
+    bool dft;           // t lies in the DFT window
+    double cr, ci;      // (2 / winlen) (cos, -sin)(2 pi tau)
+};
+
 template <typename T>
-__device__ inline double plane_wave(const StepArgs<T> &a, int64_t t, int x, int y, int z) {
-    double g = 1.0;
-    if ((double)t < a.t_ramp) {
-        double s = sin(M_PI * (double)t / (2.0 * a.t_ramp));
-        g = s * s;
+__device__ inline StepConst step_const(const StepArgs<T> &a, int64_t t) {
+    StepConst c{t, 0.0, 0.0, false, 0.0, 0.0};
+    if (!a.src_on) return c;             // the DFT needs the source's period too
+    const double2 ph = a.wave_t[t % a.period];
+    const double g = ((double)t < a.t_ramp ? a.ramp[t] : 1.0) * a.amp;
+    c.gs = g * ph.y;
+    c.gc = g * ph.x;
+    if (a.dft_on && t >= a.win0 && t < a.win0 + a.winlen) {
+        const double sc = 2.0 / (double)a.winlen;
+        c.dft = true;
+        c.cr = sc * ph.x;
+        c.ci = -sc * ph.y;
     }
-    double tf = (double)(t % a.period) / (double)a.period;
-    double kr = a.khat[0] * ((double)x - a.rc[0]) + a.khat[1] * ((double)y - a.rc[1]) +
-                a.khat[2] * ((double)z - a.rc[2]);
-    double u = tf - kr * a.inv_lam;
-    u -= floor(u);
-    return g * a.amp * sin(2.0 * M_PI * u);
+    return c;
+}
+
+template <typename T, int DIM>
+__device__ inline double plane_wave(const StepArgs<T> &a, const StepConst &sc, int x, int y, int z) {
+    const double2 px = a.wave_x[x], py = a.wave_y[y];
+    double ur = px.x * py.x - px.y * py.y, ui = px.x * py.y + px.y * py.x;
+    if (DIM == 3) {
+        const double2 pz = a.wave_z[z];
+        const double r = ur * pz.x - ui * pz.y;
+        ui = ur * pz.y + ui * pz.x;
+        ur = r;
+    }
+    return sc.gs * ur - sc.gc * ui;
 }
 
 // Fields at a cell from pulled 2-D reduced populations.
@@ -200,15 +242,13 @@ __device__ inline void equilibrium2d(const T F[3], T scale, T q[11]) {
 
 // Accumulate the running DFT of the fields at a contour / probe node.
 template <typename T>
-__device__ inline void dft_accumulate(const StepArgs<T> &a, int64_t t, int dim, int x, int y,
+__device__ inline void dft_accumulate(const StepArgs<T> &a, const StepConst &st, int dim, int x, int y,
                                       int z, const double E[3], const double H[3]) {
-    if (!a.dft_on || t < a.win0 || t >= a.win0 + a.winlen) return;
+    if (!st.dft) return;
     bool surf = on_box(a.box, dim, x, y, z);
     bool probe = x == a.probe[0] && y == a.probe[1] && z == a.probe[2];
     if (!surf && !probe) return;
-    double ph = 2.0 * M_PI * (double)(t % a.period) / (double)a.period;
-    double sc = 2.0 / (double)a.winlen;
-    double cr = sc * cos(ph), ci = -sc * sin(ph);
+    const double cr = st.cr, ci = st.ci;
     for (int pass = 0; pass < 2; ++pass) {
         int64_t node;
         if (pass == 0) {
@@ -231,6 +271,28 @@ __device__ inline void dft_accumulate(const StepArgs<T> &a, int64_t t, int dim, 
 // Pull neighbours with the open boundary (clamp) or periodic wrap.
 __device__ inline int pull_lo(int x, int n, int W) { return x > 0 ? x - 1 : (W ? 0 : n - 1); }
 __device__ inline int pull_hi(int x, int n, int W) { return x < n - 1 ? x + 1 : (W ? n - 1 : 0); }
+
+// The in-domain coordinate that a coordinate outside [0, n) stands for: the
+// wrapped one on a periodic axis, the nearest face on an absorbing one.
+// Tiles and rings that reach past the domain compute such cells; on a
+// periodic axis they are exactly the wrapped neighbours, on an absorbing
+// axis their results are never used.
+__device__ inline int fold(int x, int n, int W) {
+    if (x >= 0 && x < n) return x;
+    if (W) return x < 0 ? 0 : n - 1;
+    x %= n;
+    return x < 0 ? x + n : x;
+}
+
+// Element i of an array with a wave-uniform base.  The offset is formed in
+// 32 bits (every plane is below 4 GiB, checked at create), which maps onto
+// the scalar-base + 32-bit vector-offset form of the global memory
+// instructions instead of per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ inline T *at(T *base, uint32_t i) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T *>(reinterpret_cast<B *>(base) + (size_t)(i * (uint32_t)sizeof(T)));
+}
 
 // ---------------------------------------------------------------------------
 // Vector loads/stores: each thread updates VX consecutive x-cells.  Aligned
@@ -284,21 +346,30 @@ __device__ inline void store_aligned(T *p, const T (&i)[N]) {
     }
 }
 
+template <typename T>
+__device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
+    return fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
+                sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max));
+}
+
 // ---------------------------------------------------------------------------
 // 2-D per-cell update: moments, DFT sample, collision, layer/source blend.
-// f holds the pulled populations on entry and f*(t) on exit.
+// f holds the pulled populations on entry and f*(t) on exit; inv_eps = 1/eps
+// and sig = sigma2d(x, y) come from the caller (the two-step kernel reuses
+// them for the second step).  record: the cell is in the domain and owned by
+// this thread, so it may add DFT samples and design-region history.
 // ---------------------------------------------------------------------------
 template <typename T, int POL>
-__device__ inline void cell_update2d(const StepArgs<T> &a, int64_t t, int x, int y, T eps, T f[11],
-                                     bool record = true) {
-    const T inv_eps = T(1) / eps;
+__device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst &st, int x, int y, T eps, T inv_eps,
+                                     T sig, T f[11], bool record) {
+    const int64_t t = st.t;
     T F[3];
     fields2d<T, POL>(f, eps, inv_eps, F);
-    if (a.dft_on && record) {
+    if (st.dft && record) {
         double E[3] = {0, 0, 0}, H[3] = {0, 0, 0};
         if (POL == TM) { E[2] = F[0]; H[0] = F[1]; H[1] = F[2]; }
         else { E[0] = F[0]; E[1] = F[1]; H[2] = F[2]; }
-        dft_accumulate(a, t, 2, x, y, 0, E, H);
+        dft_accumulate(a, st, 2, x, y, 0, E, H);
     }
     if (a.hist && record && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
         // E = (sum of the E-carrying populations + (6 eps - 4) z-pair)/eps,
@@ -316,12 +387,10 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, int64_t t, int x, int
     equilibrium2d<T, POL>(F, T(2), q);
 #pragma unroll
     for (int i = 0; i < 11; ++i) f[i] = q[i] - f[i];
-    const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max),
-                       sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max));
     if (sig > T(0)) {
         T R[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
-            const T w = (T)plane_wave(a, t, x, y, 0);
+            const T w = (T)plane_wave<T, 2>(a, st, x, y, 0);
             if (POL == TM) { R[0] = w * (T)a.ehat[2]; R[1] = w * (T)a.hhat[0]; R[2] = w * (T)a.hhat[1]; }
             else { R[0] = w * (T)a.ehat[0]; R[1] = w * (T)a.ehat[1]; R[2] = w * (T)a.hhat[2]; }
         }
@@ -332,86 +401,105 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, int64_t t, int x, int
     }
 }
 
-// ---------------------------------------------------------------------------
-// 2-D fused step: pull + moments + DFT + collision + layer/source + store.
-// Thread (gx, y) updates cells x0 = VX*gx .. x0+VX-1 of row y.
-// ---------------------------------------------------------------------------
-template <typename T, int POL, int VX>
-__device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, int64_t t) {
-    if (x0 >= a.nx || y >= a.ny) return;
-    const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
-    const int64_t P = a.plane, row = (int64_t)y * a.sy;
-    const int64_t rm = (int64_t)ym * a.sy, rp = (int64_t)yp * a.sy;
+// Pulled populations and eps of the VX cells x0 .. x0+VX-1 of row y
+// (0 <= y < ny, x0 a multiple of VX; cells outside [0, nx) are folded).
+template <typename T, int VX>
+__device__ inline void pull_row(const StepArgs<T> &a, int x0, int y, T (&v)[11][VX], T (&e)[VX]) {
+    const int64_t P = a.plane;
     const T *s = a.src;
-    const bool full = x0 + VX <= a.nx;
-    const bool inner = full && x0 > 0 && x0 + VX < a.nx;
-    T v[11][VX], e[VX];
-    if (inner) {
-        load_shifted<T, VX>(v[0], s + 0 * P + row + x0 - 1);   // +x from x-1
-        load_shifted<T, VX>(v[4], s + 4 * P + row + x0 - 1);
-        load_shifted<T, VX>(v[1], s + 1 * P + row + x0 + 1);   // -x from x+1
-        load_shifted<T, VX>(v[5], s + 5 * P + row + x0 + 1);
+    const uint32_t sy = (uint32_t)a.sy;
+    const uint32_t row = (uint32_t)y * sy;
+    const uint32_t rm = (uint32_t)pull_lo(y, a.ny, a.W[1]) * sy;
+    const uint32_t rp = (uint32_t)pull_hi(y, a.ny, a.W[1]) * sy;
+    if (x0 > 0 && x0 + VX < a.nx) {
+        const uint32_t c = row + (uint32_t)x0;
+        load_shifted<T, VX>(v[0], at(s + 0 * P, c - 1));   // +x movers from x-1
+        load_shifted<T, VX>(v[4], at(s + 4 * P, c - 1));
+        load_shifted<T, VX>(v[1], at(s + 1 * P, c + 1));   // -x movers from x+1
+        load_shifted<T, VX>(v[5], at(s + 5 * P, c + 1));
     } else {
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
-            const int x = x0 + k < a.nx ? x0 + k : a.nx - 1;
-            const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
-            v[0][k] = s[0 * P + row + xm];
-            v[4][k] = s[4 * P + row + xm];
-            v[1][k] = s[1 * P + row + xp];
-            v[5][k] = s[5 * P + row + xp];
+            const int x = fold(x0 + k, a.nx, a.W[0]);
+            const uint32_t cm = row + (uint32_t)pull_lo(x, a.nx, a.W[0]);
+            const uint32_t cp = row + (uint32_t)pull_hi(x, a.nx, a.W[0]);
+            v[0][k] = *at(s + 0 * P, cm);
+            v[4][k] = *at(s + 4 * P, cm);
+            v[1][k] = *at(s + 1 * P, cp);
+            v[5][k] = *at(s + 5 * P, cp);
         }
     }
-    if (full) {
-        load_aligned<T, VX>(v[2], s + 2 * P + rm + x0);        // +y from y-1
-        load_aligned<T, VX>(v[6], s + 6 * P + rm + x0);
-        load_aligned<T, VX>(v[3], s + 3 * P + rp + x0);        // -y from y+1
-        load_aligned<T, VX>(v[7], s + 7 * P + rp + x0);
-        load_aligned<T, VX>(v[8], s + 8 * P + row + x0);       // z-pair: no move
-        load_aligned<T, VX>(v[9], s + 9 * P + row + x0);
-        load_aligned<T, VX>(v[10], s + 10 * P + row + x0);
-        load_aligned<T, VX>(e, a.eps + row + x0);
+    if (x0 >= 0 && x0 + VX <= a.nx) {
+        const uint32_t c = (uint32_t)x0;
+        load_aligned<T, VX>(v[2], at(s + 2 * P, rm + c));   // +y movers from y-1
+        load_aligned<T, VX>(v[6], at(s + 6 * P, rm + c));
+        load_aligned<T, VX>(v[3], at(s + 3 * P, rp + c));   // -y movers from y+1
+        load_aligned<T, VX>(v[7], at(s + 7 * P, rp + c));
+        load_aligned<T, VX>(v[8], at(s + 8 * P, row + c));  // z-pair: no move
+        load_aligned<T, VX>(v[9], at(s + 9 * P, row + c));
+        load_aligned<T, VX>(v[10], at(s + 10 * P, row + c));
+        load_aligned<T, VX>(e, at(a.eps, row + c));
     } else {
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
-            const int x = x0 + k < a.nx ? x0 + k : a.nx - 1;
-            v[2][k] = s[2 * P + rm + x];
-            v[6][k] = s[6 * P + rm + x];
-            v[3][k] = s[3 * P + rp + x];
-            v[7][k] = s[7 * P + rp + x];
-            v[8][k] = s[8 * P + row + x];
-            v[9][k] = s[9 * P + row + x];
-            v[10][k] = s[10 * P + row + x];
-            e[k] = a.eps[row + x];
+            const uint32_t c = (uint32_t)fold(x0 + k, a.nx, a.W[0]);
+            v[2][k] = *at(s + 2 * P, rm + c);
+            v[6][k] = *at(s + 6 * P, rm + c);
+            v[3][k] = *at(s + 3 * P, rp + c);
+            v[7][k] = *at(s + 7 * P, rp + c);
+            v[8][k] = *at(s + 8 * P, row + c);
+            v[9][k] = *at(s + 9 * P, row + c);
+            v[10][k] = *at(s + 10 * P, row + c);
+            e[k] = *at(a.eps, row + c);
         }
     }
-#pragma unroll
-    for (int k = 0; k < VX; ++k) {
-        T f[11];
-#pragma unroll
-        for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-        cell_update2d<T, POL>(a, t, x0 + k, y, e[k], f);
-#pragma unroll
-        for (int i = 0; i < 11; ++i) v[i][k] = f[i];
-    }
+}
+
+// Store the cells x0 .. x0+VX-1 of row y that lie in the domain.
+template <typename T, int VX>
+__device__ inline void store_row(const StepArgs<T> &a, int x0, int y, const T (&v)[11][VX]) {
+    const int64_t P = a.plane;
     T *d = a.dst;
-    if (full) {
+    const uint32_t c = (uint32_t)y * (uint32_t)a.sy + (uint32_t)x0;
+    if (x0 + VX <= a.nx) {
 #pragma unroll
-        for (int i = 0; i < 11; ++i) store_aligned<T, VX>(d + i * P + row + x0, v[i]);
+        for (int i = 0; i < 11; ++i) store_aligned<T, VX>(at(d + i * P, c), v[i]);
     } else {
 #pragma unroll
         for (int k = 0; k < VX; ++k)
             if (x0 + k < a.nx)
 #pragma unroll
-                for (int i = 0; i < 11; ++i) d[i * P + row + x0 + k] = v[i][k];
+                for (int i = 0; i < 11; ++i) *at(d + i * P, c + k) = v[i][k];
     }
+}
+
+// ---------------------------------------------------------------------------
+// 2-D fused step: pull + moments + DFT + collision + layer/source + store.
+// The calling thread updates cells x0 .. x0+VX-1 of row y.
+// ---------------------------------------------------------------------------
+template <typename T, int POL, int VX>
+__device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const StepConst &st) {
+    if (x0 >= a.nx || y >= a.ny) return;
+    T v[11][VX], e[VX];
+    pull_row<T, VX>(a, x0, y, v, e);
+#pragma unroll
+    for (int k = 0; k < VX; ++k) {
+        const int x = fold(x0 + k, a.nx, a.W[0]);
+        T f[11];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) f[i] = v[i][k];
+        cell_update2d<T, POL>(a, st, x, y, e[k], T(1) / e[k], sigma2d<T>(a, x, y), f, x0 + k < a.nx);
+#pragma unroll
+        for (int i = 0; i < 11; ++i) v[i][k] = f[i];
+    }
+    store_row<T, VX>(a, x0, y, v);
 }
 
 template <typename T, int POL, int VX>
 __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
     const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    step2d_cells<T, POL, VX>(a, x0, y, step_time(a.t_base, a.t_off));
+    step2d_cells<T, POL, VX>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
 }
 
 // Batched persistent step: one launch advances many 2-D instances of
@@ -433,135 +521,210 @@ __global__ void __launch_bounds__(256) k_step2d_batch(const StepArgs<T> *__restr
         const int tx = local % a.tiles_x, ty = local / a.tiles_x;
         const int x0 = (tx * (int)blockDim.x + (int)threadIdx.x) * VX;
         const int y = ty * (int)blockDim.y + (int)threadIdx.y;
-        step2d_cells<T, POL, VX>(a, x0, y, t);
+        step2d_cells<T, POL, VX>(a, x0, y, step_const(a, t));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Two time steps per launch (temporal blocking through LDS).
-// A block owns a TX x TY output tile.  Step t is computed on the tile grown
-// by one cell on every side (pulling from global memory as the one-step
-// kernel does; on a periodic axis the ring holds the wrapped cells, on an
-// absorbing axis cells outside the domain are skipped); the 11 results go
-// to LDS.  Step t+1 then pulls from LDS -- the open-boundary clamp becomes
-// "read your own slot" on the domain faces -- and writes the tile.  Each
-// cell runs the same per-cell code as the one-step kernel, so the result is
-// bit-identical; ring cells belong to neighbouring tiles and never record
-// DFT samples.  HBM traffic per two steps: the state is read once (plus the
-// ring) and written once.
+//
+// A 256-thread block owns a TX x TY output tile, cut into 256 row segments
+// of VX = 16 bytes / sizeof(T) cells, one per thread.  Step t runs on
+// the tile's segments and on a one-cell ring around it, pulling from global
+// memory exactly as the one-step kernel does.  Each moving population goes
+// to LDS only where step t+1 will pull it from: the +x movers (planes 0, 4)
+// of the tile and of the ring column on the left, the -x movers (1, 5) of
+// the tile and the right ring column, the +y movers (2, 6) of the tile and
+// the ring row above, the -y movers (3, 7) of the tile and the ring row
+// below.  The non-moving z-pair, eps, 1/eps and the layer strength of a
+// thread's own cells stay in its registers.  Step t+1 then pulls from LDS --
+// the open-boundary clamp becomes "read your own value" on the domain faces
+// -- and writes the tile.  Every cell goes through the same per-cell code as
+// in the one-step kernel, so the result is bit-identical; ring cells never
+// record DFT samples.  HBM traffic per two steps: the state is read once
+// (plus the ring) and written once.
 // ---------------------------------------------------------------------------
+template <typename T, int TX, int TY>
+struct alignas(16) X2Lds {
+    static constexpr int VX = 16 / (int)sizeof(T);
+    static constexpr int SX = TX + VX;   // padded row of the x-moving planes
+    T xm[2][TY][SX];                     // planes 0, 4: tile column ox at VX + ox, left ring at VX - 1
+    T xp[2][TY][SX];                     // planes 1, 5: tile column ox at ox, right ring at TX
+    T ym[2][TY + 1][TX];                 // planes 2, 6: ring row above at 0, tile row oy at oy + 1
+    T yp[2][TY + 1][TX];                 // planes 3, 7: tile row oy at oy, ring row below at TY
+};
+
+// One segment per thread: TX x TY = 256 segments of VX cells.
+template <typename T, int TX, int TY>
+__host__ __device__ constexpr bool x2_tile_ok() {
+    constexpr int VX = 16 / (int)sizeof(T);
+    return TX % VX == 0 && (TX / VX) * TY == 256;
+}
+
+template <typename T, int N>
+__device__ inline void lds_load(T (&o)[N], const T *p) { load_aligned<T, N>(o, p); }
+template <typename T, int N>
+__device__ inline void lds_store(T *p, const T (&i)[N]) { store_aligned<T, N>(p, i); }
+
 template <typename T, int POL, int TX, int TY>
-__device__ inline void step2d_x2_tile(const StepArgs<T> &a, T (&lds)[8][TY + 2][TX + 2], int x0, int y0,
-                                      int64_t t) {
-    constexpr int EX = TX + 2, EY = TY + 2;
-    constexpr int NI = TX * TY / 256;             // tile cells per thread
-    constexpr int NR = 2 * EX + 2 * TY;           // ring cells
-    static_assert(TX * TY % 256 == 0 && NR <= 256, "tile shape");
-    const int64_t P = a.plane;
-    const T *s = a.src;
+__device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t) {
+    const StepConst s0 = step_const(a, t), s1 = step_const(a, t + 1);
+    constexpr int VX = X2Lds<T, TX, TY>::VX;
+    constexpr int TPR = TX / VX;             // segments per tile row
+    constexpr int NI = 1;                    // segments per thread
+    constexpr int NR = 2 * TPR + 2 * TY;     // ring work items
+    static_assert(x2_tile_ok<T, TX, TY>(), "two-step tile shape");
     const int tid = threadIdx.x;
-    T zp[NI][3], ep[NI];
+    T zp[NI][3][VX], ep[NI][VX], ip[NI][VX], sg[NI][VX];
 
-    // step t on one cell of the grown tile (ex, ey); returns false if the
-    // cell lies outside the domain on an absorbing axis
-    auto step_a = [&](int ex, int ey, T f[11], T &eps) -> bool {
-        int x = x0 - 1 + ex, y = y0 - 1 + ey;
-        const bool owned = ex >= 1 && ex <= TX && ey >= 1 && ey <= TY && x < a.nx && y < a.ny;
-        if (x < 0 || x >= a.nx) {
-            if (a.W[0]) return false;
-            x = (x % a.nx + a.nx) % a.nx;
-        }
-        if (y < 0 || y >= a.ny) {
-            if (a.W[1]) return false;
-            y = (y % a.ny + a.ny) % a.ny;
-        }
-        const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
-        const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
-        const int64_t row = (int64_t)y * a.sy, rm = (int64_t)ym * a.sy, rp = (int64_t)yp * a.sy;
-        f[0] = s[0 * P + row + xm];
-        f[1] = s[1 * P + row + xp];
-        f[2] = s[2 * P + rm + x];
-        f[3] = s[3 * P + rp + x];
-        f[4] = s[4 * P + row + xm];
-        f[5] = s[5 * P + row + xp];
-        f[6] = s[6 * P + rm + x];
-        f[7] = s[7 * P + rp + x];
-        f[8] = s[8 * P + row + x];
-        f[9] = s[9 * P + row + x];
-        f[10] = s[10 * P + row + x];
-        eps = a.eps[row + x];
-        cell_update2d<T, POL>(a, t, x, y, eps, f, owned);
-        return true;
-    };
-
-    // step t: the thread's own tile cells ...
+    // step t on the thread's own segment
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
-        const int i = tid + 256 * it;
-        const int ex = i % TX + 1, ey = i / TX + 1;
-        T f[11], eps = T(1);
-        const bool ok = step_a(ex, ey, f, eps);
+        const int seg = tid + 256 * it;
+        const int sx = (seg % TPR) * VX, sy = seg / TPR;
+        const int x = x0 + sx, y = y0 + sy;
+        const int yf = fold(y, a.ny, a.W[1]);
+        T v[11][VX], e[VX];
+        pull_row<T, VX>(a, x, yf, v, e);
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
-            if (ok) lds[p][ey][ex] = f[p];
-        zp[it][0] = f[8];
-        zp[it][1] = f[9];
-        zp[it][2] = f[10];
-        ep[it] = eps;
+        for (int k = 0; k < VX; ++k) {
+            const int xf = fold(x + k, a.nx, a.W[0]);
+            ep[it][k] = e[k];
+            ip[it][k] = T(1) / e[k];
+            sg[it][k] = sigma2d<T>(a, xf, yf);
+            T f[11];
+#pragma unroll
+            for (int i = 0; i < 11; ++i) f[i] = v[i][k];
+            cell_update2d<T, POL>(a, s0, xf, yf, e[k], ip[it][k], sg[it][k], f, x + k < a.nx && y < a.ny);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) v[i][k] = f[i];
+            zp[it][0][k] = f[8];
+            zp[it][1][k] = f[9];
+            zp[it][2][k] = f[10];
+        }
+        lds_store<T, VX>(&L.xm[0][sy][VX + sx], v[0]);
+        lds_store<T, VX>(&L.xm[1][sy][VX + sx], v[4]);
+        lds_store<T, VX>(&L.xp[0][sy][sx], v[1]);
+        lds_store<T, VX>(&L.xp[1][sy][sx], v[5]);
+        lds_store<T, VX>(&L.ym[0][sy + 1][sx], v[2]);
+        lds_store<T, VX>(&L.ym[1][sy + 1][sx], v[6]);
+        lds_store<T, VX>(&L.yp[0][sy][sx], v[3]);
+        lds_store<T, VX>(&L.yp[1][sy][sx], v[7]);
     }
-    // ... and the ring around the tile (only its streaming planes are used)
-    if (tid < NR) {
-        int ex, ey;
-        if (tid < EX) { ex = tid; ey = 0; }
-        else if (tid < 2 * EX) { ex = tid - EX; ey = EY - 1; }
-        else if (tid < 2 * EX + TY) { ex = 0; ey = tid - 2 * EX + 1; }
-        else { ex = EX - 1; ey = tid - 2 * EX - TY + 1; }
-        T f[11], eps;
-        if (step_a(ex, ey, f, eps)) {
+    // step t on the ring: segments of the rows above and below the tile, and
+    // a segment next to each tile row on the left (its last cell is used)
+    // and on the right (its first cell is used)
+    for (int r = tid; r < NR; r += 256) {
+        int x, y;
+        if (r < TPR) { x = x0 + r * VX; y = y0 - 1; }
+        else if (r < 2 * TPR) { x = x0 + (r - TPR) * VX; y = y0 + TY; }
+        else if (r < 2 * TPR + TY) { x = x0 - VX; y = y0 + (r - 2 * TPR); }
+        else { x = x0 + TX; y = y0 + (r - 2 * TPR - TY); }
+        const int yf = fold(y, a.ny, a.W[1]);
+        T v[11][VX], e[VX];
+        pull_row<T, VX>(a, x, yf, v, e);
 #pragma unroll
-            for (int p = 0; p < 8; ++p) lds[p][ey][ex] = f[p];
+        for (int k = 0; k < VX; ++k) {
+            const int xf = fold(x + k, a.nx, a.W[0]);
+            T f[11];
+#pragma unroll
+            for (int i = 0; i < 11; ++i) f[i] = v[i][k];
+            cell_update2d<T, POL>(a, s0, xf, yf, e[k], T(1) / e[k], sigma2d<T>(a, xf, yf), f, false);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) v[i][k] = f[i];
+        }
+        if (r < TPR) {
+            lds_store<T, VX>(&L.ym[0][0][x - x0], v[2]);
+            lds_store<T, VX>(&L.ym[1][0][x - x0], v[6]);
+        } else if (r < 2 * TPR) {
+            lds_store<T, VX>(&L.yp[0][TY][x - x0], v[3]);
+            lds_store<T, VX>(&L.yp[1][TY][x - x0], v[7]);
+        } else if (r < 2 * TPR + TY) {
+            L.xm[0][y - y0][VX - 1] = v[0][VX - 1];
+            L.xm[1][y - y0][VX - 1] = v[4][VX - 1];
+        } else {
+            L.xp[0][y - y0][TX] = v[1][0];
+            L.xp[1][y - y0][TX] = v[5][0];
         }
     }
     __syncthreads();
 
-    // step t+1 on the thread's own tile cells
-    T *d = a.dst;
+    // step t+1 on the thread's own segments
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
-        const int i = tid + 256 * it;
-        const int ox = i % TX, oy = i / TX;
-        const int x = x0 + ox, y = y0 + oy;
+        const int seg = tid + 256 * it;
+        const int sx = (seg % TPR) * VX, sy = seg / TPR;
+        const int x = x0 + sx, y = y0 + sy;
         if (x >= a.nx || y >= a.ny) continue;
-        const int ex = ox + 1, ey = oy + 1;
-        const int exm = (a.W[0] && x == 0) ? ex : ex - 1;
-        const int exp = (a.W[0] && x == a.nx - 1) ? ex : ex + 1;
-        const int eym = (a.W[1] && y == 0) ? ey : ey - 1;
-        const int eyp = (a.W[1] && y == a.ny - 1) ? ey : ey + 1;
-        T f[11];
-        f[0] = lds[0][ey][exm];
-        f[4] = lds[4][ey][exm];
-        f[1] = lds[1][ey][exp];
-        f[5] = lds[5][ey][exp];
-        f[2] = lds[2][eym][ex];
-        f[6] = lds[6][eym][ex];
-        f[3] = lds[3][eyp][ex];
-        f[7] = lds[7][eyp][ex];
-        f[8] = zp[it][0];
-        f[9] = zp[it][1];
-        f[10] = zp[it][2];
-        const int64_t c = (int64_t)y * a.sy + x;
-        cell_update2d<T, POL>(a, t + 1, x, y, ep[it], f);
+        T v[11][VX];
+        {   // +x movers from the left neighbour (own value on an absorbing left face)
+            T o0[VX], o4[VX];
+            lds_load<T, VX>(o0, &L.xm[0][sy][VX + sx]);
+            lds_load<T, VX>(o4, &L.xm[1][sy][VX + sx]);
+            const bool clamp = a.W[0] && x == 0;
+            v[0][0] = clamp ? o0[0] : L.xm[0][sy][VX + sx - 1];
+            v[4][0] = clamp ? o4[0] : L.xm[1][sy][VX + sx - 1];
 #pragma unroll
-        for (int p = 0; p < 11; ++p) d[p * P + c] = f[p];
+            for (int k = 1; k < VX; ++k) {
+                v[0][k] = o0[k - 1];
+                v[4][k] = o4[k - 1];
+            }
+        }
+        {   // -x movers from the right neighbour (own value on an absorbing right face)
+            T o1[VX], o5[VX];
+            lds_load<T, VX>(o1, &L.xp[0][sy][sx]);
+            lds_load<T, VX>(o5, &L.xp[1][sy][sx]);
+            const T n1 = L.xp[0][sy][sx + VX], n5 = L.xp[1][sy][sx + VX];
+#pragma unroll
+            for (int k = 0; k < VX; ++k) {
+                const bool clamp = a.W[0] && x + k == a.nx - 1;
+                v[1][k] = clamp ? o1[k] : (k + 1 < VX ? o1[(k + 1) % VX] : n1);
+                v[5][k] = clamp ? o5[k] : (k + 1 < VX ? o5[(k + 1) % VX] : n5);
+            }
+        }
+        {   // +y movers from the row above, -y movers from the row below
+            const int rm = (a.W[1] && y == 0) ? sy + 1 : sy;
+            const int rp = (a.W[1] && y == a.ny - 1) ? sy : sy + 1;
+            lds_load<T, VX>(v[2], &L.ym[0][rm][sx]);
+            lds_load<T, VX>(v[6], &L.ym[1][rm][sx]);
+            lds_load<T, VX>(v[3], &L.yp[0][rp][sx]);
+            lds_load<T, VX>(v[7], &L.yp[1][rp][sx]);
+        }
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const int xf = fold(x + k, a.nx, a.W[0]);
+            T f[11];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = v[i][k];
+            f[8] = zp[it][0][k];
+            f[9] = zp[it][1][k];
+            f[10] = zp[it][2][k];
+            cell_update2d<T, POL>(a, s1, xf, y, ep[it][k], ip[it][k], sg[it][k], f, x + k < a.nx);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) v[i][k] = f[i];
+        }
+        store_row<T, VX>(a, x, y, v);
     }
 }
 
+// XCD-aware tile order.  The work-groups of a launch are dealt round-robin
+// to the 8 XCDs, each with its own L2: block b runs on XCD b mod 8.  Giving
+// every XCD one contiguous band of row-major tiles keeps a tile and the
+// neighbours whose edge rows and columns it re-reads in the same L2.
+__device__ inline int xcd_tile(int b, int ntiles) {
+    constexpr int NXCD = 8;
+    const int xcd = b % NXCD, j = b / NXCD;
+    const int q = ntiles / NXCD, r = ntiles % NXCD;
+    return xcd * q + (xcd < r ? xcd : r) + j;
+}
+
+// One block per tile, a 1-D grid of tiles_x * tiles_y blocks.
 template <typename T, int POL, int TX, int TY>
-__global__ void __launch_bounds__(256) k_step2d_x2(StepArgs<T> a) {
-    // only the 8 streaming planes are exchanged through LDS; the z-pair and
-    // eps of a thread's own cells stay in its registers between the steps
-    __shared__ T lds[8][TY + 2][TX + 2];
-    step2d_x2_tile<T, POL, TX, TY>(a, lds, blockIdx.x * TX, blockIdx.y * TY, step_time(a.t_base, a.t_off));
+__global__ void __launch_bounds__(256, 4) k_step2d_x2(StepArgs<T> a) {
+    __shared__ X2Lds<T, TX, TY> lds;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    step2d_x2_tile<T, POL, TX, TY>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
+                                   step_time(a.t_base, a.t_off));
 }
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).
@@ -570,14 +733,16 @@ __global__ void __launch_bounds__(256) k_step2d_tile_batch(const StepArgs<T> *__
                                                            const int *__restrict__ tile_inst,
                                                            const int *__restrict__ tile_first, int ntiles,
                                                            const int64_t *t_base, int64_t t_off) {
+    constexpr int VX = X2Lds<T, TX, TY>::VX, TPR = TX / VX;
     const int64_t t = step_time(t_base, t_off);
     for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
         const int inst = tile_inst[w];
         const StepArgs<T> &a = descs[inst];
         const int local = w - tile_first[inst];
         const int x0 = (local % a.tiles_x) * TX, y0 = (local / a.tiles_x) * TY;
-        for (int i = threadIdx.x; i < TX * TY; i += blockDim.x)
-            step2d_cells<T, POL, 1>(a, x0 + i % TX, y0 + i / TX, t);
+        const StepConst st = step_const(a, t);
+        for (int seg = threadIdx.x; seg < TPR * TY; seg += blockDim.x)
+            step2d_cells<T, POL, VX>(a, x0 + (seg % TPR) * VX, y0 + seg / TPR, st);
     }
 }
 
@@ -585,11 +750,11 @@ __global__ void __launch_bounds__(256) k_step2d_tile_batch(const StepArgs<T> *__
 // (instance, tile) work list (tiles of TX x TY cells); a barrier separates
 // consecutive tiles of a block because they share the LDS tile.
 template <typename T, int POL, int TX, int TY>
-__global__ void __launch_bounds__(256) k_step2d_x2_batch(const StepArgs<T> *__restrict__ descs,
+__global__ void __launch_bounds__(256, 4) k_step2d_x2_batch(const StepArgs<T> *__restrict__ descs,
                                                          const int *__restrict__ tile_inst,
                                                          const int *__restrict__ tile_first, int ntiles,
                                                          const int64_t *t_base, int64_t t_off) {
-    __shared__ T lds[8][TY + 2][TX + 2];
+    __shared__ X2Lds<T, TX, TY> lds;
     const int64_t t = step_time(t_base, t_off);
     for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
         const int inst = tile_inst[w];
@@ -651,25 +816,26 @@ __device__ inline void equilibrium3d(const T E[3], const T H[3], T eps, T scale,
 }
 
 template <typename T>
-__device__ inline void cell_update3d(const StepArgs<T> &a, int64_t t, int x, int y, int z, T eps, T f[27]) {
+__device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst &st, int x, int y, int z, T eps,
+                                     T f[27]) {
     const T inv_eps = T(1) / eps;
     T E[3], H[3];
     fields3d(f, inv_eps, E, H);
-    if (a.dft_on) {
+    if (st.dft) {
         double Ed[3] = {E[0], E[1], E[2]}, Hd[3] = {H[0], H[1], H[2]};
-        dft_accumulate(a, t, 3, x, y, z, Ed, Hd);
+        dft_accumulate(a, st, 3, x, y, z, Ed, Hd);
     }
     T q[27];
     equilibrium3d(E, H, eps, T(2), q);
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = q[i] - f[i];
-    const T sig = fmax(fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max),
-                            sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max)),
-                       sigma_axis<T>(z, a.nz, a.W[2], a.sigma_max));
+    const T sig = fmax(fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
+                            sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max)),
+                       sigma_axis<T>(z, a.nz, a.W[2], a.inv_w[2], a.sigma_max));
     if (sig > T(0)) {
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
-            const T w = (T)plane_wave(a, t, x, y, z);
+            const T w = (T)plane_wave<T, 3>(a, st, x, y, z);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 Er[k] = w * (T)a.ehat[k];
@@ -692,11 +858,11 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
     const int ym = pull_lo(y, a.ny, a.W[1]), yp = pull_hi(y, a.ny, a.W[1]);
     const int zm = pull_lo(z, a.nz, a.W[2]), zp = pull_hi(z, a.nz, a.W[2]);
     const int64_t P = a.plane;
-    const int64_t base = (int64_t)z * a.sz + (int64_t)y * a.sy;
+    const uint32_t sy = (uint32_t)a.sy, sz = (uint32_t)a.sz;
+    const uint32_t base = (uint32_t)z * sz + (uint32_t)y * sy;
     // row start of the source of each direction (x handled separately)
-    const int64_t srow[6] = {base, base, (int64_t)z * a.sz + (int64_t)ym * a.sy,
-                             (int64_t)z * a.sz + (int64_t)yp * a.sy, (int64_t)zm * a.sz + (int64_t)y * a.sy,
-                             (int64_t)zp * a.sz + (int64_t)y * a.sy};
+    const uint32_t srow[6] = {base, base, (uint32_t)z * sz + (uint32_t)ym * sy, (uint32_t)z * sz + (uint32_t)yp * sy,
+                              (uint32_t)zm * sz + (uint32_t)y * sy, (uint32_t)zp * sz + (uint32_t)y * sy};
     const T *s = a.src;
     const bool full = x0 + VX <= a.nx;
     const bool inner = full && x0 > 0 && x0 + VX < a.nx;
@@ -704,18 +870,18 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
     if (inner) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            load_shifted<T, VX>(v[k], s + k * P + base + x0 - 1);          // +x from x-1
-            load_shifted<T, VX>(v[4 + k], s + (4 + k) * P + base + x0 + 1);  // -x from x+1
+            load_shifted<T, VX>(v[k], at(s + k * P, base + x0 - 1));            // +x from x-1
+            load_shifted<T, VX>(v[4 + k], at(s + (4 + k) * P, base + x0 + 1));  // -x from x+1
         }
     } else {
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
             const int x = x0 + j < a.nx ? x0 + j : a.nx - 1;
-            const int xm = pull_lo(x, a.nx, a.W[0]), xp = pull_hi(x, a.nx, a.W[0]);
+            const uint32_t xm = (uint32_t)pull_lo(x, a.nx, a.W[0]), xp = (uint32_t)pull_hi(x, a.nx, a.W[0]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                v[k][j] = s[k * P + base + xm];
-                v[4 + k][j] = s[(4 + k) * P + base + xp];
+                v[k][j] = *at(s + k * P, base + xm);
+                v[4 + k][j] = *at(s + (4 + k) * P, base + xp);
             }
         }
     }
@@ -723,43 +889,43 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
 #pragma unroll
         for (int d = 2; d < 6; ++d)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) load_aligned<T, VX>(v[4 * d + k], s + (4 * d + k) * P + srow[d] + x0);
+            for (int k = 0; k < 4; ++k) load_aligned<T, VX>(v[4 * d + k], at(s + (4 * d + k) * P, srow[d] + x0));
 #pragma unroll
-        for (int k = 0; k < 3; ++k) load_aligned<T, VX>(v[24 + k], s + (24 + k) * P + base + x0);
-        load_aligned<T, VX>(e, a.eps + base + x0);
+        for (int k = 0; k < 3; ++k) load_aligned<T, VX>(v[24 + k], at(s + (24 + k) * P, base + x0));
+        load_aligned<T, VX>(e, at(a.eps, base + x0));
     } else {
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
-            const int x = x0 + j < a.nx ? x0 + j : a.nx - 1;
+            const uint32_t x = (uint32_t)(x0 + j < a.nx ? x0 + j : a.nx - 1);
 #pragma unroll
             for (int d = 2; d < 6; ++d)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) v[4 * d + k][j] = s[(4 * d + k) * P + srow[d] + x];
+                for (int k = 0; k < 4; ++k) v[4 * d + k][j] = *at(s + (4 * d + k) * P, srow[d] + x);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) v[24 + k][j] = s[(24 + k) * P + base + x];
-            e[j] = a.eps[base + x];
+            for (int k = 0; k < 3; ++k) v[24 + k][j] = *at(s + (24 + k) * P, base + x);
+            e[j] = *at(a.eps, base + x);
         }
     }
-    const int64_t t = step_time(a.t_base, a.t_off);
+    const StepConst st = step_const(a, step_time(a.t_base, a.t_off));
 #pragma unroll
     for (int j = 0; j < VX; ++j) {
         T f[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) f[i] = v[i][j];
-        cell_update3d<T>(a, t, x0 + j, y, z, e[j], f);
+        cell_update3d<T>(a, st, x0 + j, y, z, e[j], f);
 #pragma unroll
         for (int i = 0; i < 27; ++i) v[i][j] = f[i];
     }
     T *d = a.dst;
     if (full) {
 #pragma unroll
-        for (int i = 0; i < 27; ++i) store_aligned<T, VX>(d + i * P + base + x0, v[i]);
+        for (int i = 0; i < 27; ++i) store_aligned<T, VX>(at(d + i * P, base + x0), v[i]);
     } else {
 #pragma unroll
         for (int j = 0; j < VX; ++j)
             if (x0 + j < a.nx)
 #pragma unroll
-                for (int i = 0; i < 27; ++i) d[i * P + base + x0 + j] = v[i][j];
+                for (int i = 0; i < 27; ++i) *at(d + i * P, base + x0 + j) = v[i][j];
     }
 }
 
@@ -781,6 +947,7 @@ struct AdjArgs {
     int nx, ny;
     int64_t sy, plane;
     int W[2];
+    T inv_w[2];
     T sigma_max;
     const T *__restrict__ src;   // mu(t+1)
     T *__restrict__ dst;         // mu(t)
@@ -884,7 +1051,8 @@ __global__ void __launch_bounds__(256) k_adjoint2d(AdjArgs<T> a) {
     // K^T lambda = (1 - sigma)(2 L^T Q^T lambda - lambda)
     T o[11];
     fields2d_T<T, POL>(u, eps, inv_eps, o);
-    const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.sigma_max), sigma_axis<T>(y, a.ny, a.W[1], a.sigma_max));
+    const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
+                       sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max));
 #pragma unroll
     for (int i = 0; i < 11; ++i) l[i] = (T(1) - sig) * (T(2) * o[i] - l[i]);
     // objective source L^T dJ/dF at contour nodes inside the DFT window

@@ -82,6 +82,8 @@ struct lbm_em {
     lbm_em_plane_wave pw{};
     double hhat[3] = {0, 0, 0};
     int period = 0;
+    double *wtab = nullptr;             // phase tables of the source (StepArgs::wave_*)
+    int batch_refs = 0;                 // batches that hold this handle
     // contour DFT
     bool dft_set = false;
     Box box{};
@@ -150,7 +152,10 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     a.sy = h->sy;
     a.sz = h->sz;
     a.plane = h->plane;
-    for (int k = 0; k < 3; ++k) a.W[k] = h->cfg.absorb[k];
+    for (int k = 0; k < 3; ++k) {
+        a.W[k] = h->cfg.absorb[k];
+        a.inv_w[k] = a.W[k] > 0 ? T(1) / (T)a.W[k] : T(0);
+    }
     a.sigma_max = (T)h->cfg.sigma_max;
     a.src = (const T *)src;
     a.dst = (T *)dst;
@@ -160,13 +165,16 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     if (h->src_on) {
         a.amp = h->pw.amplitude;
         a.t_ramp = h->pw.ramp_periods * (double)h->period;
-        a.inv_lam = 1.0 / h->pw.lambda;
         for (int k = 0; k < 3; ++k) {
-            a.khat[k] = h->pw.khat[k];
             a.ehat[k] = h->pw.ehat[k];
             a.hhat[k] = h->hhat[k];
-            a.rc[k] = h->pw.center[k];
         }
+        const double2 *w = (const double2 *)h->wtab;
+        a.wave_t = w;
+        a.wave_x = w + h->period;
+        a.wave_y = a.wave_x + h->cfg.nx;
+        a.wave_z = a.wave_y + h->cfg.ny;
+        a.ramp = (const double *)(a.wave_z + h->cfg.nz);
     }
     a.dft_on = h->dft_set ? 1 : 0;
     a.box = h->box;
@@ -218,12 +226,20 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
 }
 
 // Two steps in one launch (2-D): reads src, writes f*(t+1) to dst.
+// Two-step tiles: TX x TY cells, TX a multiple of the 16-byte segment and
+// TX*TY a multiple of 256 segments' worth (see x2_tile_ok).
+#define LBM_X2_TILES_F32(M) M(64, 16) M(128, 8) M(256, 4) M(32, 32)
+#define LBM_X2_TILES_F64(M) M(32, 16) M(64, 8) M(128, 4) M(16, 32)
+
 template <typename T, int POL>
-void launch_step2_pol(const StepArgs<T> &a, int tx, int ty, hipStream_t s) {
-    dim3 grid((unsigned)((a.nx + tx - 1) / tx), (unsigned)((a.ny + ty - 1) / ty), 1);
+void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
+    a.tiles_x = (a.nx + tx - 1) / tx;
+    a.tiles_y = (a.ny + ty - 1) / ty;
+    dim3 grid((unsigned)(a.tiles_x * a.tiles_y), 1, 1);
 #define LBM_X2(TX, TY) \
     if (tx == TX && ty == TY) { hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(256), 0, s, a); return; }
-    LBM_X2(64, 16) LBM_X2(64, 8) LBM_X2(64, 4) LBM_X2(32, 16) LBM_X2(32, 8) LBM_X2(16, 16)
+    if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_X2) }
+    else { LBM_X2_TILES_F64(LBM_X2) }
 #undef LBM_X2
     fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
@@ -247,10 +263,11 @@ void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_
     else launch_step2_t<double>(h, src, dst, t_base, t_off, s, dft);
 }
 
-bool fused_tile_ok(int tx, int ty) {
-    static const int ok[][2] = {{64, 16}, {64, 8}, {64, 4}, {32, 16}, {32, 8}, {16, 16}};
-    for (auto &o : ok)
-        if (o[0] == tx && o[1] == ty) return true;
+bool fused_tile_ok(int precision, int tx, int ty) {
+#define LBM_X2_OK(TX, TY) if (tx == TX && ty == TY) return true;
+    if (precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_OK) }
+    else { LBM_X2_TILES_F64(LBM_X2_OK) }
+#undef LBM_X2_OK
     return false;
 }
 
@@ -404,7 +421,8 @@ void launch_batch_x2_pol(const lbm_em_batch_s *b, const BatchGroup &g, int par, 
                                g.tile_inst, g.tile_first, g.ntiles, t_base, t_off);                            \
         return;                                                                                                \
     }
-    LBM_X2B(64, 16) LBM_X2B(64, 8) LBM_X2B(64, 4) LBM_X2B(32, 16) LBM_X2B(32, 8) LBM_X2B(16, 16)
+    if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_X2B) }
+    else { LBM_X2_TILES_F64(LBM_X2B) }
 #undef LBM_X2B
     fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
@@ -453,6 +471,7 @@ void free_batch(lbm_em_batch_s *b) {
     else (void)hipDeviceSynchronize();
     free_groups(b);
     hfree(b->t_dev);
+    for (lbm_em *h : b->hs) --h->batch_refs;
     delete b;
 }
 
@@ -505,7 +524,10 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
         b->ftx = h0->ftx;
         b->fty = h0->fty;
         b->budget = (int64_t)192 << 20;
-        for (int i = 0; i < count; ++i) b->hs.push_back(hs[i]);
+        for (int i = 0; i < count; ++i) {
+            b->hs.push_back(hs[i]);
+            ++hs[i]->batch_refs;
+        }
         hip_check(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev), "attribute");
         b->cus = std::max(1, b->cus);
         hip_check(hipMalloc(&b->t_dev, 64), "hipMalloc batch");
@@ -658,8 +680,10 @@ void launch_adjoint(const lbm_em *h, const void *src, void *dst, int64_t t, cons
     a.ny = h->cfg.ny;
     a.sy = h->sy;
     a.plane = h->plane;
-    a.W[0] = h->cfg.absorb[0];
-    a.W[1] = h->cfg.absorb[1];
+    for (int k = 0; k < 2; ++k) {
+        a.W[k] = h->cfg.absorb[k];
+        a.inv_w[k] = a.W[k] > 0 ? T(1) / (T)a.W[k] : T(0);
+    }
     a.sigma_max = (T)h->cfg.sigma_max;
     a.src = (const T *)src;
     a.dst = (T *)dst;
@@ -695,6 +719,7 @@ void free_handle(lbm_em *h) {
     hfree(h->t_dev);
     hfree(h->ck);
     hfree(h->adj_P);
+    hfree(h->wtab);
     delete h;
 }
 
@@ -718,6 +743,11 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
         if (c.nx < 1 || c.ny < 1 || c.nz < 1) fail(LBM_EM_EINVAL, "grid sizes must be >= 1");
         if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 31)
             fail(LBM_EM_EINVAL, "more than 2^31 cells");
+        {   // kernels address a population plane with 32-bit byte offsets
+            const int64_t esz = c.precision == LBM_EM_FP64 ? 8 : 4;
+            if (round_up(c.nx, 64) * c.ny * c.nz * esz >= (int64_t)1 << 32)
+                fail(LBM_EM_EINVAL, "grid too large: one population plane (x padded to 64) must stay below 4 GiB");
+        }
         if (c.pol != LBM_EM_TM && c.pol != LBM_EM_TE && c.pol != LBM_EM_3D)
             fail(LBM_EM_EINVAL, "pol must be LBM_EM_TM, LBM_EM_TE or LBM_EM_3D");
         if (c.pol != LBM_EM_3D && c.nz != 1) fail(LBM_EM_EINVAL, "TM/TE runs need nz == 1");
@@ -776,6 +806,7 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
 lbm_em_status lbm_em_destroy(lbm_em_handle h) {
     return guarded([&] {
         check_handle(h);
+        if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         free_handle(h);
     });
 }
@@ -842,12 +873,47 @@ lbm_em_status lbm_em_set_source(lbm_em_handle hh, const lbm_em_plane_wave *pw) {
             if (h->cfg.pol == LBM_EM_TE && std::fabs(pw->ehat[2]) > 1e-12)
                 fail(LBM_EM_EINVAL, "TE needs ehat in the xy plane");
         }
+        const double t_ramp = pw->ramp_periods * T;
+        if (t_ramp > 1e7) fail(LBM_EM_EINVAL, "ramp longer than 1e7 steps");
+        if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
+        select_device(h);
+        // phase tables: e^{2 pi j k/T} (k < T), e^{2 pi j u_a} per column,
+        // row and slab (u_a = khat_a (a - center_a) / lambda, reduced to
+        // [0, 1) before the sine), and the ramp g(t) = sin^2(pi t / (2 t_ramp))
+        const int period = (int)std::lround(T);
+        const int nramp = (int)std::ceil(t_ramp);
+        const int n[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz};
+        std::vector<double> tab;
+        tab.reserve(2 * ((size_t)period + n[0] + n[1] + n[2]) + nramp);
+        auto unit = [&](double u) {
+            u -= std::floor(u);
+            tab.push_back(std::cos(2.0 * M_PI * u));
+            tab.push_back(std::sin(2.0 * M_PI * u));
+        };
+        for (int k = 0; k < period; ++k) unit((double)k / (double)period);
+        for (int ax = 0; ax < 3; ++ax)
+            for (int i = 0; i < n[ax]; ++i) unit(pw->khat[ax] * ((double)i - pw->center[ax]) / pw->lambda);
+        for (int i = 0; i < nramp; ++i) {
+            const double sr = std::sin(M_PI * (double)i / (2.0 * t_ramp));
+            tab.push_back(sr * sr);
+        }
+        double *dtab = nullptr;
+        hip_check(hipMalloc(&dtab, tab.size() * sizeof(double)), "hipMalloc source tables");
+        hipError_t e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) {
+            hfree(dtab);
+            hip_check(e, "H2D source tables");
+        }
+        sync(h);            // no launch in flight still reads the old tables
+        hfree(h->wtab);
+        h->wtab = dtab;
         h->pw = *pw;
-        const double *k = pw->khat, *e = pw->ehat;
-        h->hhat[0] = k[1] * e[2] - k[2] * e[1];
-        h->hhat[1] = k[2] * e[0] - k[0] * e[2];
-        h->hhat[2] = k[0] * e[1] - k[1] * e[0];
-        h->period = (int)std::lround(T);
+        const double *k = pw->khat, *ev = pw->ehat;
+        h->hhat[0] = k[1] * ev[2] - k[2] * ev[1];
+        h->hhat[1] = k[2] * ev[0] - k[0] * ev[2];
+        h->hhat[2] = k[0] * ev[1] - k[1] * ev[0];
+        h->period = period;
         h->src_on = true;
         drop_graphs(h);
     });
@@ -859,6 +925,7 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle hh, const int32_t lo[3], const int32
         lbm_em *h = check_handle(hh);
         if (!lo || !hi) fail(LBM_EM_EINVAL, "null box");
         if (!h->src_on) fail(LBM_EM_ESTATE, "set the source before the contour (the DFT frequency is the source's)");
+        if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         const int n[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz};
         for (int a = 0; a < h->dim; ++a)
             if (lo[a] < 1 || hi[a] > n[a] - 2 || hi[a] - lo[a] < 2)
@@ -971,8 +1038,10 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
         if (steps_per_launch != 1 && steps_per_launch != 2) fail(LBM_EM_EINVAL, "steps_per_launch must be 1 or 2");
         if (steps_per_launch == 2 && h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "two steps per launch is 2-D only");
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
-            if (!fused_tile_ok(tile_x, tile_y))
-                fail(LBM_EM_EINVAL, "two-step tile must be 64x16, 64x8, 64x4, 32x16, 32x8 or 16x16");
+            if (!fused_tile_ok(h->cfg.precision, tile_x, tile_y))
+                fail(LBM_EM_EINVAL, h->cfg.precision == LBM_EM_FP32
+                                        ? "FP32 two-step tile must be 64x16, 128x8, 256x4 or 32x32"
+                                        : "FP64 two-step tile must be 32x16, 64x8, 128x4 or 16x32");
             h->ftx = tile_x;
             h->fty = tile_y;
         }
@@ -1013,8 +1082,10 @@ lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_u
             for (auto &sh : shapes)
                 if (tile_ok(h, vx, sh[0], sh[1])) cands.push_back({1, vx, sh[0], sh[1]});
         if (h->dim == 2) {
-            static const int ft[][2] = {{64, 16}, {64, 8}, {64, 4}, {32, 16}, {32, 8}, {16, 16}};
-            for (auto &f : ft) cands.push_back({2, f[0], f[1], 0});
+#define LBM_X2_CAND(TX, TY) cands.push_back({2, TX, TY, 0});
+            if (h->cfg.precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_CAND) }
+            else { LBM_X2_TILES_F64(LBM_X2_CAND) }
+#undef LBM_X2_CAND
         }
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");

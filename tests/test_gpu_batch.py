@@ -117,3 +117,15 @@ def test_batch_rejects_mismatched_handles(lib):
         lib.step_many([a, d], 1)
     with pytest.raises(LbmEmError):
         lib.step_many([a, a], 1)
+    # a handle held by a batch can be neither destroyed nor re-sourced
+    g = [_make(lib, c[0], "fp32"), _make(lib, c[1], "fp32")]
+    bb = lib.Batch(g)
+    with pytest.raises(LbmEmError):
+        g[0].close()
+    with pytest.raises(LbmEmError):
+        g[1].set_source(c[1].lam, [1.0, 0, 0], [0, 0, 1.0], 1.0, 1.0)
+    bb.step(2)
+    bb.close()
+    g[1].set_source(c[1].lam, [1.0, 0, 0], [0, 0, 1.0], 1.0, 1.0)
+    for s in g:
+        s.close()

@@ -282,37 +282,49 @@ def test_autotune_verifies_and_does_not_advance(gpu):
         sims[0].set_tile(1, 100, 1)
 
 
+X2_TILES = {"fp32": [(64, 16), (128, 8), (256, 4), (32, 32)],
+            "fp64": [(32, 16), (64, 8), (128, 4), (16, 32)]}
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("pol", ["TM", "TE"])
 def test_two_steps_per_launch_is_bit_identical(gpu, prec, pol):
     """Temporal blocking (two steps per launch through LDS) reproduces one
-    step per launch bit for bit: fields and DFT phasors, on a ragged grid
-    with one periodic and one absorbing axis, odd step counts (graph chunks
-    + fused pairs + a single trailing step), and on a 1-row periodic grid."""
+    step per launch bit for bit: fields and DFT phasors, for every two-step
+    tile, on a ragged grid with one periodic and one absorbing axis (both
+    ways round, so ragged tiles meet both the wrap and the clamp), odd step
+    counts (graph chunks + fused pairs + a single trailing step), and on a
+    1-row grid and a periodic grid smaller than one segment."""
     nx, ny = 203, 77
     rng = np.random.default_rng(5)
     eps = 1.0 + (rng.random((1, ny, nx)) < 0.2) * rng.uniform(0.2, 3.0, (1, ny, nx))
     eps[:, :, :12] = 1.0
     eps[:, :, -12:] = 1.0
+    eps[:, :10, :] = 1.0
+    eps[:, -10:, :] = 1.0
     th = np.deg2rad(25.0)
     kh = [np.cos(th), np.sin(th), 0.0]
     eh = [0, 0, 1.0] if pol == "TM" else [-np.sin(th), np.cos(th), 0.0]
-    runs = []
-    for fuse, tile in ((1, (0, 0)), (2, (64, 16)), (2, (32, 8)), (2, (16, 16)), (2, (64, 4))):
-        s = gpu(nx, ny, 1, pol=pol, precision=prec, absorb=(11, 0, 0), sigma_max=W.SIGMA_MAX)
-        s.set_permittivity(eps)
-        s.set_source(10.0, kh, eh, 1.0, 1.0)
-        s.set_ntff((60, 20, 0), (140, 56, 0), 100, 30)
-        s.set_fusion(fuse, tile)
-        assert s.get_fusion() == fuse
-        for n in (3, 131, 1):
-            s.step(n)
-        runs.append((s.fields(), s.phasors()))
-        say("fusion", prec, pol, fuse, s.t)
-    (E1, H1), (X1, p1) = runs[0]
-    for (E2, H2), (X2, p2) in runs[1:]:
-        assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
-        assert np.array_equal(X1, X2) and np.array_equal(p1, p2)
+    tiles = X2_TILES[prec]
+    for absorb in ((11, 0, 0), (0, 9, 0)):
+        runs = []
+        for fuse, tile in [(1, (0, 0))] + [(2, t) for t in tiles]:
+            s = gpu(nx, ny, 1, pol=pol, precision=prec, absorb=absorb, sigma_max=W.SIGMA_MAX)
+            s.set_permittivity(eps)
+            s.set_source(10.0, kh, eh, 1.0, 1.0)
+            s.set_ntff((60, 20, 0), (140, 56, 0), 100, 30)
+            s.set_fusion(fuse, tile)
+            assert s.get_fusion() == fuse
+            for n in (3, 131, 1):
+                s.step(n)
+            runs.append((s.fields(), s.phasors()))
+            say("fusion", prec, pol, absorb, fuse, tile, s.t)
+            s.close()
+        (E1, H1), (X1, p1) = runs[0]
+        assert np.abs(E1).max() > 0
+        for (E2, H2), (X2, p2) in runs[1:]:
+            assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
+            assert np.array_equal(X1, X2) and np.array_equal(p1, p2)
     # a single periodic row (1-D planar problem) and a tiny periodic grid
     for n in ((96, 1), (5, 4)):
         out = []
