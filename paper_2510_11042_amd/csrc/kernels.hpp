@@ -92,6 +92,10 @@ __host__ __device__ inline bool on_box(const Box &b, int dim, int x, int y, int 
 // Everything one step needs.  Per-step quantities (source ramp and phase,
 // DFT factor) are derived in the kernel from the step index t, so the same
 // launch can be replayed from a graph with t read from device memory.
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { typedef float2 type; };
+template <> struct Cplx<double> { typedef double2 type; };
+
 template <typename T>
 struct StepArgs {
     int nx, ny, nz;
@@ -108,10 +112,10 @@ struct StepArgs {
     int src_on;
     int period;                 // T = 3 lambda steps
     double amp, t_ramp;
-    double ehat[3], hhat[3];
+    T ehat[3], hhat[3];         // E and H directions of the incident wave
     const double *ramp;         // g(t) for t < t_ramp
     const double2 *wave_t;      // e^{2 pi j k / T}, k < T
-    const double2 *wave_x, *wave_y, *wave_z;   // e^{2 pi j u_a} per column / row / slab
+    const typename Cplx<T>::type *wave_x, *wave_y, *wave_z;   // e^{2 pi j u_a} per column / row / slab
     // running DFT on the contour box + probe node
     int dft_on;
     Box box;
@@ -157,21 +161,22 @@ __device__ inline int64_t step_time(const int64_t *t_base, int64_t t_off) {
 // modulo one period first), so a cell pays two or three gathers and a few
 // multiplies instead of an FP64 sine.
 // DFT: inside the window, the factor (2 / winlen) e^{-j omega t}.
+template <typename T>
 struct StepConst {
     int64_t t;
-    double gs, gc;      // g(t) E0 sin(2 pi tau), g(t) E0 cos(2 pi tau)
+    T gs, gc;           // g(t) E0 sin(2 pi tau), g(t) E0 cos(2 pi tau)
     bool dft;           // t lies in the DFT window
     double cr, ci;      // (2 / winlen) (cos, -sin)(2 pi tau)
 };
 
 template <typename T>
-__device__ inline StepConst step_const(const StepArgs<T> &a, int64_t t) {
-    StepConst c{t, 0.0, 0.0, false, 0.0, 0.0};
+__device__ inline StepConst<T> step_const(const StepArgs<T> &a, int64_t t) {
+    StepConst<T> c{t, T(0), T(0), false, 0.0, 0.0};
     if (!a.src_on) return c;             // the DFT needs the source's period too
     const double2 ph = a.wave_t[t % a.period];
     const double g = ((double)t < a.t_ramp ? a.ramp[t] : 1.0) * a.amp;
-    c.gs = g * ph.y;
-    c.gc = g * ph.x;
+    c.gs = (T)(g * ph.y);
+    c.gc = (T)(g * ph.x);
     if (a.dft_on && t >= a.win0 && t < a.win0 + a.winlen) {
         const double sc = 2.0 / (double)a.winlen;
         c.dft = true;
@@ -181,17 +186,32 @@ __device__ inline StepConst step_const(const StepArgs<T> &a, int64_t t) {
     return c;
 }
 
+// The incident value at a cell, in the arithmetic type of the run (the
+// per-axis tables are stored in it).
 template <typename T, int DIM>
-__device__ inline double plane_wave(const StepArgs<T> &a, const StepConst &sc, int x, int y, int z) {
-    const double2 px = a.wave_x[x], py = a.wave_y[y];
-    double ur = px.x * py.x - px.y * py.y, ui = px.x * py.y + px.y * py.x;
+__device__ inline T plane_wave(const StepArgs<T> &a, const StepConst<T> &sc, int x, int y, int z) {
+    const auto px = a.wave_x[x], py = a.wave_y[y];
+    T ur = px.x * py.x - px.y * py.y, ui = px.x * py.y + px.y * py.x;
     if (DIM == 3) {
-        const double2 pz = a.wave_z[z];
-        const double r = ur * pz.x - ui * pz.y;
+        const auto pz = a.wave_z[z];
+        const T r = ur * pz.x - ui * pz.y;
         ui = ur * pz.y + ui * pz.x;
         ur = r;
     }
     return sc.gs * ur - sc.gc * ui;
+}
+
+// 1 / eps: for FP32 the hardware reciprocal refined by one Newton step
+// (within an ulp of the rounded quotient, exact for eps = 1), for FP64 the
+// rounded quotient.  Every kernel uses this, so they stay bit-identical.
+template <typename T>
+__device__ inline T recip(T e) {
+    if constexpr (sizeof(T) == 4) {
+        const float r = __builtin_amdgcn_rcpf(e);
+        return __builtin_fmaf(r, __builtin_fmaf(-e, r, 1.0f), r);
+    } else {
+        return 1.0 / e;
+    }
 }
 
 // Fields at a cell from pulled 2-D reduced populations.
@@ -241,9 +261,11 @@ __device__ inline void equilibrium2d(const T F[3], T scale, T q[11]) {
 }
 
 // Accumulate the running DFT of the fields at a contour / probe node.
-template <typename T>
-__device__ inline void dft_accumulate(const StepArgs<T> &a, const StepConst &st, int dim, int x, int y,
-                                      int z, const double E[3], const double H[3]) {
+// F = (Ex, Ey, Ez, Hx, Hy, Hz); only the components in MASK (bit c for
+// F[c]) are non-zero for this field layout and are accumulated.
+template <int MASK, typename T>
+__device__ inline void dft_accumulate(const StepArgs<T> &a, const StepConst<T> &st, int dim, int x, int y,
+                                      int z, const double F[6]) {
     if (!st.dft) return;
     bool surf = on_box(a.box, dim, x, y, z);
     bool probe = x == a.probe[0] && y == a.probe[1] && z == a.probe[2];
@@ -259,12 +281,12 @@ __device__ inline void dft_accumulate(const StepArgs<T> &a, const StepConst &st,
             node = a.nnodes;
         }
         double *p = a.acc + node * 12;
-        for (int c = 0; c < 3; ++c) {
-            p[2 * c] += E[c] * cr;
-            p[2 * c + 1] += E[c] * ci;
-            p[6 + 2 * c] += H[c] * cr;
-            p[6 + 2 * c + 1] += H[c] * ci;
-        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if ((MASK >> c) & 1) {
+                p[2 * c] += F[c] * cr;
+                p[2 * c + 1] += F[c] * ci;
+            }
     }
 }
 
@@ -360,16 +382,20 @@ __device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
 // this thread, so it may add DFT samples and design-region history.
 // ---------------------------------------------------------------------------
 template <typename T, int POL>
-__device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst &st, int x, int y, T eps, T inv_eps,
-                                     T sig, T f[11], bool record) {
+__device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, T eps,
+                                     T inv_eps, T sig, T f[11], bool record) {
     const int64_t t = st.t;
     T F[3];
     fields2d<T, POL>(f, eps, inv_eps, F);
     if (st.dft && record) {
-        double E[3] = {0, 0, 0}, H[3] = {0, 0, 0};
-        if (POL == TM) { E[2] = F[0]; H[0] = F[1]; H[1] = F[2]; }
-        else { E[0] = F[0]; E[1] = F[1]; H[2] = F[2]; }
-        dft_accumulate(a, st, 2, x, y, 0, E, H);
+        double G[6] = {0, 0, 0, 0, 0, 0};
+        if (POL == TM) {
+            G[2] = F[0]; G[3] = F[1]; G[4] = F[2];
+            dft_accumulate<0x1c>(a, st, 2, x, y, 0, G);
+        } else {
+            G[0] = F[0]; G[1] = F[1]; G[5] = F[2];
+            dft_accumulate<0x23>(a, st, 2, x, y, 0, G);
+        }
     }
     if (a.hist && record && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
         // E = (sum of the E-carrying populations + (6 eps - 4) z-pair)/eps,
@@ -388,16 +414,18 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst &st, 
 #pragma unroll
     for (int i = 0; i < 11; ++i) f[i] = q[i] - f[i];
     if (sig > T(0)) {
+        // relax towards the incident wave's equilibrium (zero where eps != 1):
+        // f + sig (f_ref - f), one fused multiply-add per population
         T R[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
-            const T w = (T)plane_wave<T, 2>(a, st, x, y, 0);
-            if (POL == TM) { R[0] = w * (T)a.ehat[2]; R[1] = w * (T)a.hhat[0]; R[2] = w * (T)a.hhat[1]; }
-            else { R[0] = w * (T)a.ehat[0]; R[1] = w * (T)a.ehat[1]; R[2] = w * (T)a.hhat[2]; }
+            const T w = plane_wave<T, 2>(a, st, x, y, 0);
+            if (POL == TM) { R[0] = w * a.ehat[2]; R[1] = w * a.hhat[0]; R[2] = w * a.hhat[1]; }
+            else { R[0] = w * a.ehat[0]; R[1] = w * a.ehat[1]; R[2] = w * a.hhat[2]; }
         }
         T qr[11];
         equilibrium2d<T, POL>(R, T(1), qr);
 #pragma unroll
-        for (int i = 0; i < 11; ++i) f[i] = f[i] - sig * (f[i] - qr[i]);
+        for (int i = 0; i < 11; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
     }
 }
 
@@ -478,7 +506,7 @@ __device__ inline void store_row(const StepArgs<T> &a, int x0, int y, const T (&
 // The calling thread updates cells x0 .. x0+VX-1 of row y.
 // ---------------------------------------------------------------------------
 template <typename T, int POL, int VX>
-__device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const StepConst &st) {
+__device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const StepConst<T> &st) {
     if (x0 >= a.nx || y >= a.ny) return;
     T v[11][VX], e[VX];
     pull_row<T, VX>(a, x0, y, v, e);
@@ -488,7 +516,7 @@ __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const S
         T f[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-        cell_update2d<T, POL>(a, st, x, y, e[k], T(1) / e[k], sigma2d<T>(a, x, y), f, x0 + k < a.nx);
+        cell_update2d<T, POL>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f, x0 + k < a.nx);
 #pragma unroll
         for (int i = 0; i < 11; ++i) v[i][k] = f[i];
     }
@@ -568,11 +596,11 @@ __device__ inline void lds_store(T *p, const T (&i)[N]) { store_aligned<T, N>(p,
 
 template <typename T, int POL, int TX, int TY>
 __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t) {
-    const StepConst s0 = step_const(a, t), s1 = step_const(a, t + 1);
+    const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
     constexpr int VX = X2Lds<T, TX, TY>::VX;
     constexpr int TPR = TX / VX;             // segments per tile row
     constexpr int NI = 1;                    // segments per thread
-    constexpr int NR = 2 * TPR + 2 * TY;     // ring work items
+    constexpr int NR = 2 * TX + 2 * TY;      // ring cells
     static_assert(x2_tile_ok<T, TX, TY>(), "two-step tile shape");
     const int tid = threadIdx.x;
     T zp[NI][3][VX], ep[NI][VX], ip[NI][VX], sg[NI][VX];
@@ -590,7 +618,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         for (int k = 0; k < VX; ++k) {
             const int xf = fold(x + k, a.nx, a.W[0]);
             ep[it][k] = e[k];
-            ip[it][k] = T(1) / e[k];
+            ip[it][k] = recip(e[k]);
             sg[it][k] = sigma2d<T>(a, xf, yf);
             T f[11];
 #pragma unroll
@@ -611,40 +639,34 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         lds_store<T, VX>(&L.yp[0][sy][sx], v[3]);
         lds_store<T, VX>(&L.yp[1][sy][sx], v[7]);
     }
-    // step t on the ring: segments of the rows above and below the tile, and
-    // a segment next to each tile row on the left (its last cell is used)
-    // and on the right (its first cell is used)
+    // step t on the ring, one cell per thread: the rows above and below the
+    // tile and the columns to its left and right (no corners: nothing pulls
+    // from them)
     for (int r = tid; r < NR; r += 256) {
         int x, y;
-        if (r < TPR) { x = x0 + r * VX; y = y0 - 1; }
-        else if (r < 2 * TPR) { x = x0 + (r - TPR) * VX; y = y0 + TY; }
-        else if (r < 2 * TPR + TY) { x = x0 - VX; y = y0 + (r - 2 * TPR); }
-        else { x = x0 + TX; y = y0 + (r - 2 * TPR - TY); }
-        const int yf = fold(y, a.ny, a.W[1]);
-        T v[11][VX], e[VX];
-        pull_row<T, VX>(a, x, yf, v, e);
+        if (r < TX) { x = x0 + r; y = y0 - 1; }
+        else if (r < 2 * TX) { x = x0 + (r - TX); y = y0 + TY; }
+        else if (r < 2 * TX + TY) { x = x0 - 1; y = y0 + (r - 2 * TX); }
+        else { x = x0 + TX; y = y0 + (r - 2 * TX - TY); }
+        const int xf = fold(x, a.nx, a.W[0]), yf = fold(y, a.ny, a.W[1]);
+        T v[11][1], e[1];
+        pull_row<T, 1>(a, xf, yf, v, e);
+        T f[11];
 #pragma unroll
-        for (int k = 0; k < VX; ++k) {
-            const int xf = fold(x + k, a.nx, a.W[0]);
-            T f[11];
-#pragma unroll
-            for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL>(a, s0, xf, yf, e[k], T(1) / e[k], sigma2d<T>(a, xf, yf), f, false);
-#pragma unroll
-            for (int i = 0; i < 11; ++i) v[i][k] = f[i];
-        }
-        if (r < TPR) {
-            lds_store<T, VX>(&L.ym[0][0][x - x0], v[2]);
-            lds_store<T, VX>(&L.ym[1][0][x - x0], v[6]);
-        } else if (r < 2 * TPR) {
-            lds_store<T, VX>(&L.yp[0][TY][x - x0], v[3]);
-            lds_store<T, VX>(&L.yp[1][TY][x - x0], v[7]);
-        } else if (r < 2 * TPR + TY) {
-            L.xm[0][y - y0][VX - 1] = v[0][VX - 1];
-            L.xm[1][y - y0][VX - 1] = v[4][VX - 1];
+        for (int i = 0; i < 11; ++i) f[i] = v[i][0];
+        cell_update2d<T, POL>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf), f, false);
+        if (r < TX) {
+            L.ym[0][0][r] = f[2];
+            L.ym[1][0][r] = f[6];
+        } else if (r < 2 * TX) {
+            L.yp[0][TY][r - TX] = f[3];
+            L.yp[1][TY][r - TX] = f[7];
+        } else if (r < 2 * TX + TY) {
+            L.xm[0][y - y0][VX - 1] = f[0];
+            L.xm[1][y - y0][VX - 1] = f[4];
         } else {
-            L.xp[0][y - y0][TX] = v[1][0];
-            L.xp[1][y - y0][TX] = v[5][0];
+            L.xp[0][y - y0][TX] = f[1];
+            L.xp[1][y - y0][TX] = f[5];
         }
     }
     __syncthreads();
@@ -740,7 +762,7 @@ __global__ void __launch_bounds__(256) k_step2d_tile_batch(const StepArgs<T> *__
         const StepArgs<T> &a = descs[inst];
         const int local = w - tile_first[inst];
         const int x0 = (local % a.tiles_x) * TX, y0 = (local / a.tiles_x) * TY;
-        const StepConst st = step_const(a, t);
+        const StepConst<T> st = step_const(a, t);
         for (int seg = threadIdx.x; seg < TPR * TY; seg += blockDim.x)
             step2d_cells<T, POL, VX>(a, x0 + (seg % TPR) * VX, y0 + seg / TPR, st);
     }
@@ -816,14 +838,14 @@ __device__ inline void equilibrium3d(const T E[3], const T H[3], T eps, T scale,
 }
 
 template <typename T>
-__device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst &st, int x, int y, int z, T eps,
+__device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, int z, T eps,
                                      T f[27]) {
-    const T inv_eps = T(1) / eps;
+    const T inv_eps = recip(eps);
     T E[3], H[3];
     fields3d(f, inv_eps, E, H);
     if (st.dft) {
-        double Ed[3] = {E[0], E[1], E[2]}, Hd[3] = {H[0], H[1], H[2]};
-        dft_accumulate(a, st, 3, x, y, z, Ed, Hd);
+        const double G[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
+        dft_accumulate<0x3f>(a, st, 3, x, y, z, G);
     }
     T q[27];
     equilibrium3d(E, H, eps, T(2), q);
@@ -835,17 +857,17 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst &st, 
     if (sig > T(0)) {
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
-            const T w = (T)plane_wave<T, 3>(a, st, x, y, z);
+            const T w = plane_wave<T, 3>(a, st, x, y, z);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                Er[k] = w * (T)a.ehat[k];
-                Hr[k] = w * (T)a.hhat[k];
+                Er[k] = w * a.ehat[k];
+                Hr[k] = w * a.hhat[k];
             }
         }
         T qr[27];
         equilibrium3d(Er, Hr, eps, T(1), qr);
 #pragma unroll
-        for (int i = 0; i < 27; ++i) f[i] = f[i] - sig * (f[i] - qr[i]);
+        for (int i = 0; i < 27; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
     }
 }
 
@@ -906,7 +928,7 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
             e[j] = *at(a.eps, base + x);
         }
     }
-    const StepConst st = step_const(a, step_time(a.t_base, a.t_off));
+    const StepConst<T> st = step_const(a, step_time(a.t_base, a.t_off));
 #pragma unroll
     for (int j = 0; j < VX; ++j) {
         T f[27];
@@ -1036,7 +1058,7 @@ __global__ void __launch_bounds__(256) k_adjoint2d(AdjArgs<T> a) {
     l[10] = m[10 * P + c];
 
     const T eps = a.eps[c];
-    const T inv_eps = T(1) / eps;
+    const T inv_eps = recip(eps);
     T u[3];
     equilibrium2d_T<T, POL>(l, u);
     // gradient: lambda . dK/deps s = 2 (Q^T lambda)_E . dE/deps
@@ -1167,7 +1189,7 @@ __global__ void __launch_bounds__(256) k_fields(StepArgs<T> a, T *E, T *H) {
                    s[8 * P + c],        s[9 * P + c],        s[10 * P + c]};
         const T eps = a.eps[c];
         T F[3];
-        fields2d<T, POL>(f, eps, T(1) / eps, F);
+        fields2d<T, POL>(f, eps, recip(eps), F);
         if (POL == TM) { Ev[2] = F[0]; Hv[0] = F[1]; Hv[1] = F[2]; }
         else { Ev[0] = F[0]; Ev[1] = F[1]; Hv[2] = F[2]; }
     } else {
@@ -1181,7 +1203,7 @@ __global__ void __launch_bounds__(256) k_fields(StepArgs<T> a, T *E, T *H) {
         for (int d = 0; d < 6; ++d)
             for (int k = 0; k < 4; ++k) f[4 * d + k] = a.src[(4 * d + k) * P + src_cell[d]];
         for (int k = 0; k < 3; ++k) f[24 + k] = a.src[(24 + k) * P + c];
-        fields3d(f, T(1) / a.eps[c], Ev, Hv);
+        fields3d(f, recip(a.eps[c]), Ev, Hv);
     }
     for (int k = 0; k < 3; ++k) {
         E[cell * 3 + k] = Ev[k];

@@ -82,7 +82,8 @@ struct lbm_em {
     lbm_em_plane_wave pw{};
     double hhat[3] = {0, 0, 0};
     int period = 0;
-    double *wtab = nullptr;             // phase tables of the source (StepArgs::wave_*)
+    double *wtab = nullptr;             // phase tables of the source (StepArgs::wave_*, ramp)
+    int64_t axes_off = 0;               // offset of the per-axis tables in doubles
     int batch_refs = 0;                 // batches that hold this handle
     // contour DFT
     bool dft_set = false;
@@ -166,15 +167,17 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
         a.amp = h->pw.amplitude;
         a.t_ramp = h->pw.ramp_periods * (double)h->period;
         for (int k = 0; k < 3; ++k) {
-            a.ehat[k] = h->pw.ehat[k];
-            a.hhat[k] = h->hhat[k];
+            a.ehat[k] = (T)h->pw.ehat[k];
+            a.hhat[k] = (T)h->hhat[k];
         }
+        // table layout: see lbm_em_set_source
         const double2 *w = (const double2 *)h->wtab;
         a.wave_t = w;
-        a.wave_x = w + h->period;
+        a.ramp = (const double *)(w + h->period);
+        using C2 = typename Cplx<T>::type;
+        a.wave_x = (const C2 *)(h->wtab + h->axes_off);
         a.wave_y = a.wave_x + h->cfg.nx;
         a.wave_z = a.wave_y + h->cfg.ny;
-        a.ramp = (const double *)(a.wave_z + h->cfg.nz);
     }
     a.dft_on = h->dft_set ? 1 : 0;
     a.box = h->box;
@@ -877,29 +880,41 @@ lbm_em_status lbm_em_set_source(lbm_em_handle hh, const lbm_em_plane_wave *pw) {
         if (t_ramp > 1e7) fail(LBM_EM_EINVAL, "ramp longer than 1e7 steps");
         if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         select_device(h);
-        // phase tables: e^{2 pi j k/T} (k < T), e^{2 pi j u_a} per column,
-        // row and slab (u_a = khat_a (a - center_a) / lambda, reduced to
-        // [0, 1) before the sine), and the ramp g(t) = sin^2(pi t / (2 t_ramp))
+        // Tables, in one allocation: (cos, sin)(2 pi k / T) for k < T (FP64);
+        // the ramp g(t) = sin^2(pi t / (2 t_ramp)) for t < t_ramp (FP64);
+        // (cos, sin)(2 pi u_a) per column, row and slab, u_a = khat_a (a -
+        // center_a) / lambda reduced to [0, 1) before the sine, computed in
+        // FP64 and stored in the run's precision.
         const int period = (int)std::lround(T);
         const int nramp = (int)std::ceil(t_ramp);
         const int n[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz};
-        std::vector<double> tab;
-        tab.reserve(2 * ((size_t)period + n[0] + n[1] + n[2]) + nramp);
-        auto unit = [&](double u) {
+        std::vector<double> head, axes;
+        auto unit = [](std::vector<double> &v, double u) {
             u -= std::floor(u);
-            tab.push_back(std::cos(2.0 * M_PI * u));
-            tab.push_back(std::sin(2.0 * M_PI * u));
+            v.push_back(std::cos(2.0 * M_PI * u));
+            v.push_back(std::sin(2.0 * M_PI * u));
         };
-        for (int k = 0; k < period; ++k) unit((double)k / (double)period);
-        for (int ax = 0; ax < 3; ++ax)
-            for (int i = 0; i < n[ax]; ++i) unit(pw->khat[ax] * ((double)i - pw->center[ax]) / pw->lambda);
+        for (int k = 0; k < period; ++k) unit(head, (double)k / (double)period);
         for (int i = 0; i < nramp; ++i) {
             const double sr = std::sin(M_PI * (double)i / (2.0 * t_ramp));
-            tab.push_back(sr * sr);
+            head.push_back(sr * sr);
+        }
+        if (head.size() % 2) head.push_back(0.0);     // 16-byte aligned axis tables
+        for (int ax = 0; ax < 3; ++ax)
+            for (int i = 0; i < n[ax]; ++i) unit(axes, pw->khat[ax] * ((double)i - pw->center[ax]) / pw->lambda);
+        std::vector<char> bytes(head.size() * 8 + axes.size() * h->elem);
+        std::memcpy(bytes.data(), head.data(), head.size() * 8);
+        char *ap = bytes.data() + head.size() * 8;
+        for (size_t i = 0; i < axes.size(); ++i) {
+            if (h->elem == 8) std::memcpy(ap + 8 * i, &axes[i], 8);
+            else {
+                const float v = (float)axes[i];
+                std::memcpy(ap + 4 * i, &v, 4);
+            }
         }
         double *dtab = nullptr;
-        hip_check(hipMalloc(&dtab, tab.size() * sizeof(double)), "hipMalloc source tables");
-        hipError_t e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        hip_check(hipMalloc(&dtab, bytes.size()), "hipMalloc source tables");
+        hipError_t e = hipMemcpyAsync(dtab, bytes.data(), bytes.size(), hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) {
             hfree(dtab);
@@ -914,6 +929,7 @@ lbm_em_status lbm_em_set_source(lbm_em_handle hh, const lbm_em_plane_wave *pw) {
         h->hhat[1] = k[2] * ev[0] - k[0] * ev[2];
         h->hhat[2] = k[0] * ev[1] - k[1] * ev[0];
         h->period = period;
+        h->axes_off = (int64_t)head.size();
         h->src_on = true;
         drop_graphs(h);
     });
