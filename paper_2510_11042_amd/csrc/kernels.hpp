@@ -582,11 +582,17 @@ struct alignas(16) X2Lds {
     T yp[2][TY + 1][TX];                 // planes 3, 7: tile row oy at oy, ring row below at TY
 };
 
-// One segment per thread: TX x TY = 256 segments of VX cells.
+// One segment of VX cells per thread: blocks of (TX / VX) * TY threads,
+// 256, 512 or 1024 (the larger tiles re-read a smaller halo fraction; the
+// LDS tile grows with them, up to ~140 KB of the 160 KB of a CU).
+template <typename T, int TX, int TY>
+__host__ __device__ constexpr int x2_threads() {
+    return (TX / (16 / (int)sizeof(T))) * TY;
+}
 template <typename T, int TX, int TY>
 __host__ __device__ constexpr bool x2_tile_ok() {
-    constexpr int VX = 16 / (int)sizeof(T);
-    return TX % VX == 0 && (TX / VX) * TY == 256;
+    constexpr int VX = 16 / (int)sizeof(T), NT = x2_threads<T, TX, TY>();
+    return TX % VX == 0 && (NT == 256 || NT == 512 || NT == 1024);
 }
 
 template <typename T, int N>
@@ -600,6 +606,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     constexpr int VX = X2Lds<T, TX, TY>::VX;
     constexpr int TPR = TX / VX;             // segments per tile row
     constexpr int NI = 1;                    // segments per thread
+    constexpr int NT = x2_threads<T, TX, TY>();
     constexpr int NR = 2 * TX + 2 * TY;      // ring cells
     static_assert(x2_tile_ok<T, TX, TY>(), "two-step tile shape");
     const int tid = threadIdx.x;
@@ -608,7 +615,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     // step t on the thread's own segment
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
-        const int seg = tid + 256 * it;
+        const int seg = tid + NT * it;
         const int sx = (seg % TPR) * VX, sy = seg / TPR;
         const int x = x0 + sx, y = y0 + sy;
         const int yf = fold(y, a.ny, a.W[1]);
@@ -642,7 +649,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     // step t on the ring, one cell per thread: the rows above and below the
     // tile and the columns to its left and right (no corners: nothing pulls
     // from them)
-    for (int r = tid; r < NR; r += 256) {
+    for (int r = tid; r < NR; r += NT) {
         int x, y;
         if (r < TX) { x = x0 + r; y = y0 - 1; }
         else if (r < 2 * TX) { x = x0 + (r - TX); y = y0 + TY; }
@@ -674,7 +681,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     // step t+1 on the thread's own segments
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
-        const int seg = tid + 256 * it;
+        const int seg = tid + NT * it;
         const int sx = (seg % TPR) * VX, sy = seg / TPR;
         const int x = x0 + sx, y = y0 + sy;
         if (x >= a.nx || y >= a.ny) continue;
@@ -740,9 +747,11 @@ __device__ inline int xcd_tile(int b, int ntiles) {
     return xcd * q + (xcd < r ? xcd : r) + j;
 }
 
-// One block per tile, a 1-D grid of tiles_x * tiles_y blocks.
+// One block per tile, a 1-D grid of tiles_x * tiles_y blocks.  The launch
+// bound asks for 4 waves per SIMD (at most 128 VGPRs).
 template <typename T, int POL, int TX, int TY>
-__global__ void __launch_bounds__(256, 4) k_step2d_x2(StepArgs<T> a) {
+__global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
+    k_step2d_x2(StepArgs<T> a) {
     __shared__ X2Lds<T, TX, TY> lds;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     step2d_x2_tile<T, POL, TX, TY>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
@@ -751,7 +760,7 @@ __global__ void __launch_bounds__(256, 4) k_step2d_x2(StepArgs<T> a) {
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).
 template <typename T, int POL, int TX, int TY>
-__global__ void __launch_bounds__(256) k_step2d_tile_batch(const StepArgs<T> *__restrict__ descs,
+__global__ void __launch_bounds__((x2_threads<T, TX, TY>())) k_step2d_tile_batch(const StepArgs<T> *__restrict__ descs,
                                                            const int *__restrict__ tile_inst,
                                                            const int *__restrict__ tile_first, int ntiles,
                                                            const int64_t *t_base, int64_t t_off) {
@@ -772,13 +781,16 @@ __global__ void __launch_bounds__(256) k_step2d_tile_batch(const StepArgs<T> *__
 // (instance, tile) work list (tiles of TX x TY cells); a barrier separates
 // consecutive tiles of a block because they share the LDS tile.
 template <typename T, int POL, int TX, int TY>
-__global__ void __launch_bounds__(256, 4) k_step2d_x2_batch(const StepArgs<T> *__restrict__ descs,
+__global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
+    k_step2d_x2_batch(const StepArgs<T> *__restrict__ descs,
                                                          const int *__restrict__ tile_inst,
                                                          const int *__restrict__ tile_first, int ntiles,
                                                          const int64_t *t_base, int64_t t_off) {
     __shared__ X2Lds<T, TX, TY> lds;
     const int64_t t = step_time(t_base, t_off);
-    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    for (int w0 = blockIdx.x; w0 < ntiles; w0 += gridDim.x) {
+        // one block per work item: XCD-banded order as in k_step2d_x2
+        const int w = (int)gridDim.x == ntiles ? xcd_tile(w0, ntiles) : w0;
         const int inst = tile_inst[w];
         const StepArgs<T> &a = descs[inst];
         const int local = w - tile_first[inst];

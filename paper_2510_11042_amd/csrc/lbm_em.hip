@@ -231,8 +231,8 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
 // Two steps in one launch (2-D): reads src, writes f*(t+1) to dst.
 // Two-step tiles: TX x TY cells, TX a multiple of the 16-byte segment and
 // TX*TY a multiple of 256 segments' worth (see x2_tile_ok).
-#define LBM_X2_TILES_F32(M) M(64, 16) M(128, 8) M(256, 4) M(32, 32)
-#define LBM_X2_TILES_F64(M) M(32, 16) M(64, 8) M(128, 4) M(16, 32)
+#define LBM_X2_TILES_F32(M) M(64, 16) M(128, 8) M(128, 16) M(256, 8) M(256, 16) M(128, 32)
+#define LBM_X2_TILES_F64(M) M(32, 16) M(64, 8) M(64, 16) M(128, 8) M(128, 16) M(64, 32)
 
 template <typename T, int POL>
 void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
@@ -240,7 +240,10 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
     a.tiles_y = (a.ny + ty - 1) / ty;
     dim3 grid((unsigned)(a.tiles_x * a.tiles_y), 1, 1);
 #define LBM_X2(TX, TY) \
-    if (tx == TX && ty == TY) { hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(256), 0, s, a); return; }
+    if (tx == TX && ty == TY) {                                                                        \
+        hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
+        return;                                                                                        \
+    }
     if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_X2) }
     else { LBM_X2_TILES_F64(LBM_X2) }
 #undef LBM_X2
@@ -417,10 +420,11 @@ void launch_batch_x2_pol(const lbm_em_batch_s *b, const BatchGroup &g, int par, 
 #define LBM_X2B(TX, TY)                                                                                        \
     if (b->ftx == TX && b->fty == TY) {                                                                         \
         if (two)                                                                                                \
-            hipLaunchKernelGGL((k_step2d_x2_batch<T, POL, TX, TY>), dim3(g.grid), dim3(256), 0, s, d, g.tile_inst, \
-                               g.tile_first, g.ntiles, t_base, t_off);                                         \
+            hipLaunchKernelGGL((k_step2d_x2_batch<T, POL, TX, TY>), dim3(g.grid), dim3(x2_threads<T, TX, TY>()), \
+                               0, s, d, g.tile_inst, g.tile_first, g.ntiles, t_base, t_off);                   \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_step2d_tile_batch<T, POL, TX, TY>), dim3(g.grid), dim3(256), 0, s, d,        \
+            hipLaunchKernelGGL((k_step2d_tile_batch<T, POL, TX, TY>), dim3(g.grid), dim3(x2_threads<T, TX, TY>()), \
+                               0, s, d,                                                                        \
                                g.tile_inst, g.tile_first, g.ntiles, t_base, t_off);                            \
         return;                                                                                                \
     }
@@ -1056,8 +1060,8 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
             if (!fused_tile_ok(h->cfg.precision, tile_x, tile_y))
                 fail(LBM_EM_EINVAL, h->cfg.precision == LBM_EM_FP32
-                                        ? "FP32 two-step tile must be 64x16, 128x8, 256x4 or 32x32"
-                                        : "FP64 two-step tile must be 32x16, 64x8, 128x4 or 16x32");
+                                        ? "FP32 two-step tile must be 64x16, 128x8, 128x16, 256x8, 256x16 or 128x32"
+                                        : "FP64 two-step tile must be 32x16, 64x8, 64x16, 128x8, 128x16 or 64x32");
             h->ftx = tile_x;
             h->fty = tile_y;
         }

@@ -282,8 +282,8 @@ def test_autotune_verifies_and_does_not_advance(gpu):
         sims[0].set_tile(1, 100, 1)
 
 
-X2_TILES = {"fp32": [(64, 16), (128, 8), (256, 4), (32, 32)],
-            "fp64": [(32, 16), (64, 8), (128, 4), (16, 32)]}
+X2_TILES = {"fp32": [(64, 16), (128, 8), (128, 16), (256, 8), (256, 16), (128, 32)],
+            "fp64": [(32, 16), (64, 8), (64, 16), (128, 8), (128, 16), (64, 32)]}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
