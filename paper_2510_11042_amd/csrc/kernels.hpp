@@ -218,15 +218,15 @@ __device__ inline T recip(T e) {
 //   TM: F = (E_z, H_x, H_y); TE: F = (E_x, E_y, H_z).
 template <typename T, int POL>
 __device__ inline void fields2d(const T s[11], T eps, T inv_eps, T F[3]) {
-    const T rest = T(6) * eps - T(4);  // z-pair (x2) plus slaved rest population
+    const T rest = fma(T(6), eps, T(-4));  // z-pair (x2) plus slaved rest population
     if (POL == TM) {
-        F[0] = (s[0] + s[1] + s[2] + s[3] + rest * s[8]) * inv_eps;
-        F[1] = s[4] + s[5] + s[2] - s[3] + T(2) * s[9];
-        F[2] = s[6] + s[7] - s[0] + s[1] + T(2) * s[10];
+        F[0] = fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
+        F[1] = fma(T(2), s[9], s[4] + s[5] + s[2] - s[3]);
+        F[2] = fma(T(2), s[10], s[6] + s[7] - s[0] + s[1]);
     } else {
-        F[0] = (s[0] + s[1] + s[2] + s[3] + rest * s[8]) * inv_eps;
-        F[1] = (s[4] + s[5] + s[6] + s[7] + rest * s[9]) * inv_eps;
-        F[2] = s[4] - s[5] - s[2] + s[3] + T(2) * s[10];
+        F[0] = fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
+        F[1] = fma(rest, s[9], s[4] + s[5] + s[6] + s[7]) * inv_eps;
+        F[2] = fma(T(2), s[10], s[4] - s[5] - s[2] + s[3]);
     }
 }
 
@@ -257,6 +257,40 @@ __device__ inline void equilibrium2d(const T F[3], T scale, T q[11]) {
         q[8] = c * Ex;
         q[9] = c * Ey;
         q[10] = c * Hz;
+    }
+}
+
+// Collision at tau = 1/2: f <- 2 f^eq(F) - f, each population one fused
+// multiply-add (c = 2/6).
+template <typename T, int POL>
+__device__ inline void collide2d(const T F[3], T f[11]) {
+    const T c = T(1) / T(3);
+    if (POL == TM) {
+        const T Ez = F[0], Hx = F[1], Hy = F[2];
+        f[0] = fma(c, Ez - Hy, -f[0]);
+        f[1] = fma(c, Ez + Hy, -f[1]);
+        f[2] = fma(c, Ez + Hx, -f[2]);
+        f[3] = fma(c, Ez - Hx, -f[3]);
+        f[4] = fma(c, Hx, -f[4]);
+        f[5] = fma(c, Hx, -f[5]);
+        f[6] = fma(c, Hy, -f[6]);
+        f[7] = fma(c, Hy, -f[7]);
+        f[8] = fma(c, Ez, -f[8]);
+        f[9] = fma(c, Hx, -f[9]);
+        f[10] = fma(c, Hy, -f[10]);
+    } else {
+        const T Ex = F[0], Ey = F[1], Hz = F[2];
+        f[0] = fma(c, Ex, -f[0]);
+        f[1] = fma(c, Ex, -f[1]);
+        f[2] = fma(c, Ex - Hz, -f[2]);
+        f[3] = fma(c, Ex + Hz, -f[3]);
+        f[4] = fma(c, Ey + Hz, -f[4]);
+        f[5] = fma(c, Ey - Hz, -f[5]);
+        f[6] = fma(c, Ey, -f[6]);
+        f[7] = fma(c, Ey, -f[7]);
+        f[8] = fma(c, Ex, -f[8]);
+        f[9] = fma(c, Ey, -f[9]);
+        f[10] = fma(c, Hz, -f[10]);
     }
 }
 
@@ -381,7 +415,7 @@ __device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
 // them for the second step).  record: the cell is in the domain and owned by
 // this thread, so it may add DFT samples and design-region history.
 // ---------------------------------------------------------------------------
-template <typename T, int POL>
+template <typename T, int POL, bool HIST = false>
 __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, T eps,
                                      T inv_eps, T sig, T f[11], bool record) {
     const int64_t t = st.t;
@@ -397,7 +431,7 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
             dft_accumulate<0x23>(a, st, 2, x, y, 0, G);
         }
     }
-    if (a.hist && record && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
+    if (HIST && record && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
         // E = (sum of the E-carrying populations + (6 eps - 4) z-pair)/eps,
         // so dE/deps = (6 zpair - E)/eps at fixed populations
         const int64_t dw = a.dhi[0] - a.dlo[0] + 1, dh = a.dhi[1] - a.dlo[1] + 1;
@@ -409,10 +443,7 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
             h[2 * cell + 1] = (T(6) * f[9] - F[1]) * inv_eps;
         }
     }
-    T q[11];
-    equilibrium2d<T, POL>(F, T(2), q);
-#pragma unroll
-    for (int i = 0; i < 11; ++i) f[i] = q[i] - f[i];
+    collide2d<T, POL>(F, f);
     if (sig > T(0)) {
         // relax towards the incident wave's equilibrium (zero where eps != 1):
         // f + sig (f_ref - f), one fused multiply-add per population
@@ -505,7 +536,7 @@ __device__ inline void store_row(const StepArgs<T> &a, int x0, int y, const T (&
 // 2-D fused step: pull + moments + DFT + collision + layer/source + store.
 // The calling thread updates cells x0 .. x0+VX-1 of row y.
 // ---------------------------------------------------------------------------
-template <typename T, int POL, int VX>
+template <typename T, int POL, int VX, bool HIST = false>
 __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const StepConst<T> &st) {
     if (x0 >= a.nx || y >= a.ny) return;
     T v[11][VX], e[VX];
@@ -516,18 +547,20 @@ __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const S
         T f[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-        cell_update2d<T, POL>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f, x0 + k < a.nx);
+        cell_update2d<T, POL, HIST>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f, x0 + k < a.nx);
 #pragma unroll
         for (int i = 0; i < 11; ++i) v[i][k] = f[i];
     }
     store_row<T, VX>(a, x0, y, v);
 }
 
-template <typename T, int POL, int VX>
+// HIST: also record dE/deps of the design cells into a.hist (checkpointed
+// forward pass of the adjoint).
+template <typename T, int POL, int VX, bool HIST = false>
 __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
     const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    step2d_cells<T, POL, VX>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
+    step2d_cells<T, POL, VX, HIST>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
 }
 
 // Batched persistent step: one launch advances many 2-D instances of

@@ -195,9 +195,16 @@ void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
     const int gx = (h->cfg.nx + VX - 1) / VX;
     dim3 grid((unsigned)((gx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
               (unsigned)h->cfg.nz);
-    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX>), grid, block, 0, s, a);
-    else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE, VX>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step3d<T, VX>), grid, block, 0, s, a);
+    const bool rec = a.hist != nullptr;
+    if (h->cfg.pol == LBM_EM_TM) {
+        if (rec) hipLaunchKernelGGL((k_step2d<T, TM, VX, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<T, TM, VX>), grid, block, 0, s, a);
+    } else if (h->cfg.pol == LBM_EM_TE) {
+        if (rec) hipLaunchKernelGGL((k_step2d<T, TE, VX, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<T, TE, VX>), grid, block, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_step3d<T, VX>), grid, block, 0, s, a);
+    }
 }
 
 template <typename T>
