@@ -788,7 +788,9 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             h->elem = c.precision == LBM_EM_FP32 ? 4 : 8;
             if (h->dim == 2) {
                 h->fuse = 2;
-                h->ftx = c.precision == LBM_EM_FP32 ? 64 : 32;
+                // 1024-thread tiles: the smallest re-read halo (autotune may
+                // pick another)
+                h->ftx = c.precision == LBM_EM_FP32 ? 256 : 128;
                 h->fty = 16;
             }
             h->sy = round_up(c.nx, 64);
