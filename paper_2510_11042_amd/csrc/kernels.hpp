@@ -633,7 +633,7 @@ __device__ inline void lds_load(T (&o)[N], const T *p) { load_aligned<T, N>(o, p
 template <typename T, int N>
 __device__ inline void lds_store(T *p, const T (&i)[N]) { store_aligned<T, N>(p, i); }
 
-template <typename T, int POL, int TX, int TY>
+template <typename T, int POL, int TX, int TY, bool HIST = false>
 __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t) {
     const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
     constexpr int VX = X2Lds<T, TX, TY>::VX;
@@ -663,7 +663,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             T f[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL>(a, s0, xf, yf, e[k], ip[it][k], sg[it][k], f, x + k < a.nx && y < a.ny);
+            cell_update2d<T, POL, HIST>(a, s0, xf, yf, e[k], ip[it][k], sg[it][k], f, x + k < a.nx && y < a.ny);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
             zp[it][0][k] = f[8];
@@ -761,7 +761,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             f[8] = zp[it][0][k];
             f[9] = zp[it][1][k];
             f[10] = zp[it][2][k];
-            cell_update2d<T, POL>(a, s1, xf, y, ep[it][k], ip[it][k], sg[it][k], f, x + k < a.nx);
+            cell_update2d<T, POL, HIST>(a, s1, xf, y, ep[it][k], ip[it][k], sg[it][k], f, x + k < a.nx);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
         }
@@ -782,13 +782,14 @@ __device__ inline int xcd_tile(int b, int ntiles) {
 
 // One block per tile, a 1-D grid of tiles_x * tiles_y blocks.  The launch
 // bound asks for 4 waves per SIMD (at most 128 VGPRs).
-template <typename T, int POL, int TX, int TY>
+// HIST: also record dE/deps of the design cells (recompute of the adjoint).
+template <typename T, int POL, int TX, int TY, bool HIST = false>
 __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
     k_step2d_x2(StepArgs<T> a) {
     __shared__ X2Lds<T, TX, TY> lds;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    step2d_x2_tile<T, POL, TX, TY>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
-                                   step_time(a.t_base, a.t_off));
+    step2d_x2_tile<T, POL, TX, TY, HIST>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
+                                         step_time(a.t_base, a.t_off));
 }
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).

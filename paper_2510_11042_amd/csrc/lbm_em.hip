@@ -247,9 +247,12 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
     a.tiles_y = (a.ny + ty - 1) / ty;
     dim3 grid((unsigned)(a.tiles_x * a.tiles_y), 1, 1);
 #define LBM_X2(TX, TY) \
-    if (tx == TX && ty == TY) {                                                                        \
-        hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
-        return;                                                                                        \
+    if (tx == TX && ty == TY) {                                                                              \
+        if (a.hist)                                                                                          \
+            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a);  \
+        return;                                                                                              \
     }
     if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_X2) }
     else { LBM_X2_TILES_F64(LBM_X2) }
@@ -259,21 +262,29 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
 
 template <typename T>
 void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base, int64_t t_off,
-                    hipStream_t s, bool dft) {
+                    hipStream_t s, bool dft, void *hist = nullptr, int64_t hist_t0 = 0) {
     StepArgs<T> a = make_args<T>(h, src, dst);
     a.t_base = t_base;
     a.t_off = t_off;
     if (!dft) a.dft_on = 0;
+    if (hist) {
+        a.hist = (T *)hist;
+        a.hist_t0 = hist_t0;
+        for (int k = 0; k < 2; ++k) {
+            a.dlo[k] = h->dlo[k];
+            a.dhi[k] = h->dhi[k];
+        }
+    }
     if (h->cfg.pol == LBM_EM_TM) launch_step2_pol<T, TM>(a, h->ftx, h->fty, s);
     else launch_step2_pol<T, TE>(a, h->ftx, h->fty, s);
 }
 
 void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
-                  bool dft = true) {
+                  bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
-    if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft);
-    else launch_step2_t<double>(h, src, dst, t_base, t_off, s, dft);
+    if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
+    else launch_step2_t<double>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
 }
 
 bool fused_tile_ok(int precision, int tx, int ty) {
@@ -1457,8 +1468,17 @@ lbm_em_status lbm_em_backward(lbm_em_handle hh, double *grad_eps, int32_t where)
                 // recompute the segment from its checkpoint, recording dE/deps
                 hip_check(hipMemcpyAsync(h->buf[0], (char *)h->ck + sb * k, sb, hipMemcpyDeviceToDevice, h->stream),
                           "restore");
+                // (two steps per launch where the handle uses them, then a
+                // single trailing step)
                 int cur = 0;
-                for (int64_t t = t0; t < t1; ++t) {
+                int64_t t = t0;
+                if (h->fuse == 2)
+                    for (; t + 2 <= t1; t += 2) {
+                        launch_step2(h, cur, nullptr, t, h->stream, false, hist, t0);
+                        hip_check(hipGetLastError(), "recompute");
+                        cur ^= 1;
+                    }
+                for (; t < t1; ++t) {
                     launch_step(h, cur, nullptr, t, h->stream, false, hist, t0);
                     hip_check(hipGetLastError(), "recompute");
                     cur ^= 1;
