@@ -1028,9 +1028,11 @@ struct AdjArgs {
     int period;
     const double *G;             // (nnodes) x 6 x (re, im)
     // gradient
-    const T *hist;               // d for this step, design rectangle
+    const T *hist;               // d for step t, design rectangle
+    const T *hist_prev;          // d for step t - 1 (two-step kernel)
     double *grad;                // design rectangle, accumulated
     int dlo[2], dhi[2];
+    int tiles_x;                 // tile grid (two-step kernel)
 };
 
 // L^T u for the 11 reduced scalars (u: TM (Ez, Hx, Hy), TE (Ex, Ey, Hz)).
@@ -1066,67 +1068,72 @@ __device__ inline void equilibrium2d_T(const T l[11], T u[3]) {
     }
 }
 
-template <typename T, int POL>
-__global__ void __launch_bounds__(256) k_adjoint2d(AdjArgs<T> a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= a.nx || y >= a.ny) return;
-    const int64_t P = a.plane, row = (int64_t)y * a.sy, c = row + x;
+// Reverse pull of one cell: l_i = mu_i(r + c_i) (zero past an absorbing
+// face) plus, on an absorbing face whose forward pull was clamped, the
+// cell's own mu_i.  m = mu(t+1).
+template <typename T>
+__device__ inline void adj_pull_cell(const AdjArgs<T> &a, int x, int y, T l[11]) {
+    const int64_t P = a.plane;
     const T *m = a.src;
-    T l[11];
-    // +x populations (forward pull from x-1): adjoint from x+1
-    {
+    const uint32_t sy = (uint32_t)a.sy;
+    const uint32_t row = (uint32_t)y * sy, c = row + (uint32_t)x;
+    {   // +x populations (forward pull from x-1): adjoint from x+1
         const bool in = x + 1 < a.nx || a.W[0] == 0;
-        const int xs = x + 1 < a.nx ? x + 1 : 0;
+        const uint32_t n = row + (uint32_t)(x + 1 < a.nx ? x + 1 : 0);
         const bool self = a.W[0] && x == 0;
-        for (int i : {0, 4}) l[i] = (in ? m[i * P + row + xs] : T(0)) + (self ? m[i * P + c] : T(0));
+        for (int i : {0, 4}) l[i] = (in ? *at(m + i * P, n) : T(0)) + (self ? *at(m + i * P, c) : T(0));
     }
     {   // -x populations: adjoint from x-1
         const bool in = x > 0 || a.W[0] == 0;
-        const int xs = x > 0 ? x - 1 : a.nx - 1;
+        const uint32_t n = row + (uint32_t)(x > 0 ? x - 1 : a.nx - 1);
         const bool self = a.W[0] && x == a.nx - 1;
-        for (int i : {1, 5}) l[i] = (in ? m[i * P + row + xs] : T(0)) + (self ? m[i * P + c] : T(0));
+        for (int i : {1, 5}) l[i] = (in ? *at(m + i * P, n) : T(0)) + (self ? *at(m + i * P, c) : T(0));
     }
     {   // +y populations: adjoint from y+1
         const bool in = y + 1 < a.ny || a.W[1] == 0;
-        const int ys = y + 1 < a.ny ? y + 1 : 0;
+        const uint32_t n = (uint32_t)(y + 1 < a.ny ? y + 1 : 0) * sy + (uint32_t)x;
         const bool self = a.W[1] && y == 0;
-        for (int i : {2, 6}) l[i] = (in ? m[i * P + (int64_t)ys * a.sy + x] : T(0)) + (self ? m[i * P + c] : T(0));
+        for (int i : {2, 6}) l[i] = (in ? *at(m + i * P, n) : T(0)) + (self ? *at(m + i * P, c) : T(0));
     }
     {   // -y populations: adjoint from y-1
         const bool in = y > 0 || a.W[1] == 0;
-        const int ys = y > 0 ? y - 1 : a.ny - 1;
+        const uint32_t n = (uint32_t)(y > 0 ? y - 1 : a.ny - 1) * sy + (uint32_t)x;
         const bool self = a.W[1] && y == a.ny - 1;
-        for (int i : {3, 7}) l[i] = (in ? m[i * P + (int64_t)ys * a.sy + x] : T(0)) + (self ? m[i * P + c] : T(0));
+        for (int i : {3, 7}) l[i] = (in ? *at(m + i * P, n) : T(0)) + (self ? *at(m + i * P, c) : T(0));
     }
-    l[8] = m[8 * P + c];
-    l[9] = m[9 * P + c];
-    l[10] = m[10 * P + c];
+    l[8] = *at(m + 8 * P, c);
+    l[9] = *at(m + 9 * P, c);
+    l[10] = *at(m + 10 * P, c);
+}
 
-    const T eps = a.eps[c];
-    const T inv_eps = recip(eps);
+// One adjoint cell update at step t: l holds the reverse-pulled mu(t+1) on
+// entry and mu(t) on exit; hist = the recorded dE/deps of step t.  record:
+// the cell is in the domain and owned by this thread, so it adds its
+// gradient term.  The objective's source is part of mu(t) itself and is
+// applied to every cell, ring copies included.
+template <typename T, int POL>
+__device__ inline void adj_cell2d(const AdjArgs<T> &a, int64_t t, const T *hist, int x, int y, T eps, T inv_eps,
+                                  T sig, T l[11], bool record) {
     T u[3];
     equilibrium2d_T<T, POL>(l, u);
     // gradient: lambda . dK/deps s = 2 (Q^T lambda)_E . dE/deps
-    if (a.hist && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
+    if (record && hist && x >= a.dlo[0] && x <= a.dhi[0] && y >= a.dlo[1] && y <= a.dhi[1]) {
         const int64_t dw = a.dhi[0] - a.dlo[0] + 1;
         const int64_t cell = (int64_t)(y - a.dlo[1]) * dw + (x - a.dlo[0]);
         double g;
-        if (POL == TM) g = 2.0 * (double)u[0] * (double)a.hist[cell];
-        else g = 2.0 * ((double)u[0] * (double)a.hist[2 * cell] + (double)u[1] * (double)a.hist[2 * cell + 1]);
+        if (POL == TM) g = 2.0 * (double)u[0] * (double)hist[cell];
+        else g = 2.0 * ((double)u[0] * (double)hist[2 * cell] + (double)u[1] * (double)hist[2 * cell + 1]);
         a.grad[cell] += g;
     }
     // K^T lambda = (1 - sigma)(2 L^T Q^T lambda - lambda)
     T o[11];
     fields2d_T<T, POL>(u, eps, inv_eps, o);
-    const T sig = fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
-                       sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max));
 #pragma unroll
     for (int i = 0; i < 11; ++i) l[i] = (T(1) - sig) * (T(2) * o[i] - l[i]);
     // objective source L^T dJ/dF at contour nodes inside the DFT window
-    if (a.G && a.t >= a.win0 && a.t < a.win0 + a.winlen && on_box(a.box, 2, x, y, 0)) {
+    if (a.G && t >= a.win0 && t < a.win0 + a.winlen && on_box(a.box, 2, x, y, 0)) {
         const int64_t node = box_node_index(a.box, 2, x, y, 0);
-        const double ph = 2.0 * M_PI * (double)(a.t % a.period) / (double)a.period;
+        const double ph = 2.0 * M_PI * (double)(t % a.period) / (double)a.period;
         const double sc = 2.0 / (double)a.winlen;
         const double cr = sc * cos(ph), ci = -sc * sin(ph);
         const double *g = a.G + node * 12;
@@ -1140,9 +1147,193 @@ __global__ void __launch_bounds__(256) k_adjoint2d(AdjArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < 11; ++i) l[i] += q[i];
     }
+}
+
+template <typename T>
+__device__ inline T adj_sigma(const AdjArgs<T> &a, int x, int y) {
+    return fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
+                sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max));
+}
+
+template <typename T, int POL>
+__global__ void __launch_bounds__(256) k_adjoint2d(AdjArgs<T> a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
+    T l[11];
+    adj_pull_cell<T>(a, x, y, l);
+    const uint32_t c = (uint32_t)y * (uint32_t)a.sy + (uint32_t)x;
+    const T eps = *at(a.eps, c);
+    adj_cell2d<T, POL>(a, a.t, a.hist, x, y, eps, recip(eps), adj_sigma<T>(a, x, y), l, true);
     T *d = a.dst;
 #pragma unroll
-    for (int i = 0; i < 11; ++i) d[i * P + c] = l[i];
+    for (int i = 0; i < 11; ++i) *at(d + i * a.plane, c) = l[i];
+}
+
+// Two adjoint steps per launch (t, then t - 1), the transpose of the
+// two-step forward kernel's blocking: step t on the tile's segments and a
+// one-cell ring, reverse-pulling mu(t+1) from global memory; the moving
+// populations of mu(t) go to LDS where step t - 1 reverse-pulls them (the
+// +x movers of the tile and the right ring column, the -x movers and the
+// left column, the +y movers and the row below, the -y movers and the row
+// above); step t - 1 then writes mu(t-1).  Same per-cell function as the
+// one-step adjoint kernel, so the result is bit-identical; ring cells add
+// no gradient (their owners do).
+template <typename T, int POL, int TX, int TY>
+__global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
+    k_adjoint2d_x2(AdjArgs<T> a) {
+    constexpr int VX = X2Lds<T, TX, TY>::VX;
+    constexpr int TPR = TX / VX;
+    constexpr int NT = x2_threads<T, TX, TY>();
+    constexpr int NR = 2 * TX + 2 * TY;
+    static_assert(x2_tile_ok<T, TX, TY>(), "two-step tile shape");
+    // LDS roles (reverse pulls): xp holds planes 0, 4 (tile, right ring);
+    // xm planes 1, 5 (left ring, tile); yp planes 2, 6 (tile, row below);
+    // ym planes 3, 7 (row above, tile)
+    __shared__ X2Lds<T, TX, TY> L;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
+    const int tid = threadIdx.x;
+    const int sx = (tid % TPR) * VX, sy = tid / TPR;
+    const int x = x0 + sx, y = y0 + sy;
+    const int64_t t = a.t;
+    const int yf = fold(y, a.ny, a.W[1]);
+    T zp[3][VX], ep[VX], ip[VX], sg[VX];
+
+    // step t on the thread's segment
+    {
+        T l[11][VX];
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const int xf = fold(x + k, a.nx, a.W[0]);
+            T f[11];
+            adj_pull_cell<T>(a, xf, yf, f);
+            const T e = *at(a.eps, (uint32_t)yf * (uint32_t)a.sy + (uint32_t)xf);
+            ep[k] = e;
+            ip[k] = recip(e);
+            sg[k] = adj_sigma<T>(a, xf, yf);
+            adj_cell2d<T, POL>(a, t, a.hist, xf, yf, e, ip[k], sg[k], f, x + k < a.nx && y < a.ny);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) l[i][k] = f[i];
+            zp[0][k] = f[8];
+            zp[1][k] = f[9];
+            zp[2][k] = f[10];
+        }
+        lds_store<T, VX>(&L.xp[0][sy][sx], l[0]);
+        lds_store<T, VX>(&L.xp[1][sy][sx], l[4]);
+        lds_store<T, VX>(&L.xm[0][sy][VX + sx], l[1]);
+        lds_store<T, VX>(&L.xm[1][sy][VX + sx], l[5]);
+        lds_store<T, VX>(&L.yp[0][sy][sx], l[2]);
+        lds_store<T, VX>(&L.yp[1][sy][sx], l[6]);
+        lds_store<T, VX>(&L.ym[0][sy + 1][sx], l[3]);
+        lds_store<T, VX>(&L.ym[1][sy + 1][sx], l[7]);
+    }
+    // step t on the ring: rows above (feeds -y movers) and below (+y
+    // movers), columns left (-x movers) and right (+x movers)
+    for (int r = tid; r < NR; r += NT) {
+        int rx, ry;
+        if (r < TX) { rx = x0 + r; ry = y0 - 1; }
+        else if (r < 2 * TX) { rx = x0 + (r - TX); ry = y0 + TY; }
+        else if (r < 2 * TX + TY) { rx = x0 - 1; ry = y0 + (r - 2 * TX); }
+        else { rx = x0 + TX; ry = y0 + (r - 2 * TX - TY); }
+        const int xf = fold(rx, a.nx, a.W[0]), yf2 = fold(ry, a.ny, a.W[1]);
+        T f[11];
+        adj_pull_cell<T>(a, xf, yf2, f);
+        const T e = *at(a.eps, (uint32_t)yf2 * (uint32_t)a.sy + (uint32_t)xf);
+        adj_cell2d<T, POL>(a, t, a.hist, xf, yf2, e, recip(e), adj_sigma<T>(a, xf, yf2), f, false);
+        if (r < TX) {
+            L.ym[0][0][r] = f[3];
+            L.ym[1][0][r] = f[7];
+        } else if (r < 2 * TX) {
+            L.yp[0][TY][r - TX] = f[2];
+            L.yp[1][TY][r - TX] = f[6];
+        } else if (r < 2 * TX + TY) {
+            L.xm[0][ry - y0][VX - 1] = f[1];
+            L.xm[1][ry - y0][VX - 1] = f[5];
+        } else {
+            L.xp[0][ry - y0][TX] = f[0];
+            L.xp[1][ry - y0][TX] = f[4];
+        }
+    }
+    __syncthreads();
+
+    // step t - 1 on the thread's segment, reverse-pulling mu(t) from LDS
+    if (x >= a.nx || y >= a.ny) return;
+    T l[11][VX];
+    {   // +x movers from the right neighbour (none past an absorbing face;
+        // plus the own value on the absorbing left face)
+        T o0[VX], o4[VX];
+        lds_load<T, VX>(o0, &L.xp[0][sy][sx]);
+        lds_load<T, VX>(o4, &L.xp[1][sy][sx]);
+        const T n0 = L.xp[0][sy][sx + VX], n4 = L.xp[1][sy][sx + VX];
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const bool in = x + k + 1 < a.nx || a.W[0] == 0;
+            const bool self = a.W[0] && x + k == 0;
+            const T v0 = k + 1 < VX ? o0[(k + 1) % VX] : n0, v4 = k + 1 < VX ? o4[(k + 1) % VX] : n4;
+            l[0][k] = (in ? v0 : T(0)) + (self ? o0[k] : T(0));
+            l[4][k] = (in ? v4 : T(0)) + (self ? o4[k] : T(0));
+        }
+    }
+    {   // -x movers from the left neighbour
+        T o1[VX], o5[VX];
+        lds_load<T, VX>(o1, &L.xm[0][sy][VX + sx]);
+        lds_load<T, VX>(o5, &L.xm[1][sy][VX + sx]);
+        const T n1 = L.xm[0][sy][VX + sx - 1], n5 = L.xm[1][sy][VX + sx - 1];
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const bool in = x + k > 0 || a.W[0] == 0;
+            const bool self = a.W[0] && x + k == a.nx - 1;
+            const T v1 = k > 0 ? o1[(k + VX - 1) % VX] : n1, v5 = k > 0 ? o5[(k + VX - 1) % VX] : n5;
+            l[1][k] = (in ? v1 : T(0)) + (self ? o1[k] : T(0));
+            l[5][k] = (in ? v5 : T(0)) + (self ? o5[k] : T(0));
+        }
+    }
+    {   // +y movers from the row below, -y movers from the row above
+        const bool inp = y + 1 < a.ny || a.W[1] == 0, selfp = a.W[1] && y == 0;
+        const bool inm = y > 0 || a.W[1] == 0, selfm = a.W[1] && y == a.ny - 1;
+        T n2[VX], n6[VX], o2[VX], o6[VX], n3[VX], n7[VX], o3[VX], o7[VX];
+        lds_load<T, VX>(n2, &L.yp[0][sy + 1][sx]);
+        lds_load<T, VX>(n6, &L.yp[1][sy + 1][sx]);
+        lds_load<T, VX>(o2, &L.yp[0][sy][sx]);
+        lds_load<T, VX>(o6, &L.yp[1][sy][sx]);
+        lds_load<T, VX>(n3, &L.ym[0][sy][sx]);
+        lds_load<T, VX>(n7, &L.ym[1][sy][sx]);
+        lds_load<T, VX>(o3, &L.ym[0][sy + 1][sx]);
+        lds_load<T, VX>(o7, &L.ym[1][sy + 1][sx]);
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            l[2][k] = (inp ? n2[k] : T(0)) + (selfp ? o2[k] : T(0));
+            l[6][k] = (inp ? n6[k] : T(0)) + (selfp ? o6[k] : T(0));
+            l[3][k] = (inm ? n3[k] : T(0)) + (selfm ? o3[k] : T(0));
+            l[7][k] = (inm ? n7[k] : T(0)) + (selfm ? o7[k] : T(0));
+        }
+    }
+    const uint32_t c = (uint32_t)y * (uint32_t)a.sy + (uint32_t)x;
+#pragma unroll
+    for (int k = 0; k < VX; ++k) {
+        T f[11];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) f[i] = l[i][k];
+        f[8] = zp[0][k];
+        f[9] = zp[1][k];
+        f[10] = zp[2][k];
+        const int xf = fold(x + k, a.nx, a.W[0]);
+        adj_cell2d<T, POL>(a, t - 1, a.hist_prev, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx);
+#pragma unroll
+        for (int i = 0; i < 11; ++i) l[i][k] = f[i];
+    }
+    T *d = a.dst;
+    if (x + VX <= a.nx) {
+#pragma unroll
+        for (int i = 0; i < 11; ++i) store_aligned<T, VX>(at(d + i * a.plane, c), l[i]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VX; ++k)
+            if (x + k < a.nx)
+#pragma unroll
+                for (int i = 0; i < 11; ++i) *at(d + i * a.plane, c + k) = l[i][k];
+    }
 }
 
 // Objective weights for the adjoint source.  J = sum_a w_a kappa |P_a|^2

@@ -698,8 +698,9 @@ void reset_state(lbm_em *h) {
 }
 
 template <typename T>
+// One adjoint step at t, or (hist_prev given) the two steps t and t - 1.
 void launch_adjoint(const lbm_em *h, const void *src, void *dst, int64_t t, const void *hist, double *grad,
-                    const double *G) {
+                    const double *G, const void *hist_prev = nullptr) {
     AdjArgs<T> a{};
     a.nx = h->cfg.nx;
     a.ny = h->cfg.ny;
@@ -725,10 +726,30 @@ void launch_adjoint(const lbm_em *h, const void *src, void *dst, int64_t t, cons
         a.dlo[k] = h->dlo[k];
         a.dhi[k] = h->dhi[k];
     }
-    dim3 block(64, 4, 1);
-    dim3 grid((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, 1);
-    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_adjoint2d<T, TM>), grid, block, 0, h->stream, a);
-    else hipLaunchKernelGGL((k_adjoint2d<T, TE>), grid, block, 0, h->stream, a);
+    if (!hist_prev) {
+        dim3 block(64, 4, 1);
+        dim3 grid((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, 1);
+        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_adjoint2d<T, TM>), grid, block, 0, h->stream, a);
+        else hipLaunchKernelGGL((k_adjoint2d<T, TE>), grid, block, 0, h->stream, a);
+        return;
+    }
+    // two steps (t, t - 1) on the handle's two-step tile
+    a.hist_prev = (const T *)hist_prev;
+    const int tx = h->ftx, ty = h->fty;
+    a.tiles_x = (a.nx + tx - 1) / tx;
+    dim3 grid((unsigned)(a.tiles_x * ((a.ny + ty - 1) / ty)), 1, 1);
+#define LBM_ADJ2(TX, TY)                                                                                        \
+    if (tx == TX && ty == TY) {                                                                                 \
+        if (h->cfg.pol == LBM_EM_TM)                                                                            \
+            hipLaunchKernelGGL((k_adjoint2d_x2<T, TM, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, h->stream, a); \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_adjoint2d_x2<T, TE, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, h->stream, a); \
+        return;                                                                                                 \
+    }
+    if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_ADJ2) }
+    else { LBM_X2_TILES_F64(LBM_ADJ2) }
+#undef LBM_ADJ2
+    fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
 
 void free_handle(lbm_em *h) {
@@ -1483,13 +1504,17 @@ lbm_em_status lbm_em_backward(lbm_em_handle hh, double *grad_eps, int32_t where)
                     hip_check(hipGetLastError(), "recompute");
                     cur ^= 1;
                 }
-                // reverse sweep over the segment
-                for (int64_t t = t1 - 1; t >= t0; --t) {
-                    const char *hs = (const char *)hist + (size_t)(t - t0) * dcells * ncomp * h->elem;
-                    if (h->elem == 4) launch_adjoint<float>(h, abuf[ap], abuf[ap ^ 1], t, hs, grad, G);
-                    else launch_adjoint<double>(h, abuf[ap], abuf[ap ^ 1], t, hs, grad, G);
+                // reverse sweep over the segment (two steps per launch where
+                // the handle uses them)
+                auto hs = [&](int64_t tt) { return (const char *)hist + (size_t)(tt - t0) * dcells * ncomp * h->elem; };
+                for (int64_t t = t1 - 1; t >= t0;) {
+                    const bool two = h->fuse == 2 && t - 1 >= t0;
+                    const void *hp = two ? hs(t - 1) : nullptr;
+                    if (h->elem == 4) launch_adjoint<float>(h, abuf[ap], abuf[ap ^ 1], t, hs(t), grad, G, hp);
+                    else launch_adjoint<double>(h, abuf[ap], abuf[ap ^ 1], t, hs(t), grad, G, hp);
                     hip_check(hipGetLastError(), "adjoint step");
                     ap ^= 1;
+                    t -= two ? 2 : 1;
                 }
             }
             hip_check(hipMemcpyAsync(grad_eps, grad, dcells * sizeof(double),

@@ -48,3 +48,14 @@ def test_errors_are_status_codes_without_device():
     assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EINVAL
     assert L.lbm_em_create(None, C.byref(h)) == _lib.EINVAL
     assert L.lbm_em_step(None, 1) == _lib.EINVAL
+    # one population plane (rows padded to 64 cells) must stay below 4 GiB
+    cfg.absorb[0] = 0
+    cfg.nx, cfg.ny = 32768, 32768                      # FP32: exactly 4 GiB
+    assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EINVAL
+    assert b"4 GiB" in L.lbm_em_last_error()
+    cfg.nx = 32705                                     # padded to 32768: still 4 GiB
+    assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EINVAL
+    cfg.nx, cfg.ny = 32768, 32767                      # just below: passes to the device query
+    assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EDEVICE
+    cfg.precision, cfg.nx, cfg.ny = 1, 16384, 32768    # FP64: exactly 4 GiB
+    assert L.lbm_em_create(C.byref(cfg), C.byref(h)) == _lib.EINVAL

@@ -87,6 +87,32 @@ def test_checkpoint_spacing_is_bit_identical(P):
         assert J == grads[0][0] and np.array_equal(g, grads[0][1])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_two_step_adjoint_is_bit_identical(P, prec, pol):
+    """The backward pass with two adjoint steps per launch (and two-step
+    recompute) reproduces one step per launch bit for bit, for several
+    tiles, with absorbing or periodic x."""
+    th = np.arange(10.0, 20.01, 0.5)
+    for absorb in ((8, 8, 0), (0, 8, 0)):
+        case = _tiny_case()
+        case.pol = pol
+        case.absorb = absorb
+        runs = []
+        for fuse, tile in ((1, (0, 0)), (2, None), (2, (64, 16) if prec == "fp32" else (32, 16))):
+            inc, tot = _pair(P, case, prec, 1.0, theta=th, design=((16, 16), (23, 23)), ck=9)
+            if tile is None:
+                tot.set_fusion(fuse)
+            else:
+                tot.set_fusion(fuse, tile)
+            J = tot.forward_checkpointed(case.steps)
+            runs.append((J, tot.backward()))
+            say("two-step adjoint", prec, pol, absorb, fuse, tile, J)
+        for J, g in runs[1:]:
+            assert J == runs[0][0] and np.array_equal(g, runs[0][1])
+        assert np.abs(runs[0][1]).max() > 0
+
+
 def test_autograd_function(P):
     import torch
 

@@ -115,6 +115,32 @@ def test_three_d_sphere_fields(gpu, prec):
     compare_fields(s, o, prec, "3d sphere")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_source_phase_tables(gpu, prec):
+    """The incident wave comes from per-axis phase tables: oblique incidence
+    with all three axis phases non-zero (3-D), and a ramp of 1.5 periods
+    (an odd number of table entries before the per-axis tables), checked
+    during and after the ramp."""
+    th = np.deg2rad(35.0)
+    kh = [np.cos(th), np.sin(th), 0.0]
+    eps = np.ones((1, 50, 70))
+    eps[:, 20:30, 30:42] = 2.5
+    s, o = make_pair(gpu, 70, 50, 1, "TM", prec, (12, 12, 0), eps, 10.0, kh, [0, 0, 1.0], ramp=1.5)
+    for n in (20, 25, 105):
+        s.step(n)
+        o.step(n)
+        compare_fields(s, o, prec, f"tables 2-D t={o.t}")
+    k3 = np.array([1.0, 1.0, 1.0]) / np.sqrt(3.0)
+    e3 = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    eps3 = np.ones((24, 24, 24))
+    eps3[9:15, 9:15, 9:15] = 2.0
+    s, o = make_pair(gpu, 24, 24, 24, "3D", prec, (6, 6, 6), eps3, 10.0, list(k3), list(e3), ramp=1.5)
+    for n in (30, 60):
+        s.step(n)
+        o.step(n)
+        compare_fields(s, o, prec, f"tables 3-D t={o.t}")
+
+
 def test_graph_replay_equals_eager(gpu):
     """step(n) replays captured graphs in 64-step chunks; results must be
     bit-identical to single eager steps."""
