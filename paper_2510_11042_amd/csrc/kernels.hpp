@@ -1106,6 +1106,63 @@ __device__ inline void adj_pull_cell(const AdjArgs<T> &a, int x, int y, T l[11])
     l[10] = *at(m + 10 * P, c);
 }
 
+// Reverse pull of the VX cells x0 .. x0+VX-1 of row y (0 <= y < ny) and
+// their eps: the same values as adj_pull_cell per cell, with vector loads
+// when the segment has both x neighbours inside the domain.
+template <typename T, int VX>
+__device__ inline void adj_pull_row(const AdjArgs<T> &a, int x0, int y, T (&l)[11][VX], T (&e)[VX]) {
+    const uint32_t sy = (uint32_t)a.sy;
+    if (!(x0 > 0 && x0 + VX < a.nx)) {
+#pragma unroll
+        for (int k = 0; k < VX; ++k) {
+            const int xf = fold(x0 + k, a.nx, a.W[0]);
+            T f[11];
+            adj_pull_cell<T>(a, xf, y, f);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) l[i][k] = f[i];
+            e[k] = *at(a.eps, (uint32_t)y * sy + (uint32_t)xf);
+        }
+        return;
+    }
+    const int64_t P = a.plane;
+    const T *m = a.src;
+    const uint32_t c = (uint32_t)y * sy + (uint32_t)x0;
+    T v[VX];
+    // x movers: both neighbours inside, no face term
+    for (int i : {0, 4}) {
+        load_shifted<T, VX>(v, at(m + i * P, c + 1));
+#pragma unroll
+        for (int k = 0; k < VX; ++k) l[i][k] = v[k] + T(0);
+    }
+    for (int i : {1, 5}) {
+        load_shifted<T, VX>(v, at(m + i * P, c - 1));
+#pragma unroll
+        for (int k = 0; k < VX; ++k) l[i][k] = v[k] + T(0);
+    }
+    // y movers: the row rules are uniform over the segment
+    const bool inp = y + 1 < a.ny || a.W[1] == 0, selfp = a.W[1] && y == 0;
+    const bool inm = y > 0 || a.W[1] == 0, selfm = a.W[1] && y == a.ny - 1;
+    const uint32_t cp = (uint32_t)(y + 1 < a.ny ? y + 1 : 0) * sy + (uint32_t)x0;
+    const uint32_t cm = (uint32_t)(y > 0 ? y - 1 : a.ny - 1) * sy + (uint32_t)x0;
+    T o[VX];
+    for (int i : {2, 6}) {
+        load_aligned<T, VX>(v, at(m + i * P, cp));
+        load_aligned<T, VX>(o, at(m + i * P, c));
+#pragma unroll
+        for (int k = 0; k < VX; ++k) l[i][k] = (inp ? v[k] : T(0)) + (selfp ? o[k] : T(0));
+    }
+    for (int i : {3, 7}) {
+        load_aligned<T, VX>(v, at(m + i * P, cm));
+        load_aligned<T, VX>(o, at(m + i * P, c));
+#pragma unroll
+        for (int k = 0; k < VX; ++k) l[i][k] = (inm ? v[k] : T(0)) + (selfm ? o[k] : T(0));
+    }
+    load_aligned<T, VX>(l[8], at(m + 8 * P, c));
+    load_aligned<T, VX>(l[9], at(m + 9 * P, c));
+    load_aligned<T, VX>(l[10], at(m + 10 * P, c));
+    load_aligned<T, VX>(e, at(a.eps, c));
+}
+
 // One adjoint cell update at step t: l holds the reverse-pulled mu(t+1) on
 // entry and mu(t) on exit; hist = the recorded dE/deps of step t.  record:
 // the cell is in the domain and owned by this thread, so it adds its
@@ -1202,17 +1259,18 @@ __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<
 
     // step t on the thread's segment
     {
-        T l[11][VX];
+        T l[11][VX], e[VX];
+        adj_pull_row<T, VX>(a, x, yf, l, e);
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
             const int xf = fold(x + k, a.nx, a.W[0]);
             T f[11];
-            adj_pull_cell<T>(a, xf, yf, f);
-            const T e = *at(a.eps, (uint32_t)yf * (uint32_t)a.sy + (uint32_t)xf);
-            ep[k] = e;
-            ip[k] = recip(e);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) f[i] = l[i][k];
+            ep[k] = e[k];
+            ip[k] = recip(e[k]);
             sg[k] = adj_sigma<T>(a, xf, yf);
-            adj_cell2d<T, POL>(a, t, a.hist, xf, yf, e, ip[k], sg[k], f, x + k < a.nx && y < a.ny);
+            adj_cell2d<T, POL>(a, t, a.hist, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny);
 #pragma unroll
             for (int i = 0; i < 11; ++i) l[i][k] = f[i];
             zp[0][k] = f[8];
