@@ -166,10 +166,11 @@ def batched_extra(P, W, torch, steps=6000):
     b.step(steps)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    fuse = sims[0].get_fusion()     # two steps per launch: the state moves once per two steps
     res = {"workload": "64 seeded 2-D scatterers, sides 256-448, 6000 steps", "cells": cells,
            "groups": b.groups, "MLUPS": cells * steps / t_batch / 1e6,
-           "single_instance_MLUPS": cells * steps / t_single / 1e6,
-           "algorithmic_GBs": cells * steps * BYTES_2D / t_batch / 1e9}
+           "single_instance_MLUPS": cells * steps / t_single / 1e6, "steps_per_launch": fuse,
+           "algorithmic_GBs": cells * steps / fuse * BYTES_2D / t_batch / 1e9}
     res["batched_over_single"] = res["MLUPS"] / res["single_instance_MLUPS"]
     b.close()
     for s in sims:

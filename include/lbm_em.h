@@ -132,7 +132,9 @@ lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
  * chip-sized grid strides over).  All handles must share polarisation,
  * precision, stream and device and be at the same time step; each keeps
  * its own grid size, permittivity, source and contour.  Results are
- * bit-identical to lbm_em_step on each handle.  Uses the tile of hs[0].
+ * bit-identical to lbm_em_step on each handle.  Uses the launch settings of
+ * hs[0]; with two steps per launch, the tile with the fewest padded cells
+ * over all instances (hs[0]'s own tile when it is among the best).
  * EUNSUPPORTED for 3-D handles.  (One-shot form of the batch calls below.) */
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);
 

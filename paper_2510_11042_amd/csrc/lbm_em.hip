@@ -548,6 +548,36 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
         b->fuse = h0->fuse;
         b->ftx = h0->ftx;
         b->fty = h0->fty;
+        if (b->fuse == 2) {
+            // Two-step tile of the batch: the fewest padded cells over the
+            // instances (small, uneven grids waste much of a large tile);
+            // the handles' own tile when it is among the best, else the
+            // largest of them.
+            auto padded = [&](int tx, int ty) {
+                int64_t p = 0;
+                for (int i = 0; i < count; ++i) {
+                    const lbm_em *h = hs[i];
+                    p += (int64_t)((h->cfg.nx + tx - 1) / tx) * tx * (int64_t)((h->cfg.ny + ty - 1) / ty) * ty;
+                }
+                return p;
+            };
+            int64_t best = padded(b->ftx, b->fty);
+            int btx = b->ftx, bty = b->fty;
+#define LBM_X2_PICK(TX, TY)                                                                        \
+    {                                                                                              \
+        const int64_t p = padded(TX, TY);                                                          \
+        if (p < best || (p == best && (btx != b->ftx || bty != b->fty) && TX * TY > btx * bty)) { \
+            best = p;                                                                              \
+            btx = TX;                                                                              \
+            bty = TY;                                                                              \
+        }                                                                                          \
+    }
+            if (b->precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_PICK) }
+            else { LBM_X2_TILES_F64(LBM_X2_PICK) }
+#undef LBM_X2_PICK
+            b->ftx = btx;
+            b->fty = bty;
+        }
         b->budget = (int64_t)192 << 20;
         for (int i = 0; i < count; ++i) {
             b->hs.push_back(hs[i]);
