@@ -12,8 +12,10 @@ FP64 DFT accumulators.  Inputs are resident in device memory before timing.
 Reported value: lattice updates per second over the whole step (MLUPS).
 Also reported: the step kernel's achieved algorithmic bandwidth (92 B per
 cell per launch: the kernel advances two time steps per launch, reading and
-writing the 11-scalar state once) against the 8 TB/s HBM peak, an extra 3-D sphere
-measurement (384^3, 220 B per update), and the FP64 oracle timed on a
+writing the 11-scalar state once) against the 8 TB/s HBM peak, extras (the same
+job with the TM and TE instances on two concurrent HIP streams, a 3-D sphere
+(384^3, 220 B per update), a batched and an inverse-design configuration),
+and the FP64 oracle timed on a
 bounded sample of the same workload on the host cores together with the
 GPU-vs-oracle field error on that sample.
 """
@@ -58,7 +60,9 @@ def recorded_traffic(key, tile=None):
     return rec.get("bytes_per_launch")
 
 
-def cylinder_workload(Simulation, W, lbm_steps, tile=None):
+def cylinder_workload(Simulation, W, lbm_steps, tile=None, streams=None):
+    """The eight solves; with `streams` = {pol: stream handle} each
+    polarisation's instances are ordered on their own HIP stream."""
     sims = []
     for pol in ("TM", "TE"):
         for eps_in in (1.0, 1.5, 2.25, 4.0):
@@ -67,7 +71,7 @@ def cylinder_workload(Simulation, W, lbm_steps, tile=None):
                 case = W.vacuum_companion(case)
             kh, eh = W.plane_wave_2d(0.0, pol)
             s = Simulation(1024, 1024, 1, pol=pol, precision="fp32", absorb=case.absorb,
-                           sigma_max=W.SIGMA_MAX)
+                           sigma_max=W.SIGMA_MAX, stream=streams[pol] if streams else None)
             s.set_permittivity(case.eps)
             s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
             s.set_ntff(case.box_lo, case.box_hi, *case.window)
@@ -77,6 +81,8 @@ def cylinder_workload(Simulation, W, lbm_steps, tile=None):
     # two-step tile (profiling runs) replaces the tuning.
     for pol in ("TM", "TE"):
         group = [s for p, _, s in sims if p == pol]
+        if tile is True:
+            continue                  # the caller sets the tiles
         if tile:
             group[0].set_fusion(2, tile)
         else:
@@ -106,6 +112,46 @@ def run_workload(sims, lbm_steps, theta, torch, events):
             if p == pol and e != 1.0:
                 out[(pol, e)] = s.farfield(theta, incident=inc)
     return out
+
+
+def two_stream_extra(Simulation, W, torch, lbm_steps, theta, tiles):
+    """The same eight solves with the TM instances on one HIP stream and the
+    TE instances on a second one, enqueued alternately: two independent
+    step kernels share the GPU and overlap each other's load, compute and
+    store phases.  Whole job (stepping + far field), wall clock."""
+    import ctypes as C
+
+    st = {p: torch.cuda.Stream() for p in ("TM", "TE")}
+    sims = cylinder_workload(Simulation, W, lbm_steps, streams={p: C.c_void_p(v.cuda_stream) for p, v in st.items()},
+                             tile=None if tiles is None else True)
+    if tiles is not None:
+        for p, _, s in sims:
+            s.set_fusion(2, tiles[p])
+    tm = [s for p, _, s in sims if p == "TM"]
+    te = [s for p, _, s in sims if p == "TE"]
+
+    def job():
+        for a, b in zip(tm, te):
+            a.reset()
+            b.reset()
+            a.step(lbm_steps)
+            b.step(lbm_steps)
+        out = []
+        for pol in ("TM", "TE"):
+            inc = [s for p, e, s in sims if p == pol and e == 1.0][0]
+            out += [s.farfield(theta, incident=inc) for p, e, s in sims if p == pol and e != 1.0]
+        return out
+
+    job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for _, _, s in sims:
+        s.close()
+    return {"workload": "the benchmark's eight solves + NTFF, TM and TE instances on two HIP streams",
+            "MLUPS": len(sims) * 1024 * 1024 * lbm_steps / dt / 1e6, "seconds": dt}
 
 
 def sphere_extra(Simulation, W, torch, steps=200):
@@ -279,7 +325,7 @@ def main():
     ap.add_argument("--lbm-steps", type=int, default=8000, help="time steps per solve (workload: 8000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="copy,sphere,batched,adjoint",
+    ap.add_argument("--extras", default="copy,streams,sphere,batched,adjoint",
                     help="comma list of extra measurements to run")
     ap.add_argument("--tile", default=None,
                     help="two-step tile TX,TY instead of autotuning (profiling runs)")
@@ -364,6 +410,9 @@ def main():
         line["extra"] = {}
         if "copy" in want:
             line["roofline"]["measured_copy_GBs"] = copy_ceiling(P)
+        if "streams" in want and args.lbm_steps >= 2000:
+            tiles = {p: s.get_fusion_tile() for p, _, s in sims} if fuse == 2 else None
+            line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, args.lbm_steps, theta, tiles)
         if "sphere" in want:
             line["extra"]["sphere_3d"] = sphere_extra(Simulation, W, torch)
         if "batched" in want:
