@@ -55,7 +55,7 @@ def recorded_traffic(key, tile=None):
         return None
     if tile is not None:
         args = rec.get("kernel", "").split("<")[-1].rstrip(">").split(",")
-        if [a.strip() for a in args[2:]] != [str(t) for t in tile]:
+        if [a.strip() for a in args[-2:]] != [str(t) for t in tile]:
             return None
     return rec.get("bytes_per_launch")
 
@@ -166,14 +166,18 @@ def sphere_extra(Simulation, W, torch, steps=200):
     s.step(steps)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    fuse = s.get_fusion()           # steps per launch: the state moves once per launch
+    ms = e0.elapsed_time(e1) / steps * fuse
     cells = 384 ** 3
-    res = {"workload": "sphere-384^3-eps2.25-x6-lambda24", "cells": cells, "launches": steps,
-           "ms_per_launch": ms, "MLUPS": cells / (ms * 1e-3) / 1e6,
-           "algorithmic_bytes_per_update": BYTES_3D,
+    res = {"workload": "sphere-384^3-eps2.25-x6-lambda24", "cells": cells, "launches": steps // fuse,
+           "steps_per_launch": fuse, "kernel": "k_step3d_x2" if fuse == 2 else "k_step3d",
+           "tile": list(s.get_fusion_tile()) if fuse == 2 else list(s.get_tile()),
+           "ms_per_launch": ms, "MLUPS": cells * fuse / (ms * 1e-3) / 1e6,
+           "algorithmic_bytes_per_launch": cells * BYTES_3D,
            "achieved_GBs": cells * BYTES_3D / (ms * 1e-3) / 1e9}
     res["frac_of_hbm_peak"] = res["achieved_GBs"] / HBM_PEAK_GBS
-    res["traffic"] = recorded_traffic("k_step3d_fp32_384")
+    res["traffic"] = recorded_traffic(("k_step3d_x2" if fuse == 2 else "k_step3d") + "_fp32_384",
+                                      res["tile"] if fuse == 2 else None)
     s.close()
     return res
 

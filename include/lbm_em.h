@@ -165,18 +165,20 @@ lbm_em_status lbm_em_batch_destroy(lbm_em_batch b);
 lbm_em_status lbm_em_set_tile(lbm_em_handle h, int32_t vx, int32_t bx, int32_t by);
 lbm_em_status lbm_em_get_tile(lbm_em_handle h, int32_t *vx, int32_t *bx, int32_t *by);
 
-/* Time steps per launch of lbm_em_step: 1, or 2 for 2-D handles (two
- * steps fused through LDS: the state is read and written once per two
- * steps; bit-identical results; the 2-D default).  tile_x x tile_y is the
- * two-step kernel's output tile, one of 64x16, 64x8, 64x4, 32x16, 32x8,
- * 16x16 (0 x 0 keeps the current one).  EUNSUPPORTED for 2 on 3-D handles.
- * get_fusion's tile outputs may be NULL. */
+/* Time steps per launch of lbm_em_step: 1 or 2 (the default).  Two steps
+ * per launch read and write the state once per two steps and give bit-
+ * identical results: in 2-D a TX x TY tile plus a one-cell ring through LDS
+ * (FP32 tiles 64x16, 128x8, 128x16, 256x8, 256x16, 128x32; FP64 32x16,
+ * 64x8, 64x16, 128x8, 128x16, 64x32), in 3-D a TX x TY column tile that
+ * marches along z with a one-plane lag (FP32 64x16, 64x8, 32x16; FP64
+ * 32x16, 32x8, 16x16).  tile 0 x 0 keeps the current one; EINVAL for other
+ * tiles.  get_fusion's tile outputs may be NULL. */
 lbm_em_status lbm_em_set_fusion(lbm_em_handle h, int32_t steps_per_launch, int32_t tile_x, int32_t tile_y);
 lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y);
 
 /* Time every supported launch shape on this handle's grid -- one step per
- * launch with every tile, and (2-D) two steps per launch with every
- * two-step tile -- `launches` launches each, reading the current state and
+ * launch with every tile, and two steps per launch with every two-step
+ * tile -- `launches` launches each, reading the current state and
  * writing the spare buffer with the DFT off, so the simulation is not
  * advanced; keep the fastest per time step and verify that it reproduces
  * one-cell-per-thread single steps bit for bit (EDEVICE if not).

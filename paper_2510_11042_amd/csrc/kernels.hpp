@@ -884,12 +884,21 @@ __device__ inline void equilibrium3d(const T E[3], const T H[3], T eps, T scale,
 }
 
 template <typename T>
+__device__ inline T sigma3d(const StepArgs<T> &a, int x, int y, int z) {
+    return fmax(fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
+                     sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max)),
+                sigma_axis<T>(z, a.nz, a.W[2], a.inv_w[2], a.sigma_max));
+}
+
+// 3-D per-cell update (moments, DFT sample, collision, layer/source);
+// inv_eps = 1/eps and sig = sigma3d(x, y, z) from the caller; record: the
+// cell is in the domain and owned by this thread (DFT samples).
+template <typename T>
 __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, int z, T eps,
-                                     T f[27]) {
-    const T inv_eps = recip(eps);
+                                     T inv_eps, T sig, T f[27], bool record) {
     T E[3], H[3];
     fields3d(f, inv_eps, E, H);
-    if (st.dft) {
+    if (st.dft && record) {
         const double G[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
         dft_accumulate<0x3f>(a, st, 3, x, y, z, G);
     }
@@ -897,9 +906,6 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
     equilibrium3d(E, H, eps, T(2), q);
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = q[i] - f[i];
-    const T sig = fmax(fmax(sigma_axis<T>(x, a.nx, a.W[0], a.inv_w[0], a.sigma_max),
-                            sigma_axis<T>(y, a.ny, a.W[1], a.inv_w[1], a.sigma_max)),
-                       sigma_axis<T>(z, a.nz, a.W[2], a.inv_w[2], a.sigma_max));
     if (sig > T(0)) {
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
@@ -915,6 +921,29 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
 #pragma unroll
         for (int i = 0; i < 27; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
     }
+}
+
+// Pulled populations and eps of the in-domain cell (x, y, z): direction d
+// (planes 4d .. 4d+3) from r - c_d with the open-boundary clamp or wrap.
+template <typename T>
+__device__ inline void pull3d(const StepArgs<T> &a, int x, int y, int z, T f[27], T &e) {
+    const int64_t P = a.plane;
+    const T *s = a.src;
+    const uint32_t sy = (uint32_t)a.sy, sz = (uint32_t)a.sz;
+    const uint32_t zo = (uint32_t)z * sz, yo = (uint32_t)y * sy;
+    const uint32_t c = zo + yo + (uint32_t)x;
+    const uint32_t src[6] = {zo + yo + (uint32_t)pull_lo(x, a.nx, a.W[0]), zo + yo + (uint32_t)pull_hi(x, a.nx, a.W[0]),
+                             zo + (uint32_t)pull_lo(y, a.ny, a.W[1]) * sy + (uint32_t)x,
+                             zo + (uint32_t)pull_hi(y, a.ny, a.W[1]) * sy + (uint32_t)x,
+                             (uint32_t)pull_lo(z, a.nz, a.W[2]) * sz + yo + (uint32_t)x,
+                             (uint32_t)pull_hi(z, a.nz, a.W[2]) * sz + yo + (uint32_t)x};
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[4 * d + k] = *at(s + (4 * d + k) * P, src[d]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[24 + k] = *at(s + (24 + k) * P, c);
+    e = *at(a.eps, c);
 }
 
 template <typename T, int VX>
@@ -980,7 +1009,8 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
         T f[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) f[i] = v[i][j];
-        cell_update3d<T>(a, st, x0 + j, y, z, e[j], f);
+        const int xj = x0 + j < a.nx ? x0 + j : a.nx - 1;
+        cell_update3d<T>(a, st, xj, y, z, e[j], recip(e[j]), sigma3d<T>(a, xj, y, z), f, x0 + j < a.nx);
 #pragma unroll
         for (int i = 0; i < 27; ++i) v[i][j] = f[i];
     }
@@ -994,6 +1024,138 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
             if (x0 + j < a.nx)
 #pragma unroll
                 for (int i = 0; i < 27; ++i) *at(d + i * P, base + x0 + j) = v[i][j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D, two time steps per launch: a z march with a one-plane lag.
+//
+// A block of TX * TY threads (one cell each) owns an x-y tile and a chunk of
+// z planes [zb, ze).  Iteration p computes step t on plane p (the tile and a
+// one-cell x-y ring, pulling f*(t-1) from global memory) and then step t+1
+// on plane p - 1.  Step t+1 on plane q pulls its x/y movers from plane q's
+// neighbours -- kept in LDS, double-buffered by plane parity, each where it
+// is pulled from -- and its z movers from planes q - 1 and q + 1 of its own
+// column, which the same thread computed: the +z movers of the two previous
+// planes, the rest scalars, eps, 1/eps and sigma of plane p - 1 stay in its
+// registers.  Planes zb - 1 and ze (outside the chunk, folded at the domain
+// faces) are computed for their z movers only; they record nothing.  Every
+// cell runs cell_update3d, so the result is bit-identical to two one-step
+// launches.  HBM bytes per two steps: the state read once (plus the x-y ring
+// and the two extra planes per chunk) and written once.
+// ---------------------------------------------------------------------------
+template <typename T, int TX, int TY>
+struct X3Lds {
+    T xm[4][TY][TX + 1];   // +x movers (planes 0..3): left ring at column 0, tile column ox at ox + 1
+    T xp[4][TY][TX + 1];   // -x movers (planes 4..7): tile column ox at ox, right ring at TX
+    T ym[4][TY + 1][TX];   // +y movers (planes 8..11): ring row above at 0, tile row oy at oy + 1
+    T yp[4][TY + 1][TX];   // -y movers (planes 12..15): tile row oy at oy, ring row below at TY
+};
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
+    constexpr int NT = TX * TY;
+    constexpr int NR = 2 * TX + 2 * TY;
+    static_assert(NR <= NT, "ring larger than the block");
+    __shared__ X3Lds<T, TX, TY> L[2];
+    const int tiles = a.tiles_x * a.tiles_y;
+    const int tile = blockIdx.x % tiles, chunk = blockIdx.x / tiles;
+    const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
+    const int zb = chunk * zc, ze = min(zb + zc, a.nz);
+    const int tid = threadIdx.x;
+    const int ox = tid % TX, oy = tid / TX;
+    const int x = x0 + ox, y = y0 + oy;
+    const bool own = x < a.nx && y < a.ny;
+    const int xf = fold(x, a.nx, a.W[0]), yf = fold(y, a.ny, a.W[1]);
+    const int64_t t = step_time(a.t_base, a.t_off);
+    const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
+    // this thread's ring cell (same x-y position on every plane)
+    const bool ring = tid < NR;
+    int rx = 0, ry = 0;
+    if (tid < TX) { rx = x0 + tid; ry = y0 - 1; }
+    else if (tid < 2 * TX) { rx = x0 + (tid - TX); ry = y0 + TY; }
+    else if (tid < 2 * TX + TY) { rx = x0 - 1; ry = y0 + (tid - 2 * TX); }
+    else { rx = x0 + TX; ry = y0 + (tid - 2 * TX - TY); }
+    const int rxf = fold(rx, a.nx, a.W[0]), ryf = fold(ry, a.ny, a.W[1]);
+    // per-column history: +z movers of planes p-2 (pz0) and p-1 (pz1); rest
+    // scalars, eps, 1/eps and sigma of plane p-1
+    T pz0[4], pz1[4], rest[3], ep = T(1), ip = T(1), sg = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pz0[k] = pz1[k] = T(0);
+    rest[0] = rest[1] = rest[2] = T(0);
+    const int64_t P = a.plane;
+    const uint32_t sy = (uint32_t)a.sy, sz = (uint32_t)a.sz;
+
+    for (int p = zb - 1; p <= ze; ++p) {
+        const int pf = fold(p, a.nz, a.W[2]);
+        X3Lds<T, TX, TY> &B = L[p & 1];
+        // step t on plane p: own cell ...
+        T f[27], e;
+        pull3d<T>(a, xf, yf, pf, f, e);
+        const T ie = recip(e), sgp = sigma3d<T>(a, xf, yf, pf);
+        cell_update3d<T>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            B.xm[k][oy][ox + 1] = f[k];
+            B.xp[k][oy][ox] = f[4 + k];
+            B.ym[k][oy + 1][ox] = f[8 + k];
+            B.yp[k][oy][ox] = f[12 + k];
+        }
+        // ... and the ring cell (only the movers that step t+1 pulls)
+        if (ring) {
+            T g[27], ge;
+            pull3d<T>(a, rxf, ryf, pf, g, ge);
+            cell_update3d<T>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf), g, false);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (tid < TX) B.ym[k][0][tid] = g[8 + k];
+                else if (tid < 2 * TX) B.yp[k][TY][tid - TX] = g[12 + k];
+                else if (tid < 2 * TX + TY) B.xm[k][ry - y0][0] = g[k];
+                else B.xp[k][ry - y0][TX] = g[4 + k];
+            }
+        }
+        __syncthreads();
+        // step t+1 on plane q = p - 1
+        const int q = p - 1;
+        if (q >= zb) {
+            const X3Lds<T, TX, TY> &A = L[q & 1];
+            T h[27];
+            const int cxm = (a.W[0] && x == 0) ? ox + 1 : ox;          // +x movers from x-1 (own on the face)
+            const int cxp = (a.W[0] && x == a.nx - 1) ? ox : ox + 1;   // -x movers from x+1
+            const int rym = (a.W[1] && y == 0) ? oy + 1 : oy;          // +y movers from y-1
+            const int ryp = (a.W[1] && y == a.ny - 1) ? oy : oy + 1;   // -y movers from y+1
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                h[k] = A.xm[k][oy][cxm];
+                h[4 + k] = A.xp[k][oy][cxp];
+                h[8 + k] = A.ym[k][rym][ox];
+                h[12 + k] = A.yp[k][ryp][ox];
+                h[16 + k] = pz0[k];        // +z movers from plane q - 1
+                h[20 + k] = f[20 + k];     // -z movers from plane q + 1 = p
+            }
+            h[24] = rest[0];
+            h[25] = rest[1];
+            h[26] = rest[2];
+            cell_update3d<T>(a, s1, xf, yf, q, ep, ip, sg, h, own);
+            if (own) {
+                const uint32_t c = (uint32_t)q * sz + (uint32_t)y * sy + (uint32_t)x;
+#pragma unroll
+                for (int i = 0; i < 27; ++i) *at(a.dst + i * P, c) = h[i];
+            }
+        }
+        __syncthreads();
+        // plane p becomes the previous plane
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pz0[k] = pz1[k];
+            pz1[k] = f[16 + k];
+        }
+        rest[0] = f[24];
+        rest[1] = f[25];
+        rest[2] = f[26];
+        ep = e;
+        ip = ie;
+        sg = sgp;
     }
 }
 

@@ -75,7 +75,8 @@ struct lbm_em {
     int64_t t = 0;
     hipStream_t stream = nullptr;
     int vx = 1, bx = 128, by = 2;       // cells per thread along x, block shape
-    int fuse = 1;                       // time steps per launch (1, or 2 in 2-D)
+    int fuse = 1;                       // time steps per launch (1 or 2)
+    int cus = 1;                        // compute units of the device
     int ftx = 64, fty = 16;             // output tile of the two-step kernel
     // source
     bool src_on = false;
@@ -260,6 +261,48 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
     fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
 
+// 3-D two-step tiles (one cell per thread; the LDS holds two planes of the
+// tile's x/y movers: 136 KB for 64 x 16 FP32 and 32 x 16 FP64).
+#define LBM_X3_TILES_F32(M) M(64, 16) M(64, 8) M(32, 16)
+#define LBM_X3_TILES_F64(M) M(32, 16) M(32, 8) M(16, 16)
+
+// z chunk of the 3-D two-step kernel: each block marches zc planes plus two
+// extra ones; pick the chunk count that minimises rounds x (zc + 2).
+int x3_chunk(int nz, int tiles, int slots) {
+    int best_zc = nz;
+    int64_t best = INT64_MAX;
+    for (int n = 1; n <= nz; ++n) {
+        const int zc = (nz + n - 1) / n;
+        const int64_t blocks = (int64_t)tiles * ((nz + zc - 1) / zc);
+        const int64_t rounds = (blocks + slots - 1) / slots;
+        const int64_t cost = rounds * (zc + 2);
+        if (cost < best) {
+            best = cost;
+            best_zc = zc;
+        }
+    }
+    return best_zc;
+}
+
+template <typename T>
+void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
+    const int tx = h->ftx, ty = h->fty;
+    a.tiles_x = (a.nx + tx - 1) / tx;
+    a.tiles_y = (a.ny + ty - 1) / ty;
+    const int tiles = a.tiles_x * a.tiles_y;
+    const int zc = x3_chunk(a.nz, tiles, h->cus * std::max(1, 1024 / (tx * ty)));
+    dim3 grid((unsigned)(tiles * ((a.nz + zc - 1) / zc)), 1, 1);
+#define LBM_X3(TX, TY)                                                                      \
+    if (tx == TX && ty == TY) {                                                             \
+        hipLaunchKernelGGL((k_step3d_x2<T, TX, TY>), grid, dim3(TX * TY), 0, s, a, zc);     \
+        return;                                                                             \
+    }
+    if constexpr (sizeof(T) == 4) { LBM_X3_TILES_F32(LBM_X3) }
+    else { LBM_X3_TILES_F64(LBM_X3) }
+#undef LBM_X3
+    fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
+}
+
 template <typename T>
 void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base, int64_t t_off,
                     hipStream_t s, bool dft, void *hist = nullptr, int64_t hist_t0 = 0) {
@@ -276,7 +319,8 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
         }
     }
     if (h->cfg.pol == LBM_EM_TM) launch_step2_pol<T, TM>(a, h->ftx, h->fty, s);
-    else launch_step2_pol<T, TE>(a, h->ftx, h->fty, s);
+    else if (h->cfg.pol == LBM_EM_TE) launch_step2_pol<T, TE>(a, h->ftx, h->fty, s);
+    else launch_step2_3d<T>(h, a, s);
 }
 
 void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
@@ -287,9 +331,12 @@ void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_
     else launch_step2_t<double>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
 }
 
-bool fused_tile_ok(int precision, int tx, int ty) {
+bool fused_tile_ok(int dim, int precision, int tx, int ty) {
 #define LBM_X2_OK(TX, TY) if (tx == TX && ty == TY) return true;
-    if (precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_OK) }
+    if (dim == 3) {
+        if (precision == LBM_EM_FP32) { LBM_X3_TILES_F32(LBM_X2_OK) }
+        else { LBM_X3_TILES_F64(LBM_X2_OK) }
+    } else if (precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_OK) }
     else { LBM_X2_TILES_F64(LBM_X2_OK) }
 #undef LBM_X2_OK
     return false;
@@ -848,11 +895,17 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             h->dim = c.pol == LBM_EM_3D ? 3 : 2;
             h->nplanes = c.pol == LBM_EM_3D ? 27 : 11;
             h->elem = c.precision == LBM_EM_FP32 ? 4 : 8;
+            hip_check(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->dev), "attribute");
+            h->cus = std::max(1, h->cus);
             if (h->dim == 2) {
                 h->fuse = 2;
                 // 1024-thread tiles: the smallest re-read halo (autotune may
                 // pick another)
                 h->ftx = c.precision == LBM_EM_FP32 ? 256 : 128;
+                h->fty = 16;
+            } else {
+                h->fuse = 2;      // z march, one-plane lag (k_step3d_x2)
+                h->ftx = c.precision == LBM_EM_FP32 ? 64 : 32;
                 h->fty = 16;
             }
             h->sy = round_up(c.nx, 64);
@@ -1127,12 +1180,14 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         if (steps_per_launch != 1 && steps_per_launch != 2) fail(LBM_EM_EINVAL, "steps_per_launch must be 1 or 2");
-        if (steps_per_launch == 2 && h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "two steps per launch is 2-D only");
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
-            if (!fused_tile_ok(h->cfg.precision, tile_x, tile_y))
-                fail(LBM_EM_EINVAL, h->cfg.precision == LBM_EM_FP32
-                                        ? "FP32 two-step tile must be 64x16, 128x8, 128x16, 256x8, 256x16 or 128x32"
-                                        : "FP64 two-step tile must be 32x16, 64x8, 64x16, 128x8, 128x16 or 64x32");
+            if (!fused_tile_ok(h->dim, h->cfg.precision, tile_x, tile_y))
+                fail(LBM_EM_EINVAL,
+                     h->dim == 3 ? (h->cfg.precision == LBM_EM_FP32 ? "3-D FP32 two-step tile must be 64x16, 64x8 or 32x16"
+                                                                    : "3-D FP64 two-step tile must be 32x16, 32x8 or 16x16")
+                     : h->cfg.precision == LBM_EM_FP32
+                         ? "FP32 two-step tile must be 64x16, 128x8, 128x16, 256x8, 256x16 or 128x32"
+                         : "FP64 two-step tile must be 32x16, 64x8, 64x16, 128x8, 128x16 or 64x32");
             h->ftx = tile_x;
             h->fty = tile_y;
         }
@@ -1172,12 +1227,15 @@ lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_u
         for (int vx : {1, 2, 4})
             for (auto &sh : shapes)
                 if (tile_ok(h, vx, sh[0], sh[1])) cands.push_back({1, vx, sh[0], sh[1]});
-        if (h->dim == 2) {
 #define LBM_X2_CAND(TX, TY) cands.push_back({2, TX, TY, 0});
+        if (h->dim == 2) {
             if (h->cfg.precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_CAND) }
             else { LBM_X2_TILES_F64(LBM_X2_CAND) }
-#undef LBM_X2_CAND
+        } else {
+            if (h->cfg.precision == LBM_EM_FP32) { LBM_X3_TILES_F32(LBM_X2_CAND) }
+            else { LBM_X3_TILES_F64(LBM_X2_CAND) }
         }
+#undef LBM_X2_CAND
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
