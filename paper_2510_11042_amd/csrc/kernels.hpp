@@ -902,10 +902,22 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
         const double G[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
         dft_accumulate<0x3f>(a, st, 3, x, y, z, G);
     }
-    T q[27];
-    equilibrium3d(E, H, eps, T(2), q);
+    // collision f <- 2 f^eq - f, one fused multiply-add per population
+    {
+        const T c = T(1) / T(3);
+        const T r = T(2) * (eps - T(1));
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f[i] = q[i] - f[i];
+        for (int d = 0; d < 6; ++d) {
+            const T cv[3] = {T(C3[d][0]), T(C3[d][1]), T(C3[d][2])};
+            T cxh[3];
+            cross3(cv, H, cxh);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) f[4 * d + k] = fma(c, E[k] - cxh[k], -f[4 * d + k]);
+            f[4 * d + 3] = fma(c, cv[0] * H[0] + cv[1] * H[1] + cv[2] * H[2], -f[4 * d + 3]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[24 + k] = fma(r, E[k], -f[24 + k]);
+    }
     if (sig > T(0)) {
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
