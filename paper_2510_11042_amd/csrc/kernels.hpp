@@ -1071,7 +1071,10 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
     static_assert(NR <= NT, "ring larger than the block");
     __shared__ X3Lds<T, TX, TY> L[2];
     const int tiles = a.tiles_x * a.tiles_y;
-    const int tile = blockIdx.x % tiles, chunk = blockIdx.x / tiles;
+    // XCD-banded order: neighbouring tiles of a chunk share an L2, so the
+    // ring cells' reads of a neighbour's plane hit it
+    const int bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = bid % tiles, chunk = bid / tiles;
     const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
     const int zb = chunk * zc, ze = min(zb + zc, a.nz);
     const int tid = threadIdx.x;
