@@ -638,37 +638,34 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
     constexpr int VX = X2Lds<T, TX, TY>::VX;
     constexpr int TPR = TX / VX;             // segments per tile row
-    constexpr int NI = 1;                    // segments per thread
     constexpr int NT = x2_threads<T, TX, TY>();
     constexpr int NR = 2 * TX + 2 * TY;      // ring cells
     static_assert(x2_tile_ok<T, TX, TY>(), "two-step tile shape");
     const int tid = threadIdx.x;
-    T zp[NI][3][VX], ep[NI][VX], ip[NI][VX], sg[NI][VX];
+    const int sx = (tid % TPR) * VX, sy = tid / TPR;   // the thread's segment in the tile
+    const int x = x0 + sx, y = y0 + sy;
+    T zp[3][VX], ep[VX], ip[VX], sg[VX];
 
     // step t on the thread's own segment
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-        const int seg = tid + NT * it;
-        const int sx = (seg % TPR) * VX, sy = seg / TPR;
-        const int x = x0 + sx, y = y0 + sy;
+    {
         const int yf = fold(y, a.ny, a.W[1]);
         T v[11][VX], e[VX];
         pull_row<T, VX>(a, x, yf, v, e);
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
             const int xf = fold(x + k, a.nx, a.W[0]);
-            ep[it][k] = e[k];
-            ip[it][k] = recip(e[k]);
-            sg[it][k] = sigma2d<T>(a, xf, yf);
+            ep[k] = e[k];
+            ip[k] = recip(e[k]);
+            sg[k] = sigma2d<T>(a, xf, yf);
             T f[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL, HIST>(a, s0, xf, yf, e[k], ip[it][k], sg[it][k], f, x + k < a.nx && y < a.ny);
+            cell_update2d<T, POL, HIST>(a, s0, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
-            zp[it][0][k] = f[8];
-            zp[it][1][k] = f[9];
-            zp[it][2][k] = f[10];
+            zp[0][k] = f[8];
+            zp[1][k] = f[9];
+            zp[2][k] = f[10];
         }
         lds_store<T, VX>(&L.xm[0][sy][VX + sx], v[0]);
         lds_store<T, VX>(&L.xm[1][sy][VX + sx], v[4]);
@@ -683,12 +680,12 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     // tile and the columns to its left and right (no corners: nothing pulls
     // from them)
     for (int r = tid; r < NR; r += NT) {
-        int x, y;
-        if (r < TX) { x = x0 + r; y = y0 - 1; }
-        else if (r < 2 * TX) { x = x0 + (r - TX); y = y0 + TY; }
-        else if (r < 2 * TX + TY) { x = x0 - 1; y = y0 + (r - 2 * TX); }
-        else { x = x0 + TX; y = y0 + (r - 2 * TX - TY); }
-        const int xf = fold(x, a.nx, a.W[0]), yf = fold(y, a.ny, a.W[1]);
+        int rx, ry;
+        if (r < TX) { rx = x0 + r; ry = y0 - 1; }
+        else if (r < 2 * TX) { rx = x0 + (r - TX); ry = y0 + TY; }
+        else if (r < 2 * TX + TY) { rx = x0 - 1; ry = y0 + (r - 2 * TX); }
+        else { rx = x0 + TX; ry = y0 + (r - 2 * TX - TY); }
+        const int xf = fold(rx, a.nx, a.W[0]), yf = fold(ry, a.ny, a.W[1]);
         T v[11][1], e[1];
         pull_row<T, 1>(a, xf, yf, v, e);
         T f[11];
@@ -702,22 +699,18 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             L.yp[0][TY][r - TX] = f[3];
             L.yp[1][TY][r - TX] = f[7];
         } else if (r < 2 * TX + TY) {
-            L.xm[0][y - y0][VX - 1] = f[0];
-            L.xm[1][y - y0][VX - 1] = f[4];
+            L.xm[0][ry - y0][VX - 1] = f[0];
+            L.xm[1][ry - y0][VX - 1] = f[4];
         } else {
-            L.xp[0][y - y0][TX] = f[1];
-            L.xp[1][y - y0][TX] = f[5];
+            L.xp[0][ry - y0][TX] = f[1];
+            L.xp[1][ry - y0][TX] = f[5];
         }
     }
     __syncthreads();
 
-    // step t+1 on the thread's own segments
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-        const int seg = tid + NT * it;
-        const int sx = (seg % TPR) * VX, sy = seg / TPR;
-        const int x = x0 + sx, y = y0 + sy;
-        if (x >= a.nx || y >= a.ny) continue;
+    // step t+1 on the thread's own segment
+    if (x >= a.nx || y >= a.ny) return;
+    {
         T v[11][VX];
         {   // +x movers from the left neighbour (own value on an absorbing left face)
             T o0[VX], o4[VX];
@@ -758,10 +751,10 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             T f[11];
 #pragma unroll
             for (int i = 0; i < 8; ++i) f[i] = v[i][k];
-            f[8] = zp[it][0][k];
-            f[9] = zp[it][1][k];
-            f[10] = zp[it][2][k];
-            cell_update2d<T, POL, HIST>(a, s1, xf, y, ep[it][k], ip[it][k], sg[it][k], f, x + k < a.nx);
+            f[8] = zp[0][k];
+            f[9] = zp[1][k];
+            f[10] = zp[2][k];
+            cell_update2d<T, POL, HIST>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
         }

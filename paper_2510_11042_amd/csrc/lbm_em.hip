@@ -237,8 +237,8 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
 }
 
 // Two steps in one launch (2-D): reads src, writes f*(t+1) to dst.
-// Two-step tiles: TX x TY cells, TX a multiple of the 16-byte segment and
-// TX*TY a multiple of 256 segments' worth (see x2_tile_ok).
+// Two-step tiles: TX x TY cells, TX a multiple of the 16-byte segment, one
+// segment per thread and 256, 512 or 1024 threads (see x2_tile_ok).
 #define LBM_X2_TILES_F32(M) M(64, 16) M(128, 8) M(128, 16) M(256, 8) M(256, 16) M(128, 32)
 #define LBM_X2_TILES_F64(M) M(32, 16) M(64, 8) M(64, 16) M(128, 8) M(128, 16) M(64, 32)
 

@@ -111,7 +111,8 @@ class Simulation:
         L.check(L.lib().lbm_em_set_tile(self._h, int(vx), int(bx), int(by)))
 
     def set_fusion(self, steps_per_launch, tile=(0, 0)):
-        """Time steps per launch (1, or 2 in 2-D) and the two-step tile."""
+        """Time steps per launch (1 or 2) and the two-step tile (TX, TY);
+        (0, 0) keeps the current tile."""
         L.check(L.lib().lbm_em_set_fusion(self._h, int(steps_per_launch), int(tile[0]), int(tile[1])))
 
     def get_fusion(self):
