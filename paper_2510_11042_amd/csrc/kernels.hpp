@@ -415,9 +415,12 @@ __device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
 // them for the second step).  record: the cell is in the domain and owned by
 // this thread, so it may add DFT samples and design-region history.
 // ---------------------------------------------------------------------------
-template <typename T, int POL, bool HIST = false>
+// PH: the cell's incident-wave phase factor (ur, ui) = e^{2 pi j u} was
+// gathered by the caller (the two-step kernel prefetches it for the tiles
+// that touch the layer), else it is gathered here.
+template <typename T, int POL, bool HIST = false, bool PH = false>
 __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, T eps,
-                                     T inv_eps, T sig, T f[11], bool record) {
+                                     T inv_eps, T sig, T f[11], bool record, T ur = T(0), T ui = T(0)) {
     const int64_t t = st.t;
     T F[3];
     fields2d<T, POL>(f, eps, inv_eps, F);
@@ -449,7 +452,7 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
         // f + sig (f_ref - f), one fused multiply-add per population
         T R[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
-            const T w = plane_wave<T, 2>(a, st, x, y, 0);
+            const T w = PH ? st.gs * ur - st.gc * ui : plane_wave<T, 2>(a, st, x, y, 0);
             if (POL == TM) { R[0] = w * a.ehat[2]; R[1] = w * a.hhat[0]; R[2] = w * a.hhat[1]; }
             else { R[0] = w * a.ehat[0]; R[1] = w * a.ehat[1]; R[2] = w * a.hhat[2]; }
         }
@@ -646,11 +649,28 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     const int x = x0 + sx, y = y0 + sy;
     T zp[3][VX], ep[VX], ip[VX], sg[VX];
 
+    // tiles that reach into the absorbing layer prefetch the incident-wave
+    // phase factors of their cells with the state (block-uniform test)
+    const bool layer_tile = a.src_on && ((a.W[0] && (x0 < a.W[0] || x0 + TX > a.nx - a.W[0])) ||
+                                         (a.W[1] && (y0 < a.W[1] || y0 + TY > a.ny - a.W[1])));
+    T ur[VX], ui[VX];
+
     // step t on the thread's own segment
     {
         const int yf = fold(y, a.ny, a.W[1]);
         T v[11][VX], e[VX];
         pull_row<T, VX>(a, x, yf, v, e);
+#pragma unroll
+        for (int k = 0; k < VX; ++k) ur[k] = ui[k] = T(0);
+        if (layer_tile) {
+            const auto py = a.wave_y[yf];
+#pragma unroll
+            for (int k = 0; k < VX; ++k) {
+                const auto px = a.wave_x[fold(x + k, a.nx, a.W[0])];
+                ur[k] = px.x * py.x - px.y * py.y;
+                ui[k] = px.x * py.y + px.y * py.x;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < VX; ++k) {
             const int xf = fold(x + k, a.nx, a.W[0]);
@@ -660,7 +680,8 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             T f[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL, HIST>(a, s0, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny);
+            cell_update2d<T, POL, HIST, true>(a, s0, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny,
+                                              ur[k], ui[k]);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
             zp[0][k] = f[8];
@@ -754,7 +775,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             f[8] = zp[0][k];
             f[9] = zp[1][k];
             f[10] = zp[2][k];
-            cell_update2d<T, POL, HIST>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx);
+            cell_update2d<T, POL, HIST, true>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx, ur[k], ui[k]);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
         }
