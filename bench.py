@@ -402,6 +402,10 @@ def main():
                      "tile": tile,
                      "ms_per_launch": ms_per_launch,
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "per_update_equivalent_GBs": alg_bytes * fuse / (ms_per_launch * 1e-3) / 1e9,
+                     "frac_note": "achieved counts the launch's minimal traffic (state read and written once per "
+                                  "launch, 92 B per cell); per_update_equivalent_GBs counts 92 B per cell update, "
+                                  "the bandwidth a one-step kernel would need for the same speed",
                      "note": "state 2 x 46 MB + eps 4 MB per instance fits the 256 MB Infinity Cache"},
     }
     # the computed intensities must be finite and positive
