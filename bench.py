@@ -44,19 +44,17 @@ def kernel_hash():
 
 
 def recorded_traffic(key, tile=None):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or
-    None when absent, taken on a different kernel source, or (two-step
-    kernel) on a different tile."""
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/) for
+    `key` and (two-step kernels) the tile, or None when absent or taken on
+    a different kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
+    if tile is not None:
+        key = f"{key}_{tile[0]}x{tile[1]}"
     rec = json.load(open(path)).get(key)
     if not rec or rec.get("kernel_hash") != kernel_hash():
         return None
-    if tile is not None:
-        args = rec.get("kernel", "").split("<")[-1].rstrip(">").split(",")
-        if [a.strip() for a in args[-2:]] != [str(t) for t in tile]:
-            return None
     return rec.get("bytes_per_launch")
 
 
