@@ -9,10 +9,12 @@ from oracle.analytic import fresnel_normal, fresnel_oblique
 from oracle.core import Oracle
 
 
-def _row_phasors(case):
+def _row_phasors(case, mu=None):
     """DFT of E (and H) along the row y = 0 over the last period."""
     o = Oracle(case.nx, case.ny, 1, case.absorb, W.SIGMA_MAX)
     o.set_eps(case.eps)
+    if mu is not None:
+        o.set_mu(mu)
     kh, eh = W.plane_wave_2d(case.theta_deg, case.pol)
     o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
     w0, wl = case.window
@@ -50,6 +52,68 @@ def test_fresnel_planar_interface(theta, pol):
         x = np.arange(case.nx)
         ratio = (E_t[vac, 2] - E_i[vac, 2]) / E_i[vac, 2] * np.exp(-2j * k * (x[vac] - 127.5))
         assert np.real(np.mean(ratio)) < -0.19
+
+
+@pytest.mark.parametrize("eps_in,mu_in", [(1.0, 4.0), (2.25, 2.25), (2.0, 3.0)])
+def test_fresnel_magnetic_interface(eps_in, mu_in):
+    """Normal incidence onto a half space of (eps_r, mu_r) (section 2.1 with a
+    permeability map; section 3.1, Eq. ref_trans with mu_r kept):
+    r = (sqrt(mu) - sqrt(eps)) / (sqrt(mu) + sqrt(eps)), t = 2 sqrt(mu) / (...).
+    eps = 1, mu = 4 reflects +1/3 (no sign flip, unlike a dielectric) and
+    transmits 4/3; eps = mu is impedance matched (no reflection, t = 1).
+    Run at lambda = 64: the transmitted amplitude carries the scheme's
+    second-order error in the denser medium, which grows as (k n)^2 (1.3 % at
+    32 cells per vacuum wavelength and n = 2, 0.3 % at 64), so its relative
+    bound is 1.5e-3 * eps * mu at 64."""
+    case = W.fresnel_case(0.0, "TM", nx=512, steps=6000, eps_in=eps_in, lam=64.0)
+    mu = W.half_space(case.nx, case.ny, case.nx // 2, mu_in)
+    tot = _row_phasors(case, mu)[:, 2]
+    inc = _row_phasors(W.vacuum_companion(case))[:, 2]
+    vac = slice(20 + 8, case.nx // 2 - 8)
+    die = slice(case.nx // 2 + 8, case.nx - 20 - 8)
+    r_meas = np.mean(np.abs(tot[vac] - inc[vac]) / np.abs(inc[vac]))
+    t_meas = np.mean(np.abs(tot[die]) / np.abs(inc[die]))
+    r_ref, t_ref = fresnel_normal(eps_in, mu_in)
+    assert abs(r_meas - abs(r_ref)) < 0.005, (r_meas, r_ref)
+    assert abs(t_meas / t_ref - 1.0) < 1.5e-3 * eps_in * mu_in, (t_meas, t_ref)
+    if abs(r_ref) > 0.1:
+        # the sign of E_r / E_i at the interface is that of sqrt(mu) - sqrt(eps)
+        k = 2 * np.pi / case.lam
+        x = np.arange(case.nx)
+        ratio = (tot[vac] - inc[vac]) / inc[vac] * np.exp(-2j * k * (x[vac] - (case.nx / 2 - 0.5)))
+        assert np.sign(np.real(np.mean(ratio))) == np.sign(r_ref), (np.mean(ratio), r_ref)
+
+
+@pytest.mark.parametrize("theta", [0.0, 30.0])
+def test_electromagnetic_duality(theta):
+    """Maxwell's equations are invariant under E -> H, H -> -E with eps and
+    mu exchanged, which turns a TM_z problem into a TE_z one.  The D3Q7
+    scheme treats e and h alike (section 2.1), so a TM run with (eps, mu)
+    maps exactly onto a TE run with (mu, eps): E_z(TM) = H_z(TE) and
+    H_y(TM) = -E_y(TE) on every cell.  This pins the permeability path
+    against the permittivity one, which the dielectric Fresnel and Mie
+    tests pin in turn."""
+    n = 96
+    y, x = np.mgrid[0:n, 0:n]
+    blob = ((x - 48) ** 2 + (y - 44) ** 2 < 15 ** 2).astype(float)
+    ring = ((x - 40) ** 2 + (y - 52) ** 2 < 9 ** 2).astype(float)
+    eps = (1.0 + 1.5 * blob)[None]
+    mu = (1.0 + 2.0 * ring)[None]
+    out = []
+    for pol, e_map, m_map in (("TM", eps, mu), ("TE", mu, eps)):
+        o = Oracle(n, n, 1, (16, 16, 0), W.SIGMA_MAX)
+        o.set_eps(e_map)
+        o.set_mu(m_map)
+        kh, eh = W.plane_wave_2d(theta, pol)
+        o.set_source(24.0, kh, eh, 1.0, W.RAMP_PERIODS)
+        o.step(300)
+        out.append(o.fields())
+    (e1, h1), (e2, h2) = out
+    scale = np.max(np.abs(e1[..., 2]))
+    assert scale > 0.1
+    assert np.max(np.abs(e1[..., 2] - h2[..., 2])) <= 1e-12 * scale
+    assert np.max(np.abs(h1[..., 0] + e2[..., 0])) <= 1e-12 * scale
+    assert np.max(np.abs(h1[..., 1] + e2[..., 1])) <= 1e-12 * scale
 
 
 def test_absorbing_layer_energy_decay():
