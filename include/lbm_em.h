@@ -69,8 +69,8 @@ typedef struct {
 /* Incident plane wave E = g(t) E0 ehat sin(omega t - k khat.(r - center)),
  * H = khat x E, omega = 2 pi/(3 lambda), k = 2 pi/lambda, g(t) =
  * sin^2(pi t/(2 t_r)) for t < t_r = ramp_periods * 3 lambda, 1 afterwards.
- * It is imposed in absorbing-layer cells whose eps_r is exactly 1; the layer
- * relaxes every other layer cell towards zero field. */
+ * It is imposed in absorbing-layer cells whose eps_r (and mu_r) is exactly 1;
+ * the layer relaxes every other layer cell towards zero field. */
 typedef struct {
     double lambda;          /* free-space wavelength in cells; 3*lambda must be integral */
     double khat[3];         /* unit propagation direction (in-plane for TM/TE)           */
@@ -98,8 +98,24 @@ lbm_em_status lbm_em_destroy(lbm_em_handle h);
 /* Set eps_r(x) (paper section 2.1: it enters the rest equilibrium and
  * E = D/eps_r).  eps: nx*ny*nz values, where = LBM_EM_HOST or LBM_EM_DEVICE,
  * dtype = LBM_EM_FP32 (float) or LBM_EM_FP64 (double).  Values are copied.
+ * 2-D handles store no rest population (it is 6 (eps_r - 1) times the
+ * stored z-pair), so a map changed between steps also rescales the rest
+ * population at once; 3-D handles keep it.  Set maps before stepping (or
+ * reset) for a run that matches the literal scheme.
  * Errors: EINVAL if a value is < 1 or not finite (checked on the host copy). */
 lbm_em_status lbm_em_set_permittivity(lbm_em_handle h, const void *eps, int32_t where,
+                                      int32_t dtype);
+
+/* Set mu_r(x) of a 2-D (TM/TE) handle (section 2.1: it enters the rest
+ * equilibrium h_0^eq = (mu_r - 1) H and H = B/mu_r).  Same layout and
+ * validation as lbm_em_set_permittivity; the first call allocates one more
+ * plane (mu_r = 1 until then), mu = NULL frees it (mu_r = 1 again).  A
+ * handle with a permeability map steps one time step per launch (this call
+ * sets it); two steps per launch, batches and the adjoint are EUNSUPPORTED
+ * with it.  Like eps_r, it also sets the (unstored) rest population h_0 =
+ * 6 (mu_r - 1) h_zpair.  Errors: EUNSUPPORTED for 3-D handles or after adjoint_setup,
+ * ESTATE while the handle belongs to a batch, EINVAL as for eps. */
+lbm_em_status lbm_em_set_permeability(lbm_em_handle h, const void *mu, int32_t where,
                                       int32_t dtype);
 
 /* Set the incident plane wave (see lbm_em_plane_wave).  EINVAL if khat or
@@ -135,7 +151,8 @@ lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
  * bit-identical to lbm_em_step on each handle.  Uses the launch settings of
  * hs[0]; with two steps per launch, the tile with the fewest padded cells
  * over all instances (hs[0]'s own tile when it is among the best).
- * EUNSUPPORTED for 3-D handles.  (One-shot form of the batch calls below.) */
+ * EUNSUPPORTED for 3-D handles and handles with a permeability map.
+ * (One-shot form of the batch calls below.) */
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);
 
 /* A reusable batch: snapshots the handles' settings (source, contour, tile;
@@ -172,7 +189,8 @@ lbm_em_status lbm_em_get_tile(lbm_em_handle h, int32_t *vx, int32_t *bx, int32_t
  * 64x8, 64x16, 128x8, 128x16, 64x32), in 3-D a TX x TY column tile that
  * marches along z with a one-plane lag (FP32 64x16, 64x8, 32x16; FP64
  * 32x16, 32x8, 16x16).  tile 0 x 0 keeps the current one; EINVAL for other
- * tiles.  get_fusion's tile outputs may be NULL. */
+ * tiles, EUNSUPPORTED for two steps on a handle with a permeability map.
+ * get_fusion's tile outputs may be NULL. */
 lbm_em_status lbm_em_set_fusion(lbm_em_handle h, int32_t steps_per_launch, int32_t tile_x, int32_t tile_y);
 lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y);
 
@@ -181,12 +199,13 @@ lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int3
  * tile -- `launches` launches each, reading the current state and
  * writing the spare buffer with the DFT off, so the simulation is not
  * advanced; keep the fastest per time step and verify that it reproduces
- * one-cell-per-thread single steps bit for bit (EDEVICE if not).
+ * one-cell-per-thread single steps bit for bit (EDEVICE if not).  With a
+ * permeability map only one-step shapes are timed.
  * *best_us (may be NULL) receives the winner's time per step. */
 lbm_em_status lbm_em_autotune(lbm_em_handle h, int32_t launches, double *best_us);
 
 /* Restart from t = 0: zero the distributions and the DFT accumulators
- * (stream-ordered, no allocation).  Permittivity, source and contour are
+ * (stream-ordered, no allocation).  Material maps, source and contour are
  * kept. */
 lbm_em_status lbm_em_reset(lbm_em_handle h);
 

@@ -4,8 +4,9 @@
 // c_0 = 0, +-x, +-y, +-z; vector distributions e_i, h_i; tau = 1/2 update
 //   f_i(r + c_i, t+1) = 2 f_i^eq(r,t) - f_i(r,t),
 //   e_i^eq = (E - c_i x H)/6, h_i^eq = (H + c_i x E)/6 (i != 0),
-//   e_0^eq = (eps_r - 1) E, h_0^eq = (mu_r - 1) H, with mu_r = 1 here,
-// and fields from the zeroth moments, E = sum_i e_i / eps_r, H = sum_i h_i.
+//   e_0^eq = (eps_r - 1) E, h_0^eq = (mu_r - 1) H,
+// and fields from the zeroth moments, E = sum_i e_i / eps_r, H = sum_i h_i / mu_r.
+// mu_r = 1 except in the 2-D one-step kernel's permeability variant (MU).
 //
 // Exact reduced state.  For every moving direction the combination
 // e_i_perp + c_i x h_i has zero equilibrium, so collision only flips its sign,
@@ -17,7 +18,10 @@
 // populations never move and have equal equilibria, so they stay equal and
 // merge into one "z-pair", and the rest population is slaved to it,
 // e_0 = 6 (eps_r - 1) e_zpair (the difference flips sign every step and
-// starts at zero).  A 2-D polarisation then needs 11 scalars per cell:
+// starts at zero; the layer relaxes both towards equilibria in the same
+// ratio).  By the same argument h_0 = 6 (mu_r - 1) h_zpair, so a 2-D
+// permeability map needs no extra state.  A 2-D polarisation then needs 11
+// scalars per cell:
 //   TM (E_z, H_x, H_y): planes 0..3  e_z of +x,-x,+y,-y
 //                       planes 4..7  h_x of +-x, h_y of +-y   (eta)
 //                       planes 8..10 z-pair e_z, h_x, h_y
@@ -106,6 +110,7 @@ struct StepArgs {
     const T *__restrict__ src;  // f*(t-1), nplanes planes
     T *__restrict__ dst;        // f*(t)
     const T *__restrict__ eps;
+    const T *__restrict__ mu;   // relative permeability, read by the MU variants only
     const int64_t *t_base;      // graph replay: t = *t_base + t_off; else NULL
     int64_t t_off;
     // plane-wave source (phase tables: see plane_wave)
@@ -216,17 +221,25 @@ __device__ inline T recip(T e) {
 
 // Fields at a cell from pulled 2-D reduced populations.
 //   TM: F = (E_z, H_x, H_y); TE: F = (E_x, E_y, H_z).
-template <typename T, int POL>
-__device__ inline void fields2d(const T s[11], T eps, T inv_eps, T F[3]) {
+// MU: the cell has permeability mu (inv_mu = 1/mu); else mu_r = 1.
+template <typename T, int POL, bool MU = false>
+__device__ inline void fields2d(const T s[11], T eps, T inv_eps, T F[3], T mu = T(1), T inv_mu = T(1)) {
     const T rest = fma(T(6), eps, T(-4));  // z-pair (x2) plus slaved rest population
     if (POL == TM) {
         F[0] = fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
-        F[1] = fma(T(2), s[9], s[4] + s[5] + s[2] - s[3]);
-        F[2] = fma(T(2), s[10], s[6] + s[7] - s[0] + s[1]);
+        if (MU) {
+            const T rest_h = fma(T(6), mu, T(-4));
+            F[1] = fma(rest_h, s[9], s[4] + s[5] + s[2] - s[3]) * inv_mu;
+            F[2] = fma(rest_h, s[10], s[6] + s[7] - s[0] + s[1]) * inv_mu;
+        } else {
+            F[1] = fma(T(2), s[9], s[4] + s[5] + s[2] - s[3]);
+            F[2] = fma(T(2), s[10], s[6] + s[7] - s[0] + s[1]);
+        }
     } else {
         F[0] = fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
         F[1] = fma(rest, s[9], s[4] + s[5] + s[6] + s[7]) * inv_eps;
-        F[2] = fma(T(2), s[10], s[4] - s[5] - s[2] + s[3]);
+        if (MU) F[2] = fma(fma(T(6), mu, T(-4)), s[10], s[4] - s[5] - s[2] + s[3]) * inv_mu;
+        else F[2] = fma(T(2), s[10], s[4] - s[5] - s[2] + s[3]);
     }
 }
 
@@ -417,13 +430,15 @@ __device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
 // ---------------------------------------------------------------------------
 // PH: the cell's incident-wave phase factor (ur, ui) = e^{2 pi j u} was
 // gathered by the caller (the two-step kernel prefetches it for the tiles
-// that touch the layer), else it is gathered here.
-template <typename T, int POL, bool HIST = false, bool PH = false>
+// that touch the layer), else it is gathered here.  MU: the cell has
+// permeability mu (inv_mu = 1/mu).
+template <typename T, int POL, bool HIST = false, bool PH = false, bool MU = false>
 __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, T eps,
-                                     T inv_eps, T sig, T f[11], bool record, T ur = T(0), T ui = T(0)) {
+                                     T inv_eps, T sig, T f[11], bool record, T ur = T(0), T ui = T(0),
+                                     T mu = T(1), T inv_mu = T(1)) {
     const int64_t t = st.t;
     T F[3];
-    fields2d<T, POL>(f, eps, inv_eps, F);
+    fields2d<T, POL, MU>(f, eps, inv_eps, F, mu, inv_mu);
     if (st.dft && record) {
         double G[6] = {0, 0, 0, 0, 0, 0};
         if (POL == TM) {
@@ -448,10 +463,10 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
     }
     collide2d<T, POL>(F, f);
     if (sig > T(0)) {
-        // relax towards the incident wave's equilibrium (zero where eps != 1):
-        // f + sig (f_ref - f), one fused multiply-add per population
+        // relax towards the incident wave's equilibrium (zero where eps != 1
+        // or mu != 1): f + sig (f_ref - f), one fused multiply-add per population
         T R[3] = {0, 0, 0};
-        if (a.src_on && eps == T(1)) {
+        if (a.src_on && eps == T(1) && (!MU || mu == T(1))) {
             const T w = PH ? st.gs * ur - st.gc * ui : plane_wave<T, 2>(a, st, x, y, 0);
             if (POL == TM) { R[0] = w * a.ehat[2]; R[1] = w * a.hhat[0]; R[2] = w * a.hhat[1]; }
             else { R[0] = w * a.ehat[0]; R[1] = w * a.ehat[1]; R[2] = w * a.hhat[2]; }
@@ -539,18 +554,30 @@ __device__ inline void store_row(const StepArgs<T> &a, int x0, int y, const T (&
 // 2-D fused step: pull + moments + DFT + collision + layer/source + store.
 // The calling thread updates cells x0 .. x0+VX-1 of row y.
 // ---------------------------------------------------------------------------
-template <typename T, int POL, int VX, bool HIST = false>
+// MU: the permeability variant (a.mu is read per cell).
+template <typename T, int POL, int VX, bool HIST = false, bool MU = false>
 __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const StepConst<T> &st) {
     if (x0 >= a.nx || y >= a.ny) return;
-    T v[11][VX], e[VX];
+    T v[11][VX], e[VX], m[VX];
     pull_row<T, VX>(a, x0, y, v, e);
+    if (MU) {
+        const uint32_t row = (uint32_t)y * (uint32_t)a.sy;
+        if (x0 >= 0 && x0 + VX <= a.nx) load_aligned<T, VX>(m, at(a.mu, row + (uint32_t)x0));
+        else
+#pragma unroll
+            for (int k = 0; k < VX; ++k) m[k] = *at(a.mu, row + (uint32_t)fold(x0 + k, a.nx, a.W[0]));
+    }
 #pragma unroll
     for (int k = 0; k < VX; ++k) {
         const int x = fold(x0 + k, a.nx, a.W[0]);
         T f[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-        cell_update2d<T, POL, HIST>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f, x0 + k < a.nx);
+        if (MU)
+            cell_update2d<T, POL, false, false, true>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f,
+                                                      x0 + k < a.nx, T(0), T(0), m[k], recip(m[k]));
+        else
+            cell_update2d<T, POL, HIST>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f, x0 + k < a.nx);
 #pragma unroll
         for (int i = 0; i < 11; ++i) v[i][k] = f[i];
     }
@@ -558,12 +585,13 @@ __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const S
 }
 
 // HIST: also record dE/deps of the design cells into a.hist (checkpointed
-// forward pass of the adjoint).
-template <typename T, int POL, int VX, bool HIST = false>
+// forward pass of the adjoint).  MU: permeability map a.mu (never with HIST).
+template <typename T, int POL, int VX, bool HIST = false, bool MU = false>
 __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
+    static_assert(!(HIST && MU), "the design-region history assumes mu_r = 1");
     const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    step2d_cells<T, POL, VX, HIST>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
+    step2d_cells<T, POL, VX, HIST, MU>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
 }
 
 // Batched persistent step: one launch advances many 2-D instances of
@@ -1675,7 +1703,12 @@ __global__ void __launch_bounds__(256) k_fields(StepArgs<T> a, T *E, T *H) {
                    s[8 * P + c],        s[9 * P + c],        s[10 * P + c]};
         const T eps = a.eps[c];
         T F[3];
-        fields2d<T, POL>(f, eps, recip(eps), F);
+        if (a.mu) {
+            const T mu = a.mu[c];
+            fields2d<T, POL, true>(f, eps, recip(eps), F, mu, recip(mu));
+        } else {
+            fields2d<T, POL>(f, eps, recip(eps), F);
+        }
         if (POL == TM) { Ev[2] = F[0]; Hv[0] = F[1]; Hv[1] = F[2]; }
         else { Ev[0] = F[0]; Ev[1] = F[1]; Hv[2] = F[2]; }
     } else {

@@ -72,6 +72,7 @@ struct lbm_em {
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;                        // buf[cur] holds f*(t-1)
     void *eps = nullptr;
+    void *mu = nullptr;                 // permeability map (2-D); NULL: mu_r = 1
     int64_t t = 0;
     hipStream_t stream = nullptr;
     int vx = 1, bx = 128, by = 2;       // cells per thread along x, block shape
@@ -162,6 +163,7 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     a.src = (const T *)src;
     a.dst = (T *)dst;
     a.eps = (const T *)h->eps;
+    a.mu = (const T *)h->mu;
     a.src_on = h->src_on ? 1 : 0;
     a.period = h->period > 0 ? h->period : 1;
     if (h->src_on) {
@@ -197,7 +199,12 @@ void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
     dim3 grid((unsigned)((gx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
               (unsigned)h->cfg.nz);
     const bool rec = a.hist != nullptr;
-    if (h->cfg.pol == LBM_EM_TM) {
+    if (a.mu) {
+        if (rec) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
+        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, true>), grid, block, 0, s, a);
+        else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE, VX, false, true>), grid, block, 0, s, a);
+        else fail(LBM_EM_EUNSUPPORTED, "a permeability map needs a 2-D (TM/TE) handle");
+    } else if (h->cfg.pol == LBM_EM_TM) {
         if (rec) hipLaunchKernelGGL((k_step2d<T, TM, VX, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_step2d<T, TM, VX>), grid, block, 0, s, a);
     } else if (h->cfg.pol == LBM_EM_TE) {
@@ -325,6 +332,7 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
 
 void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
                   bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
+    if (h->mu) fail(LBM_EM_EUNSUPPORTED, "two steps per launch need mu_r = 1");
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
     if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
@@ -575,6 +583,7 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
     for (int i = 0; i < count; ++i) {
         lbm_em *h = check_handle(hs[i]);
         if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "batched stepping supports 2-D (TM/TE) handles");
+        if (h->mu) fail(LBM_EM_EUNSUPPORTED, "batched stepping needs mu_r = 1");
         if (h->cfg.pol != h0->cfg.pol || h->cfg.precision != h0->cfg.precision)
             fail(LBM_EM_EINVAL, "batched handles must share polarisation and precision");
         if (h->stream != h0->stream || h->dev != h0->dev) fail(LBM_EM_EINVAL, "batched handles must share stream and device");
@@ -838,12 +847,68 @@ void free_handle(lbm_em *h) {
     hfree(h->buf[0]);
     hfree(h->buf[1]);
     hfree(h->eps);
+    hfree(h->mu);
     hfree(h->acc);
     hfree(h->t_dev);
     hfree(h->ck);
     hfree(h->adj_P);
     hfree(h->wtab);
     delete h;
+}
+
+// Material map upload shared by eps_r and mu_r: validate (finite, >= 1) on
+// a host copy, then convert into the padded plane `dst` of the handle.
+void load_material(lbm_em *h, const void *src, int32_t where, int32_t dtype, void *dst, const char *name) {
+    if (dtype != LBM_EM_FP32 && dtype != LBM_EM_FP64) fail(LBM_EM_EINVAL, "dtype must be FP32 or FP64");
+    if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
+    select_device(h);
+    const auto &c = h->cfg;
+    const size_t cells = (size_t)c.nx * c.ny * c.nz;
+    const size_t isz = dtype == LBM_EM_FP32 ? 4 : 8;
+    std::vector<char> host(cells * isz);
+    if (where == LBM_EM_HOST) std::memcpy(host.data(), src, host.size());
+    else {
+        hip_check(hipMemcpyAsync(host.data(), src, host.size(), hipMemcpyDeviceToHost, h->stream), "material D2H");
+        sync(h);
+    }
+    for (size_t i = 0; i < cells; ++i) {
+        double v = dtype == LBM_EM_FP32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
+        if (!std::isfinite(v) || v < 1.0) fail(LBM_EM_EINVAL, std::string(name) + " must be finite and >= 1");
+    }
+    void *d_in = nullptr;
+    hip_check(hipMalloc(&d_in, host.size()), "hipMalloc");
+    try {
+        hip_check(hipMemcpyAsync(d_in, host.data(), host.size(), hipMemcpyHostToDevice, h->stream), "material H2D");
+        dim3 grid((c.nx + 255) / 256, c.ny, c.nz);
+        if (dtype == LBM_EM_FP32 && h->elem == 4)
+            hipLaunchKernelGGL((k_load_eps<float, float>), grid, dim3(256), 0, h->stream, (const float *)d_in,
+                               (float *)dst, c.nx, c.ny, c.nz, h->sy, h->sz);
+        else if (dtype == LBM_EM_FP32)
+            hipLaunchKernelGGL((k_load_eps<float, double>), grid, dim3(256), 0, h->stream, (const float *)d_in,
+                               (double *)dst, c.nx, c.ny, c.nz, h->sy, h->sz);
+        else if (h->elem == 4)
+            hipLaunchKernelGGL((k_load_eps<double, float>), grid, dim3(256), 0, h->stream, (const double *)d_in,
+                               (float *)dst, c.nx, c.ny, c.nz, h->sy, h->sz);
+        else
+            hipLaunchKernelGGL((k_load_eps<double, double>), grid, dim3(256), 0, h->stream, (const double *)d_in,
+                               (double *)dst, c.nx, c.ny, c.nz, h->sy, h->sz);
+        hip_check(hipGetLastError(), "k_load_eps");
+        sync(h);
+    } catch (...) {
+        sync(h);
+        hfree(d_in);
+        throw;
+    }
+    hfree(d_in);
+}
+
+// Set every element of a padded material plane to 1.
+void fill_ones(lbm_em *h, void *dst) {
+    const int64_t ne = h->plane;
+    const unsigned blocks = (unsigned)((ne + 255) / 256);
+    if (h->elem == 4) hipLaunchKernelGGL((k_fill<float>), dim3(blocks), dim3(256), 0, h->stream, (float *)dst, ne, 1.0f);
+    else hipLaunchKernelGGL((k_fill<double>), dim3(blocks), dim3(256), 0, h->stream, (double *)dst, ne, 1.0);
+    hip_check(hipGetLastError(), "material init");
 }
 
 void check_unit(const double v[3], const char *name) {
@@ -919,12 +984,7 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             hip_check(hipMalloc(&h->t_dev, 64), "hipMalloc counter");
             hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset");
             hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset");
-            // eps_r = 1 everywhere (padding included)
-            const int64_t ne = h->plane;
-            const unsigned blocks = (unsigned)((ne + 255) / 256);
-            if (h->elem == 4) hipLaunchKernelGGL((k_fill<float>), dim3(blocks), dim3(256), 0, h->stream, (float *)h->eps, ne, 1.0f);
-            else hipLaunchKernelGGL((k_fill<double>), dim3(blocks), dim3(256), 0, h->stream, (double *)h->eps, ne, 1.0);
-            hip_check(hipGetLastError(), "eps init");
+            fill_ones(h, h->eps);   // eps_r = 1 everywhere (padding included)
             hip_check(hipStreamSynchronize(h->stream), "sync");
         } catch (...) {
             free_handle(h);
@@ -946,42 +1006,38 @@ lbm_em_status lbm_em_set_permittivity(lbm_em_handle hh, const void *eps, int32_t
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         if (!eps) fail(LBM_EM_EINVAL, "null eps");
-        if (dtype != LBM_EM_FP32 && dtype != LBM_EM_FP64) fail(LBM_EM_EINVAL, "dtype must be FP32 or FP64");
-        if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
+        load_material(h, eps, where, dtype, h->eps, "eps_r");
+    });
+}
+
+lbm_em_status lbm_em_set_permeability(lbm_em_handle hh, const void *mu, int32_t where, int32_t dtype) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "a permeability map needs a 2-D (TM/TE) handle");
+        if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
+        if (h->adj_set) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
         select_device(h);
-        const auto &c = h->cfg;
-        const size_t cells = (size_t)c.nx * c.ny * c.nz;
-        const size_t isz = dtype == LBM_EM_FP32 ? 4 : 8;
-        // validate on a host copy
-        std::vector<char> host(cells * isz);
-        if (where == LBM_EM_HOST) std::memcpy(host.data(), eps, host.size());
-        else {
-            hip_check(hipMemcpyAsync(host.data(), eps, host.size(), hipMemcpyDeviceToHost, h->stream), "eps D2H");
+        if (!mu) {   // back to mu_r = 1; the step stays at one per launch
             sync(h);
+            hfree(h->mu);
+            h->mu = nullptr;
+            drop_graphs(h);
+            return;
         }
-        for (size_t i = 0; i < cells; ++i) {
-            double v = dtype == LBM_EM_FP32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
-            if (!std::isfinite(v) || v < 1.0) fail(LBM_EM_EINVAL, "eps_r must be finite and >= 1");
+        void *dst = h->mu;
+        if (!dst) {
+            hip_check(hipMalloc(&dst, (size_t)h->plane * h->elem), "hipMalloc mu");
+            fill_ones(h, dst);
         }
-        void *d_in = nullptr;
-        hip_check(hipMalloc(&d_in, host.size()), "hipMalloc");
-        hip_check(hipMemcpyAsync(d_in, host.data(), host.size(), hipMemcpyHostToDevice, h->stream), "eps H2D");
-        dim3 grid((c.nx + 255) / 256, c.ny, c.nz);
-        if (dtype == LBM_EM_FP32 && h->elem == 4)
-            hipLaunchKernelGGL((k_load_eps<float, float>), grid, dim3(256), 0, h->stream, (const float *)d_in,
-                               (float *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
-        else if (dtype == LBM_EM_FP32)
-            hipLaunchKernelGGL((k_load_eps<float, double>), grid, dim3(256), 0, h->stream, (const float *)d_in,
-                               (double *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
-        else if (h->elem == 4)
-            hipLaunchKernelGGL((k_load_eps<double, float>), grid, dim3(256), 0, h->stream, (const double *)d_in,
-                               (float *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
-        else
-            hipLaunchKernelGGL((k_load_eps<double, double>), grid, dim3(256), 0, h->stream, (const double *)d_in,
-                               (double *)h->eps, c.nx, c.ny, c.nz, h->sy, h->sz);
-        hip_check(hipGetLastError(), "k_load_eps");
-        sync(h);
-        hfree(d_in);
+        try {
+            load_material(h, mu, where, dtype, dst, "mu_r");
+        } catch (...) {
+            if (dst != h->mu) hfree(dst);
+            throw;
+        }
+        h->mu = dst;
+        h->fuse = 1;
+        drop_graphs(h);
     });
 }
 
@@ -1180,6 +1236,7 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         if (steps_per_launch != 1 && steps_per_launch != 2) fail(LBM_EM_EINVAL, "steps_per_launch must be 1 or 2");
+        if (steps_per_launch == 2 && h->mu) fail(LBM_EM_EUNSUPPORTED, "two steps per launch need mu_r = 1");
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
             if (!fused_tile_ok(h->dim, h->cfg.precision, tile_x, tile_y))
                 fail(LBM_EM_EINVAL,
@@ -1228,7 +1285,9 @@ lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_u
             for (auto &sh : shapes)
                 if (tile_ok(h, vx, sh[0], sh[1])) cands.push_back({1, vx, sh[0], sh[1]});
 #define LBM_X2_CAND(TX, TY) cands.push_back({2, TX, TY, 0});
-        if (h->dim == 2) {
+        if (h->mu) {
+            // permeability map: one step per launch only
+        } else if (h->dim == 2) {
             if (h->cfg.precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_CAND) }
             else { LBM_X2_TILES_F64(LBM_X2_CAND) }
         } else {
@@ -1445,6 +1504,7 @@ lbm_em_status lbm_em_adjoint_setup(lbm_em_handle hh, lbm_em_handle inc, const do
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "the adjoint supports 2-D (TM/TE) handles");
+        if (h->mu) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
         if (!inc) fail(LBM_EM_EINVAL, "the objective needs the incident (eps = 1) companion handle");
         if (!theta_deg || n_angles < 1) fail(LBM_EM_EINVAL, "need at least one angle");
         if (!dlo || !dhi) fail(LBM_EM_EINVAL, "null design rectangle");
@@ -1459,6 +1519,7 @@ lbm_em_status lbm_em_adjoint_setup(lbm_em_handle hh, lbm_em_handle inc, const do
             if (W && (dlo[a] < W || dhi[a] >= n[a] - W)) fail(LBM_EM_EINVAL, "design rectangle overlaps the layer");
         }
         h->adj_inc = check_handle(inc);
+        if (h->adj_inc->mu) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
         h->adj_theta.assign(n_angles, 0.0);
         h->adj_w.assign(n_angles, 1.0);
         for (int i = 0; i < n_angles; ++i) {

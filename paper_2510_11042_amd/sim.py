@@ -47,6 +47,7 @@ class Simulation:
         L.check(L.lib().lbm_em_create(C.byref(cfg), C.byref(h)))
         self._h = h
         self._theta_inc = 0.0
+        self._has_mu = False
 
     @property
     def handle(self):
@@ -64,21 +65,35 @@ class Simulation:
             pass
 
     # -- inputs ----------------------------------------------------------
-    def set_permittivity(self, eps):
-        """eps: numpy array or torch tensor with nx*ny*nz values ([z][y][x])."""
+    def _set_material(self, fn, values, name):
         size = self.n[0] * self.n[1] * self.n[2]
-        if hasattr(eps, "data_ptr"):  # torch tensor
-            t = eps.contiguous()
+        if hasattr(values, "data_ptr"):  # torch tensor
+            t = values.contiguous()
             if t.numel() != size:
-                raise ValueError("eps has the wrong number of values")
+                raise ValueError(f"{name} has the wrong number of values")
             dt = {4: L.FP32, 8: L.FP64}[t.element_size()]
             where = L.DEVICE if t.is_cuda else L.HOST
-            L.check(L.lib().lbm_em_set_permittivity(self._h, C.c_void_p(t.data_ptr()), where, dt))
+            L.check(fn(self._h, C.c_void_p(t.data_ptr()), where, dt))
             return
-        a = np.ascontiguousarray(eps, dtype=np.float64)
+        a = np.ascontiguousarray(values, dtype=np.float64)
         if a.size != size:
-            raise ValueError("eps has the wrong number of values")
-        L.check(L.lib().lbm_em_set_permittivity(self._h, a.ctypes.data_as(C.c_void_p), L.HOST, L.FP64))
+            raise ValueError(f"{name} has the wrong number of values")
+        L.check(fn(self._h, a.ctypes.data_as(C.c_void_p), L.HOST, L.FP64))
+
+    def set_permittivity(self, eps):
+        """eps: numpy array or torch tensor with nx*ny*nz values ([z][y][x])."""
+        self._set_material(L.lib().lbm_em_set_permittivity, eps, "eps")
+
+    def set_permeability(self, mu):
+        """mu_r(x) of a 2-D run, laid out like eps; None returns to mu_r = 1.
+        A permeability map runs one step per launch; two-step launches,
+        batches and the adjoint refuse it."""
+        if mu is None:
+            L.check(L.lib().lbm_em_set_permeability(self._h, None, L.HOST, L.FP64))
+            self._has_mu = False
+            return
+        self._set_material(L.lib().lbm_em_set_permeability, mu, "mu")
+        self._has_mu = True
 
     def set_source(self, lam, khat, ehat, amplitude=1.0, ramp_periods=3.0, center=None):
         pw = L.PlaneWave()
@@ -252,7 +267,8 @@ def _tune_key(sim):
         arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     except Exception:  # pragma: no cover
         arch = "unknown"
-    return f"{arch}/{sim.pol}/{sim.precision}/{sim.n[0]}x{sim.n[1]}x{sim.n[2]}"
+    mu = "/mu" if sim._has_mu else ""
+    return f"{arch}/{sim.pol}/{sim.precision}/{sim.n[0]}x{sim.n[1]}x{sim.n[2]}{mu}"
 
 
 def step_many(sims, n):

@@ -84,6 +84,27 @@ def test_fresnel_magnetic_interface(eps_in, mu_in):
         assert np.sign(np.real(np.mean(ratio))) == np.sign(r_ref), (np.mean(ratio), r_ref)
 
 
+@pytest.mark.parametrize("eps_in,mu_in", [(10.0, 1.0), (200.0, 1.0), (1.0, 10.0), (1.0, 200.0)])
+def test_material_sweep_extremes(eps_in, mu_in):
+    """Section 3.1's sweep (eps_r or mu_r from 1 to 200, the other 1, at 20
+    cells per wavelength inside the medium) against Eq. ref_trans at its
+    ends.  The reflected amplitude holds 0.005; the transmitted one carries
+    the scheme's second-order error at 20 cells per inner wavelength (about
+    1 %, independent of the contrast), so it is held to 2 %."""
+    case = W.planar_sweep_case(eps_in, mu_in)
+    x0 = case.extra["x0"]
+    tot = _row_phasors(case, case.extra["mu"])[:, 2]
+    inc = _row_phasors(W.vacuum_companion(case))[:, 2]
+    vac = slice(20 + 8, x0 - 8)
+    die = slice(x0 + 8, case.nx - 20 - 8)
+    r = np.abs(tot[vac] - inc[vac]) / np.abs(inc[vac])
+    t = np.abs(tot[die]) / np.abs(inc[die])
+    r_ref, t_ref = fresnel_normal(eps_in, mu_in)
+    assert r.std() < 0.002 and t.std() < 0.01 * t_ref, (r.std(), t.std())   # no standing wave
+    assert abs(r.mean() - abs(r_ref)) < 0.005, (r.mean(), r_ref)
+    assert abs(t.mean() / t_ref - 1.0) < 0.02, (t.mean(), t_ref)
+
+
 @pytest.mark.parametrize("theta", [0.0, 30.0])
 def test_electromagnetic_duality(theta):
     """Maxwell's equations are invariant under E -> H, H -> -E with eps and

@@ -133,6 +133,29 @@ def fresnel_case(theta_deg=0.0, pol="TM", nx=256, ny=None, steps=3000, eps_in=2.
                   shape="half-space")
 
 
+def planar_sweep_case(eps_in, mu_in, pol="TM", lam_wall=20.0, W=20):
+    """One point of the section 3.1 material sweep: normal incidence from
+    vacuum onto a half space (eps_in, mu_in) on a single-row grid, resolved
+    with lam_wall = lambda / sqrt(eps mu) cells inside the medium (lambda
+    rounded so that 3 lambda is integral).  The vacuum side holds 1.5 free-
+    space wavelengths, the medium 5 inner wavelengths (+16 cells each), and
+    the run lasts the ramp plus two vacuum crossings and two medium
+    crossings plus one period, so the DFT window sees the steady state.
+    case.extra holds the interface column x0 and the permeability map mu."""
+    n = float(np.sqrt(eps_in * mu_in))
+    lam = round(3.0 * lam_wall * n) / 3.0
+    Lv = int(1.5 * lam) + 16
+    Lm = int(5.0 * lam / n) + 16
+    nx = W + Lv + Lm + W
+    x0 = W + Lv
+    T = period_steps(lam)
+    steps = int(9.0 * lam + 6 * (Lv + W) + 6 * n * (Lm + W)) + T
+    eps = half_space(nx, 1, x0, eps_in)
+    mu = half_space(nx, 1, x0, mu_in)
+    return Case2D(f"sweep-eps{eps_in:g}-mu{mu_in:g}", nx, 1, eps, lam, 0.0, pol, (W, 0, 0), steps,
+                  eps_in=eps_in, shape="half-space", extra={"x0": x0, "mu": mu, "mu_in": mu_in})
+
+
 def cylinder_case(eps_in=2.25, pol="TM", n=1024, a=25.5, lam=32.0, W=32, steps=8000,
                   half=34.5, theta_deg=0.0, shape="circle"):
     """Infinite dielectric cylinder (x = 2 pi a / lambda = 5.007 at a = 25.5,
