@@ -180,6 +180,38 @@ def sphere_extra(Simulation, W, torch, steps=200):
     return res
 
 
+def magnetic_extra(Simulation, W, torch, steps=1600):
+    """The two-step kernel's permeability variant on the cylinder grid: a
+    magnetic-dielectric cylinder (eps 2, mu 1.5), TM, 1024^2; one more
+    plane (mu) is read per launch: 96 B per cell."""
+    case = W.cylinder_case(2.0, "TM", n=1024)
+    mu = W.circle(case.nx, case.radius, 1.5)
+    s = Simulation(case.nx, case.ny, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    s.set_permeability(mu)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    s.step(256)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    fuse = s.get_fusion()
+    ms = e0.elapsed_time(e1) / steps * fuse
+    cells = case.nx * case.ny
+    nbytes = cells * (BYTES_2D + 4)
+    res = {"workload": "cylinder-1024x1024-eps2-mu1.5-TM", "kernel": "k_step2d_x2<float,TM,..,MU>" if fuse == 2
+           else "k_step2d<float,TM,..,MU>", "steps_per_launch": fuse,
+           "tile": list(s.get_fusion_tile()) if fuse == 2 else list(s.get_tile()),
+           "ms_per_launch": ms, "MLUPS": cells * fuse / (ms * 1e-3) / 1e6,
+           "algorithmic_bytes_per_launch": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9}
+    res["frac_of_hbm_peak"] = res["achieved_GBs"] / HBM_PEAK_GBS
+    s.close()
+    return res
+
+
 def batched_extra(P, W, torch, steps=6000):
     """64 seeded uneven instances (circle/hexagon, eps, size, lambda, angle),
     6000 steps: one Batch (persistent launch per step, graph replay) against
@@ -327,7 +359,7 @@ def main():
     ap.add_argument("--lbm-steps", type=int, default=8000, help="time steps per solve (workload: 8000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="copy,streams,sphere,batched,adjoint",
+    ap.add_argument("--extras", default="copy,streams,sphere,magnetic,batched,adjoint",
                     help="comma list of extra measurements to run")
     ap.add_argument("--tile", default=None,
                     help="two-step tile TX,TY instead of autotuning (profiling runs)")
@@ -421,6 +453,8 @@ def main():
             line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, args.lbm_steps, theta, tiles)
         if "sphere" in want:
             line["extra"]["sphere_3d"] = sphere_extra(Simulation, W, torch)
+        if "magnetic" in want:
+            line["extra"]["magnetic"] = magnetic_extra(Simulation, W, torch)
         if "batched" in want:
             line["extra"]["batched"] = batched_extra(P, W, torch)
         if "adjoint" in want:

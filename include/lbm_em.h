@@ -109,11 +109,10 @@ lbm_em_status lbm_em_set_permittivity(lbm_em_handle h, const void *eps, int32_t 
 /* Set mu_r(x) of a 2-D (TM/TE) handle (section 2.1: it enters the rest
  * equilibrium h_0^eq = (mu_r - 1) H and H = B/mu_r).  Same layout and
  * validation as lbm_em_set_permittivity; the first call allocates one more
- * plane (mu_r = 1 until then), mu = NULL frees it (mu_r = 1 again).  A
- * handle with a permeability map steps one time step per launch (this call
- * sets it); two steps per launch, batches and the adjoint are EUNSUPPORTED
- * with it.  Like eps_r, it also sets the (unstored) rest population h_0 =
- * 6 (mu_r - 1) h_zpair.  Errors: EUNSUPPORTED for 3-D handles or after adjoint_setup,
+ * plane (mu_r = 1 until then), mu = NULL frees it (mu_r = 1 again).  One
+ * and two steps per launch (every tile) support it; batches and the adjoint
+ * are EUNSUPPORTED with it.  Like eps_r, it also sets the (unstored) rest
+ * population h_0 = 6 (mu_r - 1) h_zpair.  Errors: EUNSUPPORTED for 3-D handles or after adjoint_setup,
  * ESTATE while the handle belongs to a batch, EINVAL as for eps. */
 lbm_em_status lbm_em_set_permeability(lbm_em_handle h, const void *mu, int32_t where,
                                       int32_t dtype);
@@ -189,8 +188,7 @@ lbm_em_status lbm_em_get_tile(lbm_em_handle h, int32_t *vx, int32_t *bx, int32_t
  * 64x8, 64x16, 128x8, 128x16, 64x32), in 3-D a TX x TY column tile that
  * marches along z with a one-plane lag (FP32 64x16, 64x8, 32x16; FP64
  * 32x16, 32x8, 16x16).  tile 0 x 0 keeps the current one; EINVAL for other
- * tiles, EUNSUPPORTED for two steps on a handle with a permeability map.
- * get_fusion's tile outputs may be NULL. */
+ * tiles.  get_fusion's tile outputs may be NULL. */
 lbm_em_status lbm_em_set_fusion(lbm_em_handle h, int32_t steps_per_launch, int32_t tile_x, int32_t tile_y);
 lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y);
 
@@ -199,8 +197,7 @@ lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int3
  * tile -- `launches` launches each, reading the current state and
  * writing the spare buffer with the DFT off, so the simulation is not
  * advanced; keep the fastest per time step and verify that it reproduces
- * one-cell-per-thread single steps bit for bit (EDEVICE if not).  With a
- * permeability map only one-step shapes are timed.
+ * one-cell-per-thread single steps bit for bit (EDEVICE if not).
  * *best_us (may be NULL) receives the winner's time per step. */
 lbm_em_status lbm_em_autotune(lbm_em_handle h, int32_t launches, double *best_us);
 

@@ -664,7 +664,9 @@ __device__ inline void lds_load(T (&o)[N], const T *p) { load_aligned<T, N>(o, p
 template <typename T, int N>
 __device__ inline void lds_store(T *p, const T (&i)[N]) { store_aligned<T, N>(p, i); }
 
-template <typename T, int POL, int TX, int TY, bool HIST = false>
+// MU: permeability map a.mu (never with HIST); mu and 1/mu of the thread's
+// own cells stay in registers like eps.
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false>
 __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t) {
     const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
     constexpr int VX = X2Lds<T, TX, TY>::VX;
@@ -675,7 +677,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     const int tid = threadIdx.x;
     const int sx = (tid % TPR) * VX, sy = tid / TPR;   // the thread's segment in the tile
     const int x = x0 + sx, y = y0 + sy;
-    T zp[3][VX], ep[VX], ip[VX], sg[VX];
+    T zp[3][VX], ep[VX], ip[VX], sg[VX], mp[VX], imp[VX];
 
     // tiles that reach into the absorbing layer prefetch the incident-wave
     // phase factors of their cells with the state (block-uniform test)
@@ -688,6 +690,17 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         const int yf = fold(y, a.ny, a.W[1]);
         T v[11][VX], e[VX];
         pull_row<T, VX>(a, x, yf, v, e);
+#pragma unroll
+        for (int k = 0; k < VX; ++k) mp[k] = imp[k] = T(1);
+        if (MU) {
+            const uint32_t row = (uint32_t)yf * (uint32_t)a.sy;
+            if (x >= 0 && x + VX <= a.nx) load_aligned<T, VX>(mp, at(a.mu, row + (uint32_t)x));
+            else
+#pragma unroll
+                for (int k = 0; k < VX; ++k) mp[k] = *at(a.mu, row + (uint32_t)fold(x + k, a.nx, a.W[0]));
+#pragma unroll
+            for (int k = 0; k < VX; ++k) imp[k] = recip(mp[k]);
+        }
 #pragma unroll
         for (int k = 0; k < VX; ++k) ur[k] = ui[k] = T(0);
         if (layer_tile) {
@@ -708,8 +721,8 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             T f[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL, HIST, true>(a, s0, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny,
-                                              ur[k], ui[k]);
+            cell_update2d<T, POL, HIST, true, MU>(a, s0, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny,
+                                                  ur[k], ui[k], mp[k], imp[k]);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
             zp[0][k] = f[8];
@@ -740,7 +753,13 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         T f[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = v[i][0];
-        cell_update2d<T, POL>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf), f, false);
+        if (MU) {
+            const T m = *at(a.mu, (uint32_t)yf * (uint32_t)a.sy + (uint32_t)xf);
+            cell_update2d<T, POL, false, false, true>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf), f,
+                                                      false, T(0), T(0), m, recip(m));
+        } else {
+            cell_update2d<T, POL>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf), f, false);
+        }
         if (r < TX) {
             L.ym[0][0][r] = f[2];
             L.ym[1][0][r] = f[6];
@@ -803,7 +822,8 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             f[8] = zp[0][k];
             f[9] = zp[1][k];
             f[10] = zp[2][k];
-            cell_update2d<T, POL, HIST, true>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx, ur[k], ui[k]);
+            cell_update2d<T, POL, HIST, true, MU>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx, ur[k], ui[k],
+                                                  mp[k], imp[k]);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
         }
@@ -825,13 +845,15 @@ __device__ inline int xcd_tile(int b, int ntiles) {
 // One block per tile, a 1-D grid of tiles_x * tiles_y blocks.  The launch
 // bound asks for 4 waves per SIMD (at most 128 VGPRs).
 // HIST: also record dE/deps of the design cells (recompute of the adjoint).
-template <typename T, int POL, int TX, int TY, bool HIST = false>
+// MU: permeability map a.mu.
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false>
 __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
     k_step2d_x2(StepArgs<T> a) {
+    static_assert(!(HIST && MU), "the design-region history assumes mu_r = 1");
     __shared__ X2Lds<T, TX, TY> lds;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    step2d_x2_tile<T, POL, TX, TY, HIST>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
-                                         step_time(a.t_base, a.t_off));
+    step2d_x2_tile<T, POL, TX, TY, HIST, MU>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
+                                             step_time(a.t_base, a.t_off));
 }
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).

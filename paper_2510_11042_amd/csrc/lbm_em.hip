@@ -258,6 +258,8 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
     if (tx == TX && ty == TY) {                                                                              \
         if (a.hist)                                                                                          \
             hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
+        else if (a.mu)                                                                                       \
+            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
         else                                                                                                 \
             hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a);  \
         return;                                                                                              \
@@ -332,7 +334,7 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
 
 void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
                   bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
-    if (h->mu) fail(LBM_EM_EUNSUPPORTED, "two steps per launch need mu_r = 1");
+    if (h->mu && hist) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
     if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
@@ -1017,7 +1019,7 @@ lbm_em_status lbm_em_set_permeability(lbm_em_handle hh, const void *mu, int32_t 
         if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         if (h->adj_set) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
         select_device(h);
-        if (!mu) {   // back to mu_r = 1; the step stays at one per launch
+        if (!mu) {   // back to mu_r = 1
             sync(h);
             hfree(h->mu);
             h->mu = nullptr;
@@ -1036,7 +1038,6 @@ lbm_em_status lbm_em_set_permeability(lbm_em_handle hh, const void *mu, int32_t 
             throw;
         }
         h->mu = dst;
-        h->fuse = 1;
         drop_graphs(h);
     });
 }
@@ -1236,7 +1237,6 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         if (steps_per_launch != 1 && steps_per_launch != 2) fail(LBM_EM_EINVAL, "steps_per_launch must be 1 or 2");
-        if (steps_per_launch == 2 && h->mu) fail(LBM_EM_EUNSUPPORTED, "two steps per launch need mu_r = 1");
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
             if (!fused_tile_ok(h->dim, h->cfg.precision, tile_x, tile_y))
                 fail(LBM_EM_EINVAL,
@@ -1285,9 +1285,7 @@ lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_u
             for (auto &sh : shapes)
                 if (tile_ok(h, vx, sh[0], sh[1])) cands.push_back({1, vx, sh[0], sh[1]});
 #define LBM_X2_CAND(TX, TY) cands.push_back({2, TX, TY, 0});
-        if (h->mu) {
-            // permeability map: one step per launch only
-        } else if (h->dim == 2) {
+        if (h->dim == 2) {
             if (h->cfg.precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_CAND) }
             else { LBM_X2_TILES_F64(LBM_X2_CAND) }
         } else {

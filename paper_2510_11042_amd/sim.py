@@ -86,8 +86,7 @@ class Simulation:
 
     def set_permeability(self, mu):
         """mu_r(x) of a 2-D run, laid out like eps; None returns to mu_r = 1.
-        A permeability map runs one step per launch; two-step launches,
-        batches and the adjoint refuse it."""
+        Batches and the adjoint refuse a handle with a permeability map."""
         if mu is None:
             L.check(L.lib().lbm_em_set_permeability(self._h, None, L.HOST, L.FP64))
             self._has_mu = False

@@ -431,7 +431,6 @@ def test_permeability_fields_match_oracle(gpu, prec, pol):
     s, o = make_pair(gpu, nx, ny, 1, pol, prec, (Wd, Wd, 0), eps, 12.0, kh, eh, ramp=1.0)
     s.set_permeability(mu)
     o.set_mu(mu)
-    assert s.get_fusion() == 1
     for n in (1, 9, 190):
         s.step(n)
         o.step(n)
@@ -447,6 +446,41 @@ def test_permeability_fields_match_oracle(gpu, prec, pol):
     compare_fields(s, o2, prec, f"mu cleared {pol} t={o2.t}")
     s.close()
     s2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_permeability_two_steps_bit_identical(gpu, prec, pol):
+    """With a permeability map, two steps per launch (every tile) reproduce
+    one step per launch bit for bit: fields and DFT phasors on a ragged grid,
+    either axis periodic, odd step counts."""
+    nx, ny = 203, 77
+    rng = np.random.default_rng(8)
+    eps = 1.0 + (rng.random((1, ny, nx)) < 0.2) * rng.uniform(0.2, 3.0, (1, ny, nx))
+    mu = 1.0 + (rng.random((1, ny, nx)) < 0.2) * rng.uniform(0.2, 3.0, (1, ny, nx))
+    mu[:, :4, :] = 1.6          # a magnetic strip inside the y layer
+    th = np.deg2rad(25.0)
+    kh = [np.cos(th), np.sin(th), 0.0]
+    eh = [0, 0, 1.0] if pol == "TM" else [-np.sin(th), np.cos(th), 0.0]
+    for absorb in ((11, 0, 0), (0, 9, 0)):
+        runs = []
+        for fuse, tile in [(1, (0, 0))] + [(2, t) for t in X2_TILES[prec]]:
+            s = gpu(nx, ny, 1, pol=pol, precision=prec, absorb=absorb, sigma_max=W.SIGMA_MAX)
+            s.set_permittivity(eps)
+            s.set_permeability(mu)
+            s.set_source(10.0, kh, eh, 1.0, 1.0)
+            s.set_ntff((60, 20, 0), (140, 56, 0), 100, 30)
+            s.set_fusion(fuse, tile)
+            for n in (3, 131, 1):
+                s.step(n)
+            runs.append((s.fields(), s.phasors()))
+            say("mu fusion", prec, pol, absorb, fuse, tile, s.t)
+            s.close()
+        (E1, H1), (X1, p1) = runs[0]
+        assert np.abs(E1).max() > 0
+        for (E2, H2), (X2, p2) in runs[1:]:
+            assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
+            assert np.array_equal(X1, X2) and np.array_equal(p1, p2)
 
 
 @pytest.mark.parametrize("pol", ["TM", "TE"])
@@ -483,9 +517,8 @@ def test_magnetic_cylinder_pipeline_intensity(gpu, pol):
 
 
 def test_permeability_api_limits(gpu):
-    """What a permeability map refuses: two steps per launch, batches, the
-    adjoint, 3-D handles, values below 1; autotune stays on one-step shapes
-    and still verifies bit-identity."""
+    """What a permeability map refuses: batches, the adjoint, 3-D handles,
+    values below 1; autotune with a map still verifies bit-identity."""
     from paper_2510_11042_amd import LbmEmError, step_many
 
     n = 64
@@ -496,9 +529,7 @@ def test_permeability_api_limits(gpu):
     mu = np.ones((1, n, n))
     mu[0, 28:36, 28:36] = 2.0
     s.set_permeability(mu)
-    assert s.get_fusion() == 1
-    with pytest.raises(LbmEmError):
-        s.set_fusion(2)
+    assert s.get_fusion() == 2
     bad = mu.copy()
     bad[0, 0, 0] = 0.5
     with pytest.raises(LbmEmError):
@@ -514,7 +545,7 @@ def test_permeability_api_limits(gpu):
     ref.set_permeability(mu)
     ref.step(10)
     s.autotune(launches=2)
-    assert s.get_fusion() == 1 and s.t == 10
+    assert s.t == 10
     s.step(30)
     ref.step(30)
     assert np.array_equal(s.fields()[0], ref.fields()[0]) and np.array_equal(s.fields()[1], ref.fields()[1])
