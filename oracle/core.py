@@ -33,6 +33,7 @@ def lib():
         L.oracle_destroy.argtypes = [P]
         L.oracle_set_eps.argtypes = [P, D]
         L.oracle_set_mu.argtypes = [P, D]
+        L.oracle_set_pec.argtypes = [P, C.c_void_p]
         L.oracle_set_source.argtypes = [P, C.c_double, D, D, C.c_double, C.c_double, D]
         L.oracle_clear_source.argtypes = [P]
         L.oracle_set_dft.argtypes = [P, I64, C.POINTER(I64), I64, I64]
@@ -94,6 +95,14 @@ class Oracle:
     def set_mu(self, mu):
         a = np.ascontiguousarray(np.broadcast_to(mu, self.shape), dtype=np.float64)
         lib().oracle_set_mu(self._h, _dp(a))
+
+    def set_pec(self, mask):
+        """Perfect-conductor cells (boolean map shaped like eps); None clears."""
+        if mask is None:
+            lib().oracle_set_pec(self._h, None)
+            return
+        self._pec = np.ascontiguousarray(np.broadcast_to(mask, self.shape), dtype=np.uint8)
+        lib().oracle_set_pec(self._h, self._pec.ctypes.data_as(C.c_void_p))
 
     # -- plane wave ----------------------------------------------------
     def set_source(self, lam, khat, ehat, amp=1.0, ramp_periods=3.0, center=None):

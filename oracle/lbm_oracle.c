@@ -41,6 +41,12 @@
  *   - Running DFT over a window of steps [t0, t0 + M T) of the fields at a
  *     list of cells: F_hat += (2/(M T)) F(t) exp(-j omega t)  (section 2.4:
  *     record the boundary fields over one period, then Fourier transform).
+ *   - Perfect electric conductor (section 3.2.1 scatters off PEC cylinders;
+ *     its boundary rule is given only in the authors' earlier work): a cell
+ *     flagged PEC has zero electric field.  Its moments give H = B (mu_r and
+ *     eps_r play no role there, so the rest populations stay zero), E is set
+ *     to 0 before the DFT sample and the collision, and the absorbing layer
+ *     imposes no incident wave on it.  The adjoint does not cover PEC cells.
  *
  * Order inside one time step t (paper section 2.1): moments -> DFT sample ->
  * collision -> absorbing-layer/source blend -> push streaming -> open
@@ -72,6 +78,7 @@ typedef struct {
     double *f;          /* populations at time t (pre-collision), NV per cell */
     double *g;          /* scratch: post-collision / streamed                 */
     double *eps, *mu;   /* per-cell relative permittivity / permeability      */
+    unsigned char *pec; /* per-cell PEC flag (NULL: no conductor)             */
     double *E, *H;      /* fields at time t, 3 per cell                       */
     int64_t t;
     /* plane wave */
@@ -159,6 +166,23 @@ static double sigma_at(const lbm_oracle *o, const int xyz[3]) {
     return s;
 }
 
+/* Material seen by the update at a cell: eps_r and mu_r, or 1 and 1 in a
+ * PEC cell, whose field recovery then zeroes E. */
+static int cell_material(const lbm_oracle *o, int64_t c, double *eps, double *mu) {
+    const int pec = o->pec && o->pec[c];
+    *eps = pec ? 1.0 : o->eps[c];
+    *mu = pec ? 1.0 : o->mu[c];
+    return pec;
+}
+
+/* Fields at a cell from its (pre-collision) populations. */
+static void cell_fields(const lbm_oracle *o, int64_t c, const double f[NV], double E[3], double H[3]) {
+    double eps, mu;
+    const int pec = cell_material(o, c, &eps, &mu);
+    moments(f, eps, mu, E, H);
+    if (pec) E[0] = E[1] = E[2] = 0.0;
+}
+
 /* Incident plane wave at a cell (reading; zero outside background cells). */
 static void reference_field(const lbm_oracle *o, const int xyz[3], double eps, double mu,
                             int64_t t, double Er[3], double Hr[3]) {
@@ -201,7 +225,7 @@ lbm_oracle *oracle_create(int nx, int ny, int nz, int Wx, int Wy, int Wz, double
 
 void oracle_destroy(lbm_oracle *o) {
     if (!o) return;
-    free(o->f); free(o->g); free(o->eps); free(o->mu); free(o->E); free(o->H);
+    free(o->f); free(o->g); free(o->eps); free(o->mu); free(o->pec); free(o->E); free(o->H);
     free(o->dft_cell); free(o->dft);
     free(o);
 }
@@ -211,6 +235,14 @@ void oracle_set_eps(lbm_oracle *o, const double *eps) {
 }
 void oracle_set_mu(lbm_oracle *o, const double *mu) {
     memcpy(o->mu, mu, (size_t)o->ncell * sizeof(double));
+}
+/* PEC flags, one byte per cell (non-zero: conductor); NULL clears them. */
+void oracle_set_pec(lbm_oracle *o, const unsigned char *flags) {
+    free(o->pec);
+    o->pec = NULL;
+    if (!flags) return;
+    o->pec = (unsigned char *)malloc((size_t)o->ncell);
+    memcpy(o->pec, flags, (size_t)o->ncell);
 }
 
 /* lambda in cells; khat, ehat unit vectors (ehat perpendicular to khat);
@@ -262,7 +294,7 @@ void oracle_set_state(lbm_oracle *o, const double *in) {
 /* Fields of the current state: E, H as [cell][3]. */
 void oracle_fields(lbm_oracle *o, double *E, double *H) {
     for (int64_t c = 0; c < o->ncell; ++c)
-        moments(o->f + c * NV, o->eps[c], o->mu[c], E + 3 * c, H + 3 * c);
+        cell_fields(o, c, o->f + c * NV, E + 3 * c, H + 3 * c);
 }
 
 int oracle_threads(void) {
@@ -278,15 +310,16 @@ int oracle_threads(void) {
 static void collide_cell(const lbm_oracle *o, int64_t c, int64_t t, double f[NV]) {
     int xyz[3];
     cell_xyz(o, c, xyz);
-    double E[3], H[3], feq[NV];
-    moments(f, o->eps[c], o->mu[c], E, H);
-    equilibrium(E, H, o->eps[c], o->mu[c], feq);
+    double E[3], H[3], feq[NV], eps, mu;
+    const int pec = cell_material(o, c, &eps, &mu);
+    cell_fields(o, c, f, E, H);
+    equilibrium(E, H, eps, mu, feq);
     for (int v = 0; v < NV; ++v) f[v] = 2.0 * feq[v] - f[v];
     double s = sigma_at(o, xyz);
     if (s > 0.0) {
-        double Er[3], Hr[3], fref[NV];
-        reference_field(o, xyz, o->eps[c], o->mu[c], t, Er, Hr);
-        equilibrium(Er, Hr, o->eps[c], o->mu[c], fref);
+        double Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0}, fref[NV];
+        if (!pec) reference_field(o, xyz, eps, mu, t, Er, Hr);
+        equilibrium(Er, Hr, eps, mu, fref);
         for (int v = 0; v < NV; ++v) f[v] = f[v] - s * (f[v] - fref[v]);
     }
 }
@@ -351,7 +384,7 @@ static void step_once(lbm_oracle *o) {
     /* 1. moments -> fields at time t */
 #pragma omp parallel for schedule(static) if (N > 4096)
     for (int64_t c = 0; c < N; ++c)
-        moments(o->f + c * NV, o->eps[c], o->mu[c], o->E + 3 * c, o->H + 3 * c);
+        cell_fields(o, c, o->f + c * NV, o->E + 3 * c, o->H + 3 * c);
 
     /* 2. running DFT of the recorded cells */
     if (o->ndft > 0 && t >= o->win0 && t < o->win0 + o->winlen) {

@@ -21,15 +21,17 @@ def probe_node(lo, hi):
     return tuple((l + h) // 2 for l, h in zip(lo, hi))
 
 
-def run_2d(case, sigma_max, ramp_periods, steps=None, collect_fields=False, mu=None):
-    """Run a workloads.Case2D (mu: optional permeability map shaped like
-    case.eps); returns dict(nodes, phasors (p, 6), probe (6,), E, H (final
-    fields, optional))."""
+def run_2d(case, sigma_max, ramp_periods, steps=None, collect_fields=False, mu=None, pec=None):
+    """Run a workloads.Case2D (mu: optional permeability map, pec: optional
+    perfect-conductor mask, both shaped like case.eps); returns dict(nodes,
+    phasors (p, 6), probe (6,), E, H (final fields, optional))."""
     steps = case.steps if steps is None else steps
     o = Oracle(case.nx, case.ny, 1, case.absorb, sigma_max)
     o.set_eps(case.eps)
     if mu is not None:
         o.set_mu(mu)
+    if pec is not None:
+        o.set_pec(pec)
     from workloads import plane_wave_2d
 
     kh, eh = plane_wave_2d(case.theta_deg, case.pol)

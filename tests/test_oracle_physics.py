@@ -137,6 +137,58 @@ def test_electromagnetic_duality(theta):
     assert np.max(np.abs(h1[..., 1] + e2[..., 1])) <= 1e-12 * scale
 
 
+def test_pec_half_space_reflects_totally():
+    """Perfect-conductor reading (zero E in flagged cells): a TM wave at
+    normal incidence onto a PEC half space is reflected with |r| = 1 (a
+    lossless wall transmits nothing), E vanishes in the conductor, and the
+    reflection's phase puts the effective wall between the last vacuum node
+    and the first PEC node."""
+    nx, Wd, lam, x0 = 256, 20, 32.0, 128
+    case = W.fresnel_case(0.0, "TM", nx=nx, eps_in=1.0, lam=lam)
+    mask = np.zeros((1, 1, nx), bool)
+    mask[..., x0:] = True
+    o = Oracle(nx, 1, 1, case.absorb, W.SIGMA_MAX)
+    o.set_pec(mask)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    o.set_source(lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    w0, wl = case.window
+    o.set_dft(np.arange(nx), w0, wl)
+    o.step(case.steps)
+    tot = o.get_dft()[:, 2]
+    inc = _row_phasors(W.vacuum_companion(case))[:, 2]
+    vac = slice(Wd + 8, x0 - 8)
+    r = np.abs(tot[vac] - inc[vac]) / np.abs(inc[vac])
+    assert abs(r.mean() - 1.0) < 1e-3 and r.std() < 1e-3, (r.mean(), r.std())
+    assert np.all(tot[x0:] == 0.0)
+    # E_r / E_i = -exp(2jk(x - x_w)): the phase gives the wall position x_w
+    k = 2 * np.pi / lam
+    x = np.arange(nx)[vac]
+    ratio = np.mean((tot[vac] - inc[vac]) / inc[vac] * np.exp(-2j * k * x))
+    x_w = -np.angle(-ratio) / (2 * k)
+    x_w = x_w + np.round((x0 - 0.5 - x_w) / (lam / 2)) * (lam / 2)
+    assert x0 - 1 <= x_w <= x0, x_w
+
+
+@pytest.mark.slow
+def test_pec_cylinder_matches_mie():
+    """Section 3.2.1's case at a coarse grid: a PEC cylinder (a = 20.5 cells,
+    lambda = 32, TM, E along the axis), |S(theta)|^2 from the NTFF of the
+    oracle run vs the PEC Lorenz-Mie series (b_n = J_n / H_n) at the
+    staircase's area-equivalent radius.  The paper reports 3e-3 at a/dx =
+    50 and a / lambda = 1; here a/dx = 20.5 holds 1 %."""
+    th = np.arange(0, 360, 0.5)
+    n, a, lam = 256, 20.5, 32.0
+    case = W.cylinder_case(1.0, "TM", n=n, a=a, lam=lam, W=32, steps=2400, half=29.5)
+    mask = W.circle(n, a, 2.0) > 1.0
+    tot = run.run_2d(case, W.SIGMA_MAX, W.RAMP_PERIODS, pec=mask)
+    inc = run.run_2d(W.vacuum_companion(case), W.SIGMA_MAX, W.RAMP_PERIODS)
+    S = run.intensity_2d(case, tot, inc, th)
+    aeq = np.sqrt(np.count_nonzero(mask) / np.pi)
+    ref = mie.cylinder_S2(th, 2 * np.pi * aeq / lam, None, "TM")
+    assert run.normalized_rms(S, ref) < 0.01, run.normalized_rms(S, ref)
+    assert np.allclose(S[1:360], S[719:360:-1], rtol=1e-6, atol=1e-9 * S.max())
+
+
 def test_absorbing_layer_energy_decay():
     """Section 2.2 open-boundary check: a pulse leaving the domain leaves
     ~1e-3 of the peak energy once the main packet has gone and <= 1e-5
