@@ -117,6 +117,20 @@ lbm_em_status lbm_em_set_permittivity(lbm_em_handle h, const void *eps, int32_t 
 lbm_em_status lbm_em_set_permeability(lbm_em_handle h, const void *mu, int32_t where,
                                       int32_t dtype);
 
+/* Perfect-conductor cells of a TM handle (section 3.2.1 scatters off PEC
+ * cylinders with E along the axis; the paper takes the boundary rule from
+ * the authors' earlier work, read here as: a flagged cell has zero electric
+ * field, its H is recovered with mu_r = 1, and the absorbing layer imposes
+ * no incident wave on it).  mask: nx*ny bytes [y][x], non-zero = conductor,
+ * on the host or the device (where); copied.  NULL removes the conductor.
+ * Cells leaving the mask return to mu_r = 1.  The mask shares the
+ * permeability plane (a conductor is stored as mu = 0), so it has the
+ * permeability map's limits: batches and the adjoint refuse the handle.
+ * Errors: EUNSUPPORTED for TE and 3-D handles or after adjoint_setup
+ * (staircase zero-E conductors are pinned for TM only), ESTATE while the
+ * handle belongs to a batch, EINVAL for a bad `where`. */
+lbm_em_status lbm_em_set_pec(lbm_em_handle h, const uint8_t *mask, int32_t where);
+
 /* Set the incident plane wave (see lbm_em_plane_wave).  EINVAL if khat or
  * ehat is not a unit vector, not perpendicular, 3*lambda is not integral,
  * or the polarisation does not match the handle (TM: ehat = +-z; TE/TM:

@@ -221,12 +221,19 @@ __device__ inline T recip(T e) {
 
 // Fields at a cell from pulled 2-D reduced populations.
 //   TM: F = (E_z, H_x, H_y); TE: F = (E_x, E_y, H_z).
-// MU: the cell has permeability mu (inv_mu = 1/mu); else mu_r = 1.
+// MU: the cell has permeability mu (inv_mu = 1/mu); else mu_r = 1.  In the
+// MU variant mu == 0 flags a perfect conductor: E = 0 there, and H is
+// recovered with mu_r = 1 (the rest populations of such a cell stay zero).
 template <typename T, int POL, bool MU = false>
 __device__ inline void fields2d(const T s[11], T eps, T inv_eps, T F[3], T mu = T(1), T inv_mu = T(1)) {
     const T rest = fma(T(6), eps, T(-4));  // z-pair (x2) plus slaved rest population
+    const bool pec = MU && mu == T(0);
+    if (MU && pec) {
+        mu = T(1);
+        inv_mu = T(1);
+    }
     if (POL == TM) {
-        F[0] = fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
+        F[0] = pec ? T(0) : fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
         if (MU) {
             const T rest_h = fma(T(6), mu, T(-4));
             F[1] = fma(rest_h, s[9], s[4] + s[5] + s[2] - s[3]) * inv_mu;
@@ -236,8 +243,8 @@ __device__ inline void fields2d(const T s[11], T eps, T inv_eps, T F[3], T mu = 
             F[2] = fma(T(2), s[10], s[6] + s[7] - s[0] + s[1]);
         }
     } else {
-        F[0] = fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
-        F[1] = fma(rest, s[9], s[4] + s[5] + s[6] + s[7]) * inv_eps;
+        F[0] = pec ? T(0) : fma(rest, s[8], s[0] + s[1] + s[2] + s[3]) * inv_eps;
+        F[1] = pec ? T(0) : fma(rest, s[9], s[4] + s[5] + s[6] + s[7]) * inv_eps;
         if (MU) F[2] = fma(fma(T(6), mu, T(-4)), s[10], s[4] - s[5] - s[2] + s[3]) * inv_mu;
         else F[2] = fma(T(2), s[10], s[4] - s[5] - s[2] + s[3]);
     }
@@ -464,7 +471,8 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
     collide2d<T, POL>(F, f);
     if (sig > T(0)) {
         // relax towards the incident wave's equilibrium (zero where eps != 1
-        // or mu != 1): f + sig (f_ref - f), one fused multiply-add per population
+        // or mu != 1, which includes a conductor's mu == 0): f + sig (f_ref - f),
+        // one fused multiply-add per population
         T R[3] = {0, 0, 0};
         if (a.src_on && eps == T(1) && (!MU || mu == T(1))) {
             const T w = PH ? st.gs * ur - st.gc * ui : plane_wave<T, 2>(a, st, x, y, 0);
@@ -1750,6 +1758,17 @@ __global__ void __launch_bounds__(256) k_fields(StepArgs<T> a, T *E, T *H) {
         E[cell * 3 + k] = Ev[k];
         H[cell * 3 + k] = Hv[k];
     }
+}
+
+// Write v into the pitched material plane wherever the dense [z][y][x]
+// byte mask is set (perfect-conductor cells: v = 0 in the mu plane).
+template <typename T>
+__global__ void k_mask_fill(const unsigned char *mask, T *plane, T v, int nx, int ny, int64_t sy, int64_t sz) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx) return;
+    if (mask[((int64_t)z * ny + y) * nx + x]) plane[(int64_t)z * sz + (int64_t)y * sy + x] = v;
 }
 
 // Copy a dense [z][y][x] array into the pitched eps buffer (any dtype in).

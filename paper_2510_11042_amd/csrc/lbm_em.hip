@@ -72,7 +72,9 @@ struct lbm_em {
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;                        // buf[cur] holds f*(t-1)
     void *eps = nullptr;
-    void *mu = nullptr;                 // permeability map (2-D); NULL: mu_r = 1
+    void *mu = nullptr;                 // permeability map (2-D; 0 = conductor); NULL: mu_r = 1
+    bool mu_user = false;               // mu holds a map set through set_permeability
+    unsigned char *pec = nullptr;       // dense [y][x] conductor mask (TM); NULL: none
     int64_t t = 0;
     hipStream_t stream = nullptr;
     int vx = 1, bx = 128, by = 2;       // cells per thread along x, block shape
@@ -850,6 +852,7 @@ void free_handle(lbm_em *h) {
     hfree(h->buf[1]);
     hfree(h->eps);
     hfree(h->mu);
+    hfree(h->pec);
     hfree(h->acc);
     hfree(h->t_dev);
     hfree(h->ck);
@@ -902,6 +905,20 @@ void load_material(lbm_em *h, const void *src, int32_t where, int32_t dtype, voi
         throw;
     }
     hfree(d_in);
+}
+
+// Write v into the mu plane at the cells of the handle's conductor mask.
+void mask_fill(lbm_em *h, double v) {
+    if (!h->pec || !h->mu) return;
+    const auto &c = h->cfg;
+    dim3 grid((c.nx + 255) / 256, c.ny, c.nz);
+    if (h->elem == 4)
+        hipLaunchKernelGGL((k_mask_fill<float>), grid, dim3(256), 0, h->stream, h->pec, (float *)h->mu, (float)v,
+                           c.nx, c.ny, h->sy, h->sz);
+    else
+        hipLaunchKernelGGL((k_mask_fill<double>), grid, dim3(256), 0, h->stream, h->pec, (double *)h->mu, v, c.nx,
+                           c.ny, h->sy, h->sz);
+    hip_check(hipGetLastError(), "k_mask_fill");
 }
 
 // Set every element of a padded material plane to 1.
@@ -1019,10 +1036,17 @@ lbm_em_status lbm_em_set_permeability(lbm_em_handle hh, const void *mu, int32_t 
         if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         if (h->adj_set) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
         select_device(h);
-        if (!mu) {   // back to mu_r = 1
+        if (!mu) {   // back to mu_r = 1 (conductor cells stay)
             sync(h);
-            hfree(h->mu);
-            h->mu = nullptr;
+            if (h->pec) {
+                fill_ones(h, h->mu);
+                mask_fill(h, 0.0);
+                sync(h);
+            } else {
+                hfree(h->mu);
+                h->mu = nullptr;
+            }
+            h->mu_user = false;
             drop_graphs(h);
             return;
         }
@@ -1038,6 +1062,55 @@ lbm_em_status lbm_em_set_permeability(lbm_em_handle hh, const void *mu, int32_t 
             throw;
         }
         h->mu = dst;
+        h->mu_user = true;
+        mask_fill(h, 0.0);
+        sync(h);
+        drop_graphs(h);
+    });
+}
+
+lbm_em_status lbm_em_set_pec(lbm_em_handle hh, const uint8_t *mask, int32_t where) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (h->cfg.pol != LBM_EM_TM)
+            fail(LBM_EM_EUNSUPPORTED, "perfect-conductor cells are supported for TM handles (E along the axis)");
+        if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
+        if (h->adj_set) fail(LBM_EM_EUNSUPPORTED, "the adjoint does not cover perfect conductors");
+        if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
+        select_device(h);
+        const size_t cells = (size_t)h->cfg.nx * h->cfg.ny * h->cfg.nz;
+        // release the previous mask: its cells return to mu_r = 1
+        mask_fill(h, 1.0);
+        sync(h);
+        hfree(h->pec);
+        h->pec = nullptr;
+        if (!mask) {
+            if (!h->mu_user) {
+                hfree(h->mu);
+                h->mu = nullptr;
+            }
+            drop_graphs(h);
+            return;
+        }
+        unsigned char *d = nullptr;
+        hip_check(hipMalloc(&d, cells), "hipMalloc pec");
+        try {
+            hip_check(hipMemcpyAsync(d, mask, cells, where == LBM_EM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                                     h->stream), "pec copy");
+            if (!h->mu) {
+                void *m = nullptr;
+                hip_check(hipMalloc(&m, (size_t)h->plane * h->elem), "hipMalloc mu");
+                h->mu = m;
+                fill_ones(h, h->mu);
+            }
+        } catch (...) {
+            sync(h);
+            hfree(d);
+            throw;
+        }
+        h->pec = d;
+        mask_fill(h, 0.0);
+        sync(h);
         drop_graphs(h);
     });
 }

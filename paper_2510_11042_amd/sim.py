@@ -47,7 +47,9 @@ class Simulation:
         L.check(L.lib().lbm_em_create(C.byref(cfg), C.byref(h)))
         self._h = h
         self._theta_inc = 0.0
-        self._has_mu = False
+        self._has_mu = False      # permeability plane in use (a map or conductor cells)
+        self._mu_user = False
+        self._pec_set = False
 
     @property
     def handle(self):
@@ -89,9 +91,35 @@ class Simulation:
         Batches and the adjoint refuse a handle with a permeability map."""
         if mu is None:
             L.check(L.lib().lbm_em_set_permeability(self._h, None, L.HOST, L.FP64))
-            self._has_mu = False
+            self._mu_user = False
+            self._has_mu = self._pec_set
             return
         self._set_material(L.lib().lbm_em_set_permeability, mu, "mu")
+        self._mu_user = True
+        self._has_mu = True
+
+    def set_pec(self, mask):
+        """Perfect-conductor cells of a TM run: boolean map laid out like eps
+        (numpy, or a torch uint8/bool tensor); None removes the conductor."""
+        if mask is None:
+            L.check(L.lib().lbm_em_set_pec(self._h, None, L.HOST))
+            self._pec_set = False
+            self._has_mu = self._mu_user
+            return
+        size = self.n[0] * self.n[1] * self.n[2]
+        if hasattr(mask, "data_ptr"):  # torch tensor
+            import torch
+
+            t = mask.contiguous().to(dtype=torch.uint8)
+            if t.numel() != size:
+                raise ValueError("mask has the wrong number of values")
+            L.check(L.lib().lbm_em_set_pec(self._h, C.c_void_p(t.data_ptr()), L.DEVICE if t.is_cuda else L.HOST))
+        else:
+            a = np.ascontiguousarray(mask, dtype=np.uint8)
+            if a.size != size:
+                raise ValueError("mask has the wrong number of values")
+            L.check(L.lib().lbm_em_set_pec(self._h, a.ctypes.data_as(C.c_void_p), L.HOST))
+        self._pec_set = True
         self._has_mu = True
 
     def set_source(self, lam, khat, ehat, amplitude=1.0, ramp_periods=3.0, center=None):

@@ -18,6 +18,9 @@ Measured here (FP32) vs the paper's value:
   cylinder a/lambda = 1, eps 20    2.5e-2   (6.6e-3)  -- see the design doc
   sphere eps 2, a/lambda = 1       0.9 / 0.9 / 1.4e-3 at phi 0/45/90
                                    (1.9 / 2.0 / 1.8e-3)
+  PEC cylinder, a/lambda = 0.1     1.8e-2   (1.5e-2)   min/max 0.411/1.03  (0.428/1.05)
+  PEC cylinder, a/lambda = 1       2.7e-3   (3.0e-3)   min/max 1.68/34.2   (1.82/34.2)
+  PEC cylinder, a/lambda = 10      3.7e-4   (7.2e-4)   min/max 7.27/2688   (8.81/2.6e3)
 The bounds are those values with a margin.
 """
 import sys
@@ -90,6 +93,56 @@ def test_cylinder_at_paper_resolution(P, eps_in, lam, a, L_over_a, periods, boun
     ref = mie.cylinder_S2(th, 2 * np.pi * a / lam, np.sqrt(eps_in), "TM")
     e, drift = nrms(S2, ref), nrms(S2, S1)
     say(f"  nRMS {e:.3e} (paper {paper:.1e}), window drift {drift:.1e}, max {S2.max():.4g} vs {ref.max():.4g}")
+    assert drift < 1e-3
+    assert e < bound
+    for s in sims:
+        s.close()
+
+
+PEC_CYLINDERS = [
+    # lambda/dx, a/dx, L/a, periods, bound, paper's normalised RMS
+    (500, 50, 20, 20, 2.5e-2, 1.5e-2),
+    (50, 50, 10, 60, 4e-3, 3.0e-3),
+    (50, 500, 4, 100, 1e-3, 7.2e-4),
+]
+
+
+@pytest.mark.parametrize("lam,a,L_over_a,periods,bound,paper", PEC_CYLINDERS, ids=lambda v: str(v))
+def test_pec_cylinder_at_paper_resolution(P, lam, a, L_over_a, periods, bound, paper):
+    """Section 3.2.1: PEC cylinders at a / lambda = 0.1, 1, 10 with
+    min(a, lambda)/dx = 50 and the paper's L/a, TM; conductor cells read as
+    zero-E cells (no rule is printed in the paper)."""
+    Wl = 32
+    n = int(round(L_over_a * a)) + 2 * Wl
+    T = int(3 * lam)
+    steps = periods * T
+    half = np.ceil(a) + max(6, np.ceil(lam / 4)) + 0.5
+    case = W.cylinder_case(1.0, "TM", n=n, a=float(a), lam=float(lam), W=Wl, steps=steps, half=half)
+    mask = W.circle(n, float(a), 2.0) > 1.0
+    say("pec cylinder", lam, a, n, steps)
+    sims = []
+    for pec in (False, True):
+        kh, eh = W.plane_wave_2d(0.0, "TM")
+        s = P.Simulation(n, n, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        if pec:
+            s.set_pec(mask)
+        s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+        s.step(steps)
+        sims.append(s)
+    inc, tot = sims
+    th = np.arange(0.0, 180.01, 0.5)
+    S1 = tot.farfield(th, incident=inc)
+    tot.set_ntff(case.box_lo, case.box_hi, steps, T)     # one more period: steady state
+    tot.step(T)
+    S2 = tot.farfield(th, incident=inc)
+    ref = mie.cylinder_S2(th, 2 * np.pi * a / lam, None, "TM")
+    aeq = np.sqrt(np.count_nonzero(mask) / np.pi)
+    e, drift = nrms(S2, ref), nrms(S2, S1)
+    e_in = min(nrms(S2, mie.cylinder_S2(th, 2 * np.pi * (a - d) / lam, None, "TM")) for d in (0.25, 0.5))
+    say(f"  nRMS {e:.3e} (paper {paper:.1e}; series at a - 1/4..1/2 cell: {e_in:.3e}; area-equivalent "
+        f"radius {aeq:.3f}), window drift {drift:.1e}, min/max {S2.min():.4g}/{S2.max():.4g} vs "
+        f"{ref.min():.4g}/{ref.max():.4g}")
     assert drift < 1e-3
     assert e < bound
     for s in sims:

@@ -558,3 +558,137 @@ def test_permeability_api_limits(gpu):
         s3.set_permeability(np.ones((8, 8, 8)))
     for h in (s, other, ref, s3):
         h.close()
+
+
+def _pec_disc(nx, ny, cx, cy, r):
+    y, x = np.mgrid[0:ny, 0:nx]
+    return (((x - cx) ** 2 + (y - cy) ** 2) < r * r)[None]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pec_fields_match_oracle(gpu, prec):
+    """Perfect-conductor cells (zero-E reading) on a ragged 83 x 61 TM grid
+    absorbing on both axes, with a conductor disc, a conductor strip reaching
+    into the layer, a dielectric blob and a magnetic blob; oblique incidence,
+    eager steps and graph chunks, the default two-step launches.  Then the
+    conductor is removed (its cells return to mu_r = 1) and a restarted run is
+    compared again."""
+    nx, ny, Wd = 83, 61, 10
+    eps, mu = _mu_maps(nx, ny, Wd)
+    pec = _pec_disc(nx, ny, 0.3 * nx, 0.6 * ny, 7.5)
+    pec[0, :4, 50:60] = True
+    th = np.deg2rad(30.0)
+    kh, eh = [np.cos(th), np.sin(th), 0.0], [0, 0, 1.0]
+    say("pec", prec)
+    s, o = make_pair(gpu, nx, ny, 1, "TM", prec, (Wd, Wd, 0), eps, 12.0, kh, eh, ramp=1.0)
+    s.set_pec(pec)
+    s.set_permeability(mu)          # the conductor stays
+    o.set_mu(mu)
+    o.set_pec(pec)
+    for n in (1, 9, 190):
+        s.step(n)
+        o.step(n)
+        compare_fields(s, o, prec, f"pec t={o.t}")
+        Eg, _ = s.fields()
+        assert np.all(Eg[pec] == 0.0)
+    s.set_pec(None)
+    s.reset()
+    o2 = Oracle(nx, ny, 1, (Wd, Wd, 0), W.SIGMA_MAX)
+    o2.set_eps(eps)
+    mu2 = mu.copy()
+    mu2[pec] = 1.0
+    o2.set_mu(mu2)
+    o2.set_source(12.0, kh, eh, 1.0, 1.0, [(nx - 1) / 2.0, (ny - 1) / 2.0, 0.0])
+    s.step(90)
+    o2.step(90)
+    compare_fields(s, o2, prec, f"pec removed t={o2.t}")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_pec_two_steps_bit_identical(gpu, prec):
+    """Conductor cells through the two-step kernel (every tile) reproduce one
+    step per launch bit for bit, TM, ragged grid, either axis periodic."""
+    nx, ny = 203, 77
+    pec = _pec_disc(nx, ny, 100.0, 38.0, 14.5)
+    pec[0, :5, 20:40] = True                        # touches the y faces / layer
+    th = np.deg2rad(25.0)
+    kh, eh = [np.cos(th), np.sin(th), 0.0], [0, 0, 1.0]
+    for absorb in ((11, 0, 0), (0, 9, 0)):
+        runs = []
+        for fuse, tile in [(1, (0, 0))] + [(2, t) for t in X2_TILES[prec]]:
+            s = gpu(nx, ny, 1, pol="TM", precision=prec, absorb=absorb, sigma_max=W.SIGMA_MAX)
+            s.set_pec(pec)
+            s.set_source(10.0, kh, eh, 1.0, 1.0)
+            s.set_ntff((60, 20, 0), (140, 56, 0), 100, 30)
+            s.set_fusion(fuse, tile)
+            for n in (3, 131, 1):
+                s.step(n)
+            runs.append((s.fields(), s.phasors()))
+            say("pec fusion", prec, absorb, fuse, tile, s.t)
+            s.close()
+        (E1, H1), (X1, p1) = runs[0]
+        assert np.abs(E1).max() > 0
+        for (E2, H2), (X2, p2) in runs[1:]:
+            assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
+            assert np.array_equal(X1, X2) and np.array_equal(p1, p2)
+
+
+def test_pec_cylinder_pipeline_intensity(gpu):
+    """Whole path on a PEC cylinder (160^2, a = 12.5, lambda = 24, TM, 1800
+    steps): contour phasors and |S|^2 against the oracle, FP64 and FP32."""
+    case = W.cylinder_case(1.0, "TM", n=160, a=12.5, lam=24.0, W=24, steps=1800, half=19.5)
+    pec = W.circle(case.nx, case.radius, 2.0) > 1.0
+    inc_case = W.vacuum_companion(case)
+    say("pec pipeline")
+    tot_o = run.run_2d(case, W.SIGMA_MAX, W.RAMP_PERIODS, pec=pec)
+    inc_o = run.run_2d(inc_case, W.SIGMA_MAX, W.RAMP_PERIODS)
+    th = np.arange(0, 360, 1.0)
+    S_o = run.intensity_2d(case, tot_o, inc_o, th)
+    for prec, ptol, stol in (("fp64", 1e-11, 1e-10), ("fp32", 1e-4, 1e-3)):
+        kh, eh = W.plane_wave_2d(0.0, "TM")
+        tot_g = gpu(case.nx, case.ny, 1, pol="TM", precision=prec, absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        tot_g.set_pec(pec)
+        tot_g.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        tot_g.set_ntff(case.box_lo, case.box_hi, *case.window)
+        tot_g.step(case.steps)
+        inc_g = _gpu_case(gpu, inc_case, prec)
+        X, probe = tot_g.phasors()
+        scale = np.abs(tot_o["phasors"]).max()
+        perr = np.abs(X - tot_o["phasors"]).max() / scale
+        say(prec, "pec phasor err", perr)
+        assert perr <= ptol
+        S_g = tot_g.farfield(th, incident=inc_g)
+        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
+        say(prec, "pec |S|^2 normalised rms err", serr)
+        assert serr <= stol
+
+
+def test_pec_api_limits(gpu):
+    """Conductor cells are refused on TE and 3-D handles; a handle with them
+    is refused by batches and the adjoint."""
+    from paper_2510_11042_amd import LbmEmError, step_many
+
+    n = 64
+    mask = _pec_disc(n, n, 31.5, 31.5, 5.0)
+    te = gpu(n, n, 1, pol="TE", precision="fp32", absorb=(12, 12, 0), sigma_max=W.SIGMA_MAX)
+    with pytest.raises(LbmEmError):
+        te.set_pec(mask)
+    s3 = gpu(8, 8, 8, pol="3D", precision="fp32", absorb=(0, 0, 0), sigma_max=W.SIGMA_MAX)
+    with pytest.raises(LbmEmError):
+        s3.set_pec(np.zeros((8, 8, 8), bool))
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    a = gpu(n, n, 1, pol="TM", precision="fp32", absorb=(12, 12, 0), sigma_max=W.SIGMA_MAX)
+    b = gpu(n, n, 1, pol="TM", precision="fp32", absorb=(12, 12, 0), sigma_max=W.SIGMA_MAX)
+    for h in (a, b):
+        h.set_source(16.0, kh, eh, 1.0, 1.0)
+    a.set_pec(mask)
+    with pytest.raises(LbmEmError):
+        step_many([a, b], 2)
+    a.set_ntff((20, 20, 0), (43, 43, 0), 48, 48)
+    with pytest.raises(LbmEmError):
+        a.adjoint_setup(b, [0.0], (28, 28), (35, 35))
+    a.set_pec(None)                 # no map left: batches work again
+    step_many([a, b], 2)
+    for h in (te, s3, a, b):
+        h.close()
