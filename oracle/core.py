@@ -34,6 +34,9 @@ def lib():
         L.oracle_set_eps.argtypes = [P, D]
         L.oracle_set_mu.argtypes = [P, D]
         L.oracle_set_pec.argtypes = [P, C.c_void_p]
+        L.oracle_set_incident_line.restype = C.c_int
+        L.oracle_set_incident_line.argtypes = [P, C.c_int]
+        L.oracle_get_line_dft.argtypes = [P, D]
         L.oracle_set_source.argtypes = [P, C.c_double, D, D, C.c_double, C.c_double, D]
         L.oracle_clear_source.argtypes = [P]
         L.oracle_set_dft.argtypes = [P, I64, C.POINTER(I64), I64, I64]
@@ -80,6 +83,7 @@ class Oracle:
             raise ValueError("oracle_create rejected the grid / layer sizes")
         self.ncell = nx * ny * nz
         self._dft_n = 0
+        self._line_n = 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -119,6 +123,22 @@ class Oracle:
 
     def clear_source(self):
         lib().oracle_clear_source(self._h)
+
+    def set_incident_line(self, axis):
+        """Exact incident line along axis 0 (x) or 1 (y), None to remove it
+        (lbm_oracle.c: the one-row auxiliary run and its layer rule).  Call
+        after set_source and before stepping."""
+        rc = lib().oracle_set_incident_line(self._h, -1 if axis is None else int(axis))
+        if rc != 0:
+            raise ValueError("the incident line needs a 2-D grid and a source along that axis")
+        self._line_n = 0 if axis is None else self.n[int(axis)]
+
+    def get_line_dft(self):
+        """The line's phasors, shape (n_axis, 6): Ex, Ey, Ez, Hx, Hy, Hz."""
+        out = np.zeros((max(self._line_n, 1), 12))
+        lib().oracle_get_line_dft(self._h, _dp(out))
+        out = out[: self._line_n]
+        return out[:, 0::2] + 1j * out[:, 1::2]
 
     # -- DFT -----------------------------------------------------------
     def set_dft(self, cells, win0, winlen):

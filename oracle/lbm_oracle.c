@@ -47,6 +47,17 @@
  *     eps_r play no role there, so the rest populations stay zero), E is set
  *     to 0 before the DFT sample and the collision, and the absorbing layer
  *     imposes no incident wave on it.  The adjoint does not cover PEC cells.
+ *   - Exact incident line (a total-field / scattered-field-like forcing for
+ *     axis-aligned incidence, which section 4 names as future work): an
+ *     auxiliary one-row run along the incidence axis (same layers on that
+ *     axis, background medium, same source) is advanced with the grid.  In a
+ *     background layer cell the update becomes
+ *         f' = f* + sigma (f_l* - f*) + sigma_a (f^eq_ref - f_l*),
+ *     with f_l* the line's post-collision populations at the cell's
+ *     coordinate along the axis and sigma_a the line's own layer strength
+ *     there: the scattered part f* - f_l* is damped by sigma and the line's
+ *     own forcing is added, so a background-only run reproduces the line
+ *     exactly, and the line's DFT is the incident field.
  *
  * Order inside one time step t (paper section 2.1): moments -> DFT sample ->
  * collision -> absorbing-layer/source blend -> push streaming -> open
@@ -70,7 +81,7 @@
 static const int CV[NQ][3] = {
     {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 
-typedef struct {
+typedef struct lbm_oracle_s {
     int n[3];           /* nx, ny, nz                                     */
     int W[3];           /* absorbing width per axis; 0 = periodic axis    */
     double sigma_max;
@@ -79,6 +90,11 @@ typedef struct {
     double *g;          /* scratch: post-collision / streamed                 */
     double *eps, *mu;   /* per-cell relative permittivity / permeability      */
     unsigned char *pec; /* per-cell PEC flag (NULL: no conductor)             */
+    /* exact incident line */
+    struct lbm_oracle_s *line;  /* the one-row auxiliary run, NULL: off      */
+    int line_axis;              /* 0: along x, 1: along y                    */
+    double *star;               /* if set: post-collision populations of the */
+                                /* current step are stored here (NV / cell)  */
     double *E, *H;      /* fields at time t, 3 per cell                       */
     int64_t t;
     /* plane wave */
@@ -227,6 +243,10 @@ void oracle_destroy(lbm_oracle *o) {
     if (!o) return;
     free(o->f); free(o->g); free(o->eps); free(o->mu); free(o->pec); free(o->E); free(o->H);
     free(o->dft_cell); free(o->dft);
+    if (o->line) {
+        free(o->line->star);
+        oracle_destroy(o->line);
+    }
     free(o);
 }
 
@@ -275,6 +295,50 @@ void oracle_set_dft(lbm_oracle *o, int64_t n, const int64_t *cells, int64_t win0
     if (n > 0) memcpy(o->dft_cell, cells, (size_t)n * sizeof(int64_t));
     o->win0 = win0;
     o->winlen = winlen;
+    if (o->line) {
+        const int na = o->n[o->line_axis];
+        int64_t *all = (int64_t *)malloc((size_t)na * sizeof(int64_t));
+        for (int u = 0; u < na; ++u) all[u] = u;
+        oracle_set_dft(o->line, na, all, win0, winlen);
+        free(all);
+    }
+}
+
+/* Exact incident line along axis (0: x, 1: y) for a 2-D grid whose source
+ * propagates along that axis; axis < 0 removes it.  The line starts from a
+ * zero state at the grid's current time, so set it before stepping.  The
+ * line records its fields at all its cells over the DFT window of the most
+ * recent oracle_set_dft call.  Returns 0, or -1 if the grid or the source
+ * does not allow a line. */
+int oracle_set_incident_line(lbm_oracle *o, int axis) {
+    if (o->line) {
+        free(o->line->star);
+        oracle_destroy(o->line);
+        o->line = NULL;
+    }
+    if (axis < 0) return 0;
+    if (axis > 1 || o->n[2] != 1 || !o->src_on || fabs(fabs(o->khat[axis]) - 1.0) > 1e-12) return -1;
+    const int na = o->n[axis];
+    lbm_oracle *l = oracle_create(axis == 0 ? na : 1, axis == 0 ? 1 : na, 1, axis == 0 ? o->W[0] : 0,
+                                  axis == 0 ? 0 : o->W[1], 0, o->sigma_max);
+    if (!l) return -1;
+    oracle_set_source(l, o->lambda, o->khat, o->ehat, o->amp, o->t_ramp, o->rc);
+    l->t = o->t;
+    l->star = (double *)calloc((size_t)na * NV, sizeof(double));
+    if (o->ndft > 0) {
+        int64_t *cells = (int64_t *)malloc((size_t)na * sizeof(int64_t));
+        for (int u = 0; u < na; ++u) cells[u] = u;
+        oracle_set_dft(l, na, cells, o->win0, o->winlen);
+        free(cells);
+    }
+    o->line = l;
+    o->line_axis = axis;
+    return 0;
+}
+
+/* The line's phasors: n_axis x 6 components x (re, im). */
+void oracle_get_line_dft(const lbm_oracle *o, double *out) {
+    if (o->line) memcpy(out, o->line->dft, (size_t)o->line->ndft * 12 * sizeof(double));
 }
 
 void oracle_get_dft(const lbm_oracle *o, double *out) {
@@ -307,6 +371,14 @@ int oracle_threads(void) {
 
 /* Collision and absorbing-layer blend of one cell, in place:
  * f <- 2 f^eq - f, then f <- f - sigma (f - f^eq_ref). */
+/* Layer strength of the incident line at coordinate u along its axis. */
+static double line_sigma(const lbm_oracle *o, int u) {
+    const lbm_oracle *l = o->line;
+    int xyz[3] = {0, 0, 0};
+    xyz[o->line_axis] = u;
+    return sigma_at(l, xyz);
+}
+
 static void collide_cell(const lbm_oracle *o, int64_t c, int64_t t, double f[NV]) {
     int xyz[3];
     cell_xyz(o, c, xyz);
@@ -315,7 +387,20 @@ static void collide_cell(const lbm_oracle *o, int64_t c, int64_t t, double f[NV]
     cell_fields(o, c, f, E, H);
     equilibrium(E, H, eps, mu, feq);
     for (int v = 0; v < NV; ++v) f[v] = 2.0 * feq[v] - f[v];
+    if (o->star) memcpy(o->star + c * NV, f, NV * sizeof(double));
     double s = sigma_at(o, xyz);
+    if (s > 0.0 && o->line && o->src_on && !pec && eps == 1.0 && mu == 1.0) {
+        /* exact incident line: damp the scattered part, add the line's own
+         * forcing (f_l* = the line's post-collision populations this step) */
+        const int u = xyz[o->line_axis];
+        const double *fl = o->line->star + (int64_t)u * NV;
+        const double sa = line_sigma(o, u);
+        double Er[3], Hr[3], fref[NV];
+        reference_field(o, xyz, eps, mu, t, Er, Hr);
+        equilibrium(Er, Hr, eps, mu, fref);
+        for (int v = 0; v < NV; ++v) f[v] = f[v] + s * (fl[v] - f[v]) + sa * (fref[v] - fl[v]);
+        return;
+    }
     if (s > 0.0) {
         double Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0}, fref[NV];
         if (!pec) reference_field(o, xyz, eps, mu, t, Er, Hr);
@@ -380,6 +465,10 @@ static void push_and_obc(const lbm_oracle *o, const double *in, double *out) {
 static void step_once(lbm_oracle *o) {
     const int64_t N = o->ncell;
     const int64_t t = o->t;
+
+    /* 0. the incident line takes its step t first; its post-collision
+     * populations of this step stay in line->star */
+    if (o->line) step_once(o->line);
 
     /* 1. moments -> fields at time t */
 #pragma omp parallel for schedule(static) if (N > 4096)

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import mie, run
+from oracle import mie, ntff, run
 from oracle.analytic import fresnel_normal, fresnel_oblique
 from oracle.core import Oracle
 
@@ -187,6 +187,63 @@ def test_pec_cylinder_matches_mie():
     ref = mie.cylinder_S2(th, 2 * np.pi * aeq / lam, None, "TM")
     assert run.normalized_rms(S, ref) < 0.01, run.normalized_rms(S, ref)
     assert np.allclose(S[1:360], S[719:360:-1], rtol=1e-6, atol=1e-9 * S.max())
+
+
+@pytest.mark.parametrize("theta,pol,axis", [(0.0, "TM", 0), (0.0, "TE", 0), (180.0, "TM", 0),
+                                            (90.0, "TE", 1), (270.0, "TM", 1)])
+def test_incident_line_is_exact(theta, pol, axis):
+    """Exact incident line (lbm_oracle.c): with the line's layer rule, a
+    background-only grid absorbing on both axes reproduces the one-row line
+    at every row, bit for bit -- the property that lets the line stand in
+    for the full vacuum companion run."""
+    nx, ny = 96, 72
+    o = Oracle(nx, ny, 1, (16, 10, 0), W.SIGMA_MAX)
+    kh, eh = W.plane_wave_2d(theta, pol)
+    kh = np.round(kh, 15)
+    o.set_source(16.0, kh, eh, 1.0, 1.0)
+    o.set_dft(np.arange(nx * ny), 150, 48)
+    o.set_incident_line(axis)
+    o.step(200)
+    X = o.get_dft().reshape(ny, nx, 6)
+    L = o.get_line_dft()
+    assert np.abs(L).max() > 0.5
+    if axis == 0:
+        assert np.array_equal(X, np.broadcast_to(L[None, :, :], X.shape))
+    else:
+        assert np.array_equal(X, np.broadcast_to(L[:, None, :], X.shape))
+
+
+@pytest.mark.slow
+def test_incident_line_cylinder_matches_companion():
+    """The line's phasors as the incident field of the NTFF: |S(theta)|^2 of
+    the small dielectric cylinder agrees with the companion-run result (the
+    two differ only in how the layers force the incident wave) to 2e-4 and
+    with Lorenz-Mie as closely as the companion does."""
+    th = np.arange(0, 360, 0.5)
+    for pol in ("TM", "TE"):
+        case = W.cylinder_case(2.25, pol, n=192, a=10.5, lam=32.0, W=32, steps=2400, half=19.5)
+        o = Oracle(case.nx, case.ny, 1, case.absorb, W.SIGMA_MAX)
+        o.set_eps(case.eps)
+        kh, eh = W.plane_wave_2d(0.0, pol)
+        o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        nodes = ntff.box_nodes(case.box_lo, case.box_hi)
+        pr = run.probe_node(case.box_lo, case.box_hi)
+        cells = np.concatenate([ntff.linear_index(nodes, (case.nx, case.ny)),
+                                ntff.linear_index(np.array([pr]), (case.nx, case.ny))])
+        o.set_dft(cells, *case.window)
+        o.set_incident_line(0)
+        o.step(case.steps)
+        X, Lx = o.get_dft(), o.get_line_dft()
+        tot = {"nodes": nodes, "phasors": X[:-1], "probe": X[-1]}
+        inc_line = {"phasors": Lx[nodes[:, 0]], "probe": Lx[pr[0]]}
+        S_line = run.intensity_2d(case, tot, inc_line, th)
+        tot_c = run.run_2d(case, W.SIGMA_MAX, W.RAMP_PERIODS)
+        inc_c = run.run_2d(W.vacuum_companion(case), W.SIGMA_MAX, W.RAMP_PERIODS)
+        S_comp = run.intensity_2d(case, tot_c, inc_c, th)
+        aeq = np.sqrt(np.count_nonzero(case.eps > 1) / np.pi)
+        ref = mie.cylinder_S2(th, 2 * np.pi * aeq / 32.0, 1.5, pol)
+        assert run.normalized_rms(S_line, S_comp) < 2e-4, (pol, run.normalized_rms(S_line, S_comp))
+        assert run.normalized_rms(S_line, ref) < 0.015, (pol, run.normalized_rms(S_line, ref))
 
 
 def test_absorbing_layer_energy_decay():
