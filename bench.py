@@ -212,6 +212,33 @@ def magnetic_extra(Simulation, W, torch, steps=1600):
     return res
 
 
+def line_extra(Simulation, W, torch, steps=1600):
+    """The cylinder grid with the exact incident line instead of a companion
+    run: the line's own small launch precedes every grid launch, and the
+    layer cells read the line's populations (1024^2, eps 2.25, TM)."""
+    case = W.cylinder_case(2.25, "TM", n=1024)
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    out = {}
+    for line in (False, True):
+        s = Simulation(case.nx, case.ny, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(case.eps)
+        s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        if line:
+            s.set_incident_line(True)
+        s.step(256)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        out["with_line" if line else "without"] = e0.elapsed_time(e1) / steps * 1e3
+        s.close()
+    return {"workload": "cylinder-1024x1024-eps2.25-TM", "us_per_step": out,
+            "line_overhead": out["with_line"] / out["without"] - 1.0,
+            "note": "the line replaces the full vacuum companion run (one more 1024^2 grid)"}
+
+
 def batched_extra(P, W, torch, steps=6000):
     """64 seeded uneven instances (circle/hexagon, eps, size, lambda, angle),
     6000 steps: one Batch (persistent launch per step, graph replay) against
@@ -359,7 +386,7 @@ def main():
     ap.add_argument("--lbm-steps", type=int, default=8000, help="time steps per solve (workload: 8000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="copy,streams,sphere,magnetic,batched,adjoint",
+    ap.add_argument("--extras", default="copy,streams,sphere,magnetic,line,batched,adjoint",
                     help="comma list of extra measurements to run")
     ap.add_argument("--tile", default=None,
                     help="two-step tile TX,TY instead of autotuning (profiling runs)")
@@ -455,6 +482,8 @@ def main():
             line["extra"]["sphere_3d"] = sphere_extra(Simulation, W, torch)
         if "magnetic" in want:
             line["extra"]["magnetic"] = magnetic_extra(Simulation, W, torch)
+        if "line" in want:
+            line["extra"]["incident_line"] = line_extra(Simulation, W, torch)
         if "batched" in want:
             line["extra"]["batched"] = batched_extra(P, W, torch)
         if "adjoint" in want:

@@ -150,6 +150,32 @@ lbm_em_status lbm_em_set_source(lbm_em_handle h, const lbm_em_plane_wave *pw);
 lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_t hi[3],
                               int64_t window_start, int64_t window_len);
 
+/* Exact incident line (a total-field / scattered-field-like forcing, which
+ * the paper names as future work in section 4) for a 2-D handle whose
+ * source propagates along +-x or +-y (|khat| components within 1e-12 of
+ * axis-aligned): a one-row (one-column) run along that axis, with the same
+ * layers on it and the same source, advances with the grid (one small
+ * launch before each grid launch).  In background layer cells (eps_r =
+ * mu_r = 1) the layer then damps only the scattered part,
+ *     f' = f* + sigma (f_l* - f*) + sigma_a (f^eq_ref - f_l*),
+ * f_l* being the line's post-collision populations at the cell's coordinate
+ * along the axis and sigma_a the line's own layer strength there.  A
+ * background-only grid reproduces the line at every row bit for bit, so the
+ * line's phasors are the exact incident field: lbm_em_farfield(h, NULL, ...)
+ * then subtracts and normalises by them and no companion run is needed.
+ * enable = 0 removes the line.  Set it after the source and before stepping
+ * (t = 0, or after a reset); a new source removes it.  Batches and the
+ * adjoint refuse a handle with a line.
+ * Errors: EUNSUPPORTED for 3-D handles or after adjoint_setup, ESTATE
+ * without a source, at t > 0 or while batched, EINVAL for other directions. */
+lbm_em_status lbm_em_set_incident_line(lbm_em_handle h, int32_t enable);
+
+/* The incident line's phasors: out[(u*6 + c)*2 + {0,1}] = (re, im) of
+ * component c in (Ex, Ey, Ez, Hx, Hy, Hz) at coordinate u along the line
+ * (over the window of lbm_em_set_ntff); *n receives the line length (out
+ * = NULL queries it).  ESTATE without a line.  Synchronises. */
+lbm_em_status lbm_em_get_line_phasors(lbm_em_handle h, double *out, int32_t *n);
+
 /* Advance n >= 0 time steps (asynchronous on the handle's stream): pull
  * streaming with the open boundary, moments, tau = 1/2 collision, absorbing
  * layer / source, contour DFT -- one fused kernel per step.  Steps are
@@ -243,7 +269,9 @@ lbm_em_status lbm_em_get_phasors(lbm_em_handle h, double *out, int32_t *n_nodes)
  * (phi ignored); 3-D: phi about khat measured from ehat.  Host arrays of
  * n_angles; out_S2 receives |S|^2 (2-D: k r |E_s|^2/|E_i|^2, Eq. S2D; 3-D:
  * k^2 r^2 |E_s|^2/|E_i|^2, Eq. S3D).  incident = NULL: no subtraction and
- * normalisation by the source amplitude.  ESTATE if the DFT window has not
+ * normalisation by the source amplitude, or, on a handle with an incident
+ * line, subtraction of and normalisation by the line's phasors.  ESTATE if
+ * the DFT window has not
  * been completed or the incident probe amplitude is zero.  Synchronises. */
 lbm_em_status lbm_em_farfield(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
                               const double *phi_deg, int32_t n_angles, double *out_S2);

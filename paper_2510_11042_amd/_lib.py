@@ -18,6 +18,7 @@ HOST, DEVICE = 0, 1
 # Every exported symbol the header declares (checked by the ABI test).
 EXPORTS = [
     "lbm_em_create", "lbm_em_destroy", "lbm_em_set_permittivity", "lbm_em_set_permeability", "lbm_em_set_pec",
+    "lbm_em_set_incident_line", "lbm_em_get_line_phasors",
     "lbm_em_set_source",
     "lbm_em_set_ntff", "lbm_em_step", "lbm_em_step_many", "lbm_em_batch_create", "lbm_em_batch_step",
     "lbm_em_batch_set_grid", "lbm_em_batch_set_cache_budget", "lbm_em_batch_groups", "lbm_em_batch_destroy", "lbm_em_set_tile", "lbm_em_get_tile", "lbm_em_set_fusion", "lbm_em_get_fusion",
@@ -64,6 +65,8 @@ def lib():
             "lbm_em_set_permittivity": [H, C.c_void_p, C.c_int32, C.c_int32],
             "lbm_em_set_permeability": [H, C.c_void_p, C.c_int32, C.c_int32],
             "lbm_em_set_pec": [H, C.c_void_p, C.c_int32],
+            "lbm_em_set_incident_line": [H, C.c_int32],
+            "lbm_em_get_line_phasors": [H, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
             "lbm_em_set_source": [H, C.POINTER(PlaneWave)],
             "lbm_em_set_ntff": [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int64, C.c_int64],
             "lbm_em_step": [H, C.c_int64],

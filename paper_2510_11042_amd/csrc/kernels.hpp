@@ -134,6 +134,14 @@ struct StepArgs {
     T *hist;
     int dlo[2], dhi[2];
     int64_t hist_t0;
+    // exact incident line (2-D, incidence along axis line_axis, line_n cells
+    // on it): post-collision populations of the line at step t in slot t & 1
+    // (2 slots x 11 planes x line_n).  The grid's kernels read line_tab; the
+    // line's own kernel writes line_rec and its phasors line_acc (line_n x 12).
+    const T *line_tab;
+    T *line_rec;
+    double *line_acc;
+    int line_axis, line_n;
 };
 
 // Layer strength at coordinate x of an axis of n cells with a layer of W
@@ -438,15 +446,30 @@ __device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
 // PH: the cell's incident-wave phase factor (ur, ui) = e^{2 pi j u} was
 // gathered by the caller (the two-step kernel prefetches it for the tiles
 // that touch the layer), else it is gathered here.  MU: the cell has
-// permeability mu (inv_mu = 1/mu).
-template <typename T, int POL, bool HIST = false, bool PH = false, bool MU = false>
+// permeability mu (inv_mu = 1/mu).  LINE: background layer cells follow the
+// exact incident line (see below).  LREC: this is the line's own update; it
+// records the post-collision populations and the phasors of every cell.
+template <typename T, int POL, bool HIST = false, bool PH = false, bool MU = false, bool LINE = false,
+          bool LREC = false>
 __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, T eps,
                                      T inv_eps, T sig, T f[11], bool record, T ur = T(0), T ui = T(0),
-                                     T mu = T(1), T inv_mu = T(1)) {
+                                     T mu = T(1), T inv_mu = T(1), const T *fl = nullptr, int fl_stride = 0) {
     const int64_t t = st.t;
     T F[3];
     fields2d<T, POL, MU>(f, eps, inv_eps, F, mu, inv_mu);
-    if (st.dft && record) {
+    if (LREC) {
+        if (st.dft && record) {
+            // line phasors, one node per line cell, same transform as the contour's
+            double *p = a.line_acc + (int64_t)(a.line_axis == 0 ? x : y) * 12;
+            const int c0 = POL == TM ? 2 : 0, c1 = POL == TM ? 3 : 1, c2 = POL == TM ? 4 : 5;
+            p[2 * c0] += (double)F[0] * st.cr;
+            p[2 * c0 + 1] += (double)F[0] * st.ci;
+            p[2 * c1] += (double)F[1] * st.cr;
+            p[2 * c1 + 1] += (double)F[1] * st.ci;
+            p[2 * c2] += (double)F[2] * st.cr;
+            p[2 * c2 + 1] += (double)F[2] * st.ci;
+        }
+    } else if (st.dft && record) {
         double G[6] = {0, 0, 0, 0, 0, 0};
         if (POL == TM) {
             G[2] = F[0]; G[3] = F[1]; G[4] = F[2];
@@ -469,20 +492,42 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
         }
     }
     collide2d<T, POL>(F, f);
+    if (LREC) {
+        T *r = a.line_rec + (int64_t)(t & 1) * 11 * a.line_n + (a.line_axis == 0 ? x : y);
+#pragma unroll
+        for (int i = 0; i < 11; ++i) r[(int64_t)i * a.line_n] = f[i];
+    }
     if (sig > T(0)) {
         // relax towards the incident wave's equilibrium (zero where eps != 1
         // or mu != 1, which includes a conductor's mu == 0): f + sig (f_ref - f),
         // one fused multiply-add per population
         T R[3] = {0, 0, 0};
-        if (a.src_on && eps == T(1) && (!MU || mu == T(1))) {
+        const bool background = a.src_on && eps == T(1) && (!MU || mu == T(1));
+        if (background) {
             const T w = PH ? st.gs * ur - st.gc * ui : plane_wave<T, 2>(a, st, x, y, 0);
             if (POL == TM) { R[0] = w * a.ehat[2]; R[1] = w * a.hhat[0]; R[2] = w * a.hhat[1]; }
             else { R[0] = w * a.ehat[0]; R[1] = w * a.ehat[1]; R[2] = w * a.hhat[2]; }
         }
         T qr[11];
         equilibrium2d<T, POL>(R, T(1), qr);
+        if (LINE && background) {
+            // exact incident line: damp the scattered part f - f_l towards
+            // zero and add the line's own relaxation, f_l + sig_a (f_ref - f_l)
+            // with sig_a its layer strength here; where f == f_l this is
+            // the line's update operation for operation.  fl: the line's
+            // post-collision populations of this step at this coordinate
+            // (plane i at fl[i * fl_stride]).
+            const int ax = a.line_axis, u = ax == 0 ? x : y;
+            const T sa = sigma_axis<T>(u, ax == 0 ? a.nx : a.ny, a.W[ax], a.inv_w[ax], a.sigma_max);
 #pragma unroll
-        for (int i = 0; i < 11; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
+            for (int i = 0; i < 11; ++i) {
+                const T l = fl[i * fl_stride];
+                f[i] = fma(sa, qr[i] - l, fma(sig, l - f[i], f[i]));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 11; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
+        }
     }
 }
 
@@ -562,8 +607,9 @@ __device__ inline void store_row(const StepArgs<T> &a, int x0, int y, const T (&
 // 2-D fused step: pull + moments + DFT + collision + layer/source + store.
 // The calling thread updates cells x0 .. x0+VX-1 of row y.
 // ---------------------------------------------------------------------------
-// MU: the permeability variant (a.mu is read per cell).
-template <typename T, int POL, int VX, bool HIST = false, bool MU = false>
+// MU: the permeability variant (a.mu is read per cell).  LINE / LREC: see
+// cell_update2d.
+template <typename T, int POL, int VX, bool HIST = false, bool MU = false, bool LINE = false, bool LREC = false>
 __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const StepConst<T> &st) {
     if (x0 >= a.nx || y >= a.ny) return;
     T v[11][VX], e[VX], m[VX];
@@ -581,11 +627,16 @@ __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const S
         T f[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = v[i][k];
+        const T *fl = nullptr;
+        if (LINE) fl = a.line_tab + (int64_t)(st.t & 1) * 11 * a.line_n + (a.line_axis == 0 ? x : y);
         if (MU)
-            cell_update2d<T, POL, false, false, true>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f,
-                                                      x0 + k < a.nx, T(0), T(0), m[k], recip(m[k]));
+            cell_update2d<T, POL, false, false, true, LINE, LREC>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y),
+                                                                  f, x0 + k < a.nx, T(0), T(0), m[k], recip(m[k]), fl,
+                                                                  a.line_n);
         else
-            cell_update2d<T, POL, HIST>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y), f, x0 + k < a.nx);
+            cell_update2d<T, POL, HIST, false, false, LINE, LREC>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y),
+                                                                  f, x0 + k < a.nx, T(0), T(0), T(1), T(1), fl,
+                                                                  a.line_n);
 #pragma unroll
         for (int i = 0; i < 11; ++i) v[i][k] = f[i];
     }
@@ -594,12 +645,33 @@ __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const S
 
 // HIST: also record dE/deps of the design cells into a.hist (checkpointed
 // forward pass of the adjoint).  MU: permeability map a.mu (never with HIST).
-template <typename T, int POL, int VX, bool HIST = false, bool MU = false>
+// LINE: the layer follows the exact incident line a.line_tab.
+template <typename T, int POL, int VX, bool HIST = false, bool MU = false, bool LINE = false>
 __global__ void __launch_bounds__(256) k_step2d(StepArgs<T> a) {
-    static_assert(!(HIST && MU), "the design-region history assumes mu_r = 1");
+    static_assert(!(HIST && (MU || LINE)), "the design-region history assumes mu_r = 1 and no line");
     const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    step2d_cells<T, POL, VX, HIST, MU>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
+    step2d_cells<T, POL, VX, HIST, MU, LINE>(a, x0, y, step_const(a, step_time(a.t_base, a.t_off)));
+}
+
+// The exact incident line's own steps (one or two per launch, matching the
+// grid's launch): a single block walks the line's cells with the grid's
+// per-cell update, records each step's post-collision populations in slot
+// t & 1 of a.line_rec for the grid's launch that follows, and accumulates
+// the line's phasors.  a0 / a1: the arguments of the two steps (buffers
+// swapped); a barrier separates them (one workgroup: its release/acquire
+// at workgroup scope makes the first step's global writes visible).
+template <typename T, int POL>
+__global__ void __launch_bounds__(1024) k_line(StepArgs<T> a0, StepArgs<T> a1, int nsteps) {
+    for (int s = 0; s < nsteps; ++s) {
+        const StepArgs<T> &a = s == 0 ? a0 : a1;
+        const StepConst<T> st = step_const(a, step_time(a.t_base, a.t_off));
+        for (int u = threadIdx.x; u < a.line_n; u += blockDim.x) {
+            if (a.line_axis == 0) step2d_cells<T, POL, 1, false, false, false, true>(a, u, 0, st);
+            else step2d_cells<T, POL, 1, false, false, false, true>(a, 0, u, st);
+        }
+        if (s + 1 < nsteps) __syncthreads();   // a workgroup barrier orders the global writes too
+    }
 }
 
 // Batched persistent step: one launch advances many 2-D instances of
@@ -673,9 +745,16 @@ template <typename T, int N>
 __device__ inline void lds_store(T *p, const T (&i)[N]) { store_aligned<T, N>(p, i); }
 
 // MU: permeability map a.mu (never with HIST); mu and 1/mu of the thread's
-// own cells stay in registers like eps.
-template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false>
-__device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t) {
+// own cells stay in registers like eps.  LINE: exact incident line.
+// Line slab of the two-step kernel: the incident line's post-collision
+// populations of steps t and t+1 at the tile's coordinates along the line
+// (with the ring), staged in LDS by tiles that reach into the layer.
+template <int TX, int TY>
+__host__ __device__ constexpr int x2_line_n() { return (TX > TY ? TX : TY) + 2; }
+
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false>
+__device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t,
+                                      T *lslab = nullptr) {
     const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
     constexpr int VX = X2Lds<T, TX, TY>::VX;
     constexpr int TPR = TX / VX;             // segments per tile row
@@ -692,6 +771,9 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
     const bool layer_tile = a.src_on && ((a.W[0] && (x0 < a.W[0] || x0 + TX > a.nx - a.W[0])) ||
                                          (a.W[1] && (y0 < a.W[1] || y0 + TY > a.ny - a.W[1])));
     T ur[VX], ui[VX];
+    // slab coordinates: entry j of a slab row is coordinate u0 + j on the line
+    constexpr int NL = x2_line_n<TX, TY>();
+    const int lu0 = (a.line_axis == 0 ? x0 : y0) - 1;
 
     // step t on the thread's own segment
     {
@@ -700,6 +782,21 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         pull_row<T, VX>(a, x, yf, v, e);
 #pragma unroll
         for (int k = 0; k < VX; ++k) mp[k] = imp[k] = T(1);
+        // tiles whose cells or ring cells reach into the layer stage the
+        // line's populations of steps t and t+1 (after the own pulls were
+        // issued, so their latencies overlap)
+        const bool line_tile = a.src_on && ((a.W[0] && (x0 - 1 < a.W[0] || x0 + TX + 1 > a.nx - a.W[0])) ||
+                                            (a.W[1] && (y0 - 1 < a.W[1] || y0 + TY + 1 > a.ny - a.W[1])));
+        if (LINE && line_tile) {
+            const int ax = a.line_axis, na = a.line_n;
+            const int nu = (ax == 0 ? TX : TY) + 2;
+            for (int k = tid; k < 2 * 11 * nu; k += NT) {
+                const int j = k % nu, r = k / nu;           // r = step (0, 1) * 11 + plane
+                const int u = fold(lu0 + j, na, a.W[ax]);
+                lslab[r * NL + j] = a.line_tab[((int64_t)((t + r / 11) & 1) * 11 + r % 11) * na + u];
+            }
+            __syncthreads();
+        }
         if (MU) {
             const uint32_t row = (uint32_t)yf * (uint32_t)a.sy;
             if (x >= 0 && x + VX <= a.nx) load_aligned<T, VX>(mp, at(a.mu, row + (uint32_t)x));
@@ -729,8 +826,9 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             T f[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL, HIST, true, MU>(a, s0, xf, yf, e[k], ip[k], sg[k], f, x + k < a.nx && y < a.ny,
-                                                  ur[k], ui[k], mp[k], imp[k]);
+            cell_update2d<T, POL, HIST, true, MU, LINE>(a, s0, xf, yf, e[k], ip[k], sg[k], f,
+                                                        x + k < a.nx && y < a.ny, ur[k], ui[k], mp[k], imp[k],
+                                                        lslab + ((a.line_axis == 0 ? x + k : y) - lu0), NL);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
             zp[0][k] = f[8];
@@ -763,10 +861,13 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         for (int i = 0; i < 11; ++i) f[i] = v[i][0];
         if (MU) {
             const T m = *at(a.mu, (uint32_t)yf * (uint32_t)a.sy + (uint32_t)xf);
-            cell_update2d<T, POL, false, false, true>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf), f,
-                                                      false, T(0), T(0), m, recip(m));
+            cell_update2d<T, POL, false, false, true, LINE>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf),
+                                                            f, false, T(0), T(0), m, recip(m),
+                                                            lslab + ((a.line_axis == 0 ? rx : ry) - lu0), NL);
         } else {
-            cell_update2d<T, POL>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf), f, false);
+            cell_update2d<T, POL, false, false, false, LINE>(a, s0, xf, yf, e[0], recip(e[0]), sigma2d<T>(a, xf, yf),
+                                                             f, false, T(0), T(0), T(1), T(1),
+                                                             lslab + ((a.line_axis == 0 ? rx : ry) - lu0), NL);
         }
         if (r < TX) {
             L.ym[0][0][r] = f[2];
@@ -830,8 +931,9 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             f[8] = zp[0][k];
             f[9] = zp[1][k];
             f[10] = zp[2][k];
-            cell_update2d<T, POL, HIST, true, MU>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx, ur[k], ui[k],
-                                                  mp[k], imp[k]);
+            cell_update2d<T, POL, HIST, true, MU, LINE>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx, ur[k],
+                                                        ui[k], mp[k], imp[k],
+                                                        lslab + 11 * NL + ((a.line_axis == 0 ? x + k : y) - lu0), NL);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
         }
@@ -853,15 +955,16 @@ __device__ inline int xcd_tile(int b, int ntiles) {
 // One block per tile, a 1-D grid of tiles_x * tiles_y blocks.  The launch
 // bound asks for 4 waves per SIMD (at most 128 VGPRs).
 // HIST: also record dE/deps of the design cells (recompute of the adjoint).
-// MU: permeability map a.mu.
-template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false>
+// MU: permeability map a.mu.  LINE: exact incident line.
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false>
 __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
     k_step2d_x2(StepArgs<T> a) {
-    static_assert(!(HIST && MU), "the design-region history assumes mu_r = 1");
+    static_assert(!(HIST && (MU || LINE)), "the design-region history assumes mu_r = 1 and no line");
     __shared__ X2Lds<T, TX, TY> lds;
+    __shared__ T lslab[LINE ? 2 * 11 * x2_line_n<TX, TY>() : 1];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    step2d_x2_tile<T, POL, TX, TY, HIST, MU>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
-                                             step_time(a.t_base, a.t_off));
+    step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
+                                                   step_time(a.t_base, a.t_off), lslab);
 }
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).

@@ -75,6 +75,12 @@ struct lbm_em {
     void *mu = nullptr;                 // permeability map (2-D; 0 = conductor); NULL: mu_r = 1
     bool mu_user = false;               // mu holds a map set through set_permeability
     unsigned char *pec = nullptr;       // dense [y][x] conductor mask (TM); NULL: none
+    // exact incident line (2-D, incidence along x or y)
+    lbm_em *line = nullptr;             // the one-row (one-column) line run; NULL: off
+    int line_axis = 0;
+    void *line_tmp = nullptr;           // the line's middle state inside a two-step launch
+    void *line_tab = nullptr;           // its post-collision populations, slots t & 1
+    double *line_acc = nullptr;         // its phasors, line_n x 12
     int64_t t = 0;
     hipStream_t stream = nullptr;
     int vx = 1, bx = 128, by = 2;       // cells per thread along x, block shape
@@ -191,6 +197,11 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     a.win0 = h->win0;
     a.winlen = h->winlen;
     a.acc = h->acc;
+    if (h->line) {
+        a.line_tab = (const T *)h->line_tab;
+        a.line_axis = h->line_axis;
+        a.line_n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+    }
     return a;
 }
 
@@ -201,11 +212,17 @@ void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
     dim3 grid((unsigned)((gx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
               (unsigned)h->cfg.nz);
     const bool rec = a.hist != nullptr;
-    if (a.mu) {
-        if (rec) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
+    if (rec && (a.mu || a.line_tab)) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1 and no incident line");
+    if (a.mu && a.line_tab) {
+        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<T, TE, VX, false, true, true>), grid, block, 0, s, a);
+    } else if (a.mu) {
         if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, true>), grid, block, 0, s, a);
         else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE, VX, false, true>), grid, block, 0, s, a);
         else fail(LBM_EM_EUNSUPPORTED, "a permeability map needs a 2-D (TM/TE) handle");
+    } else if (a.line_tab) {
+        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<T, TE, VX, false, false, true>), grid, block, 0, s, a);
     } else if (h->cfg.pol == LBM_EM_TM) {
         if (rec) hipLaunchKernelGGL((k_step2d<T, TM, VX, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_step2d<T, TM, VX>), grid, block, 0, s, a);
@@ -237,8 +254,41 @@ void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t
     else if constexpr (sizeof(T) == 4) launch_step_vx<T, 4>(a, h, s);
 }
 
+// The incident line's steps for the grid launch that follows (nsteps = 1 or
+// 2 from step t_base + t_off): parity p -> p ^ 1 like the grid, through the
+// line's middle buffer when it takes two.
+template <typename T>
+void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s, int nsteps) {
+    const lbm_em *l = h->line;
+    StepArgs<T> a0 = make_args<T>(l, l->buf[parity], nsteps == 2 ? h->line_tmp : l->buf[parity ^ 1]);
+    StepArgs<T> a1 = make_args<T>(l, h->line_tmp, l->buf[parity ^ 1]);
+    for (StepArgs<T> *a : {&a0, &a1}) {
+        a->t_base = t_base;
+        a->dft_on = h->dft_set ? 1 : 0;
+        a->win0 = h->win0;
+        a->winlen = h->winlen;
+        a->line_rec = (T *)h->line_tab;
+        a->line_acc = h->line_acc;
+        a->line_axis = h->line_axis;
+        a->line_n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+    }
+    a0.t_off = t_off;
+    a1.t_off = t_off + 1;
+    if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_line<T, TM>), dim3(1), dim3(1024), 0, s, a0, a1, nsteps);
+    else hipLaunchKernelGGL((k_line<T, TE>), dim3(1), dim3(1024), 0, s, a0, a1, nsteps);
+    hip_check(hipGetLastError(), "k_line");
+}
+
+void launch_line(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s, int nsteps) {
+    if (h->cfg.precision == LBM_EM_FP32) launch_line_t<float>(h, parity, t_base, t_off, s, nsteps);
+    else launch_line_t<double>(h, parity, t_base, t_off, s, nsteps);
+}
+
+// One step.  dft = false (autotune timing, adjoint recompute): no DFT and
+// no incident-line step (the line's table is left as it is).
 void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
                  bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
+    if (h->line && dft) launch_line(h, parity, t_base, t_off, s, 1);
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
     if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
@@ -260,8 +310,12 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
     if (tx == TX && ty == TY) {                                                                              \
         if (a.hist)                                                                                          \
             hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
+        else if (a.mu && a.line_tab)                                                                         \
+            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, true, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
         else if (a.mu)                                                                                       \
             hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
+        else if (a.line_tab)                                                                                 \
+            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, false, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
         else                                                                                                 \
             hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a);  \
         return;                                                                                              \
@@ -336,7 +390,8 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
 
 void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
                   bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
-    if (h->mu && hist) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
+    if ((h->mu || h->line) && hist) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1 and no incident line");
+    if (h->line && dft) launch_line(h, parity, t_base, t_off, s, 2);
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
     if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
@@ -588,6 +643,7 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
         lbm_em *h = check_handle(hs[i]);
         if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "batched stepping supports 2-D (TM/TE) handles");
         if (h->mu) fail(LBM_EM_EUNSUPPORTED, "batched stepping needs mu_r = 1");
+        if (h->line) fail(LBM_EM_EUNSUPPORTED, "batched stepping does not run incident lines");
         if (h->cfg.pol != h0->cfg.pol || h->cfg.precision != h0->cfg.precision)
             fail(LBM_EM_EINVAL, "batched handles must share polarisation and precision");
         if (h->stream != h0->stream || h->dev != h0->dev) fail(LBM_EM_EINVAL, "batched handles must share stream and device");
@@ -716,9 +772,34 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
     }
 }
 
+// The incident line's phasors laid out like the contour accumulators (one
+// row of 12 per box node, then the probe), in a new device buffer.
+double *line_incident(lbm_em *h) {
+    const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+    std::vector<double> L((size_t)n * 12), out((size_t)(h->nnodes + 1) * 12);
+    hip_check(hipMemcpyAsync(L.data(), h->line_acc, L.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");
+    sync(h);
+    const Box &b = h->box;
+    for (int y = b.lo[1]; y <= b.hi[1]; ++y)
+        for (int x = b.lo[0]; x <= b.hi[0]; ++x) {
+            if (!on_box(b, 2, x, y, 0)) continue;
+            const int64_t node = box_node_index(b, 2, x, y, 0);
+            const int u = h->line_axis == 0 ? x : y;
+            std::memcpy(&out[(size_t)node * 12], &L[(size_t)u * 12], 12 * sizeof(double));
+        }
+    const int up = h->line_axis == 0 ? h->probe[0] : h->probe[1];
+    std::memcpy(&out[(size_t)h->nnodes * 12], &L[(size_t)up * 12], 12 * sizeof(double));
+    double *d = nullptr;
+    hip_check(hipMalloc(&d, out.size() * sizeof(double)), "hipMalloc");
+    hip_check(hipMemcpyAsync(d, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, h->stream), "H2D");
+    sync(h);
+    return d;
+}
+
 // Far-field combinations P (4 doubles per angle, device) for angles given
 // in radians; returns the incident amplitude used for normalisation.
-double farfield_P(lbm_em *h, lbm_em *inc, const double *theta_rad, const double *phi_rad, int n, double *d_P) {
+double farfield_P(lbm_em *h, const double *acc_inc, const double *theta_rad, const double *phi_rad, int n,
+                  double *d_P) {
     std::vector<double> ang(2 * (size_t)n);
     for (int i = 0; i < n; ++i) {
         ang[i] = theta_rad[i];
@@ -729,7 +810,7 @@ double farfield_P(lbm_em *h, lbm_em *inc, const double *theta_rad, const double 
     hip_check(hipMemcpyAsync(d_ang, ang.data(), ang.size() * sizeof(double), hipMemcpyHostToDevice, h->stream), "H2D");
     NtffArgs a{};
     a.acc = h->acc;
-    a.acc_inc = inc ? inc->acc : nullptr;
+    a.acc_inc = acc_inc;
     a.box = h->box;
     a.dim = h->dim;
     a.pol = h->cfg.pol;
@@ -749,9 +830,9 @@ double farfield_P(lbm_em *h, lbm_em *inc, const double *theta_rad, const double 
     hipLaunchKernelGGL(k_ntff, dim3(n), dim3(256), 0, h->stream, a);
     hip_check(hipGetLastError(), "k_ntff");
     double amp = h->pw.amplitude;
-    if (inc) {
+    if (acc_inc) {
         double pr[12];
-        hip_check(hipMemcpyAsync(pr, inc->acc + inc->nnodes * 12, sizeof pr, hipMemcpyDeviceToHost, h->stream), "D2H");
+        hip_check(hipMemcpyAsync(pr, acc_inc + h->nnodes * 12, sizeof pr, hipMemcpyDeviceToHost, h->stream), "D2H");
         sync(h);
         const double *v = h->cfg.pol == LBM_EM_TE ? pr + 6 : pr;
         const double *u = h->cfg.pol == LBM_EM_TE ? h->hhat : h->pw.ehat;
@@ -785,6 +866,11 @@ void reset_state(lbm_em *h) {
         hip_check(hipMemsetAsync(h->acc, 0, (size_t)(h->nnodes + 1) * 12 * sizeof(double), h->stream), "hipMemset dft");
     h->t = 0;
     h->cur = 0;
+    if (h->line) {
+        reset_state(h->line);
+        const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        hip_check(hipMemsetAsync(h->line_acc, 0, (size_t)n * 12 * sizeof(double), h->stream), "hipMemset line dft");
+    }
 }
 
 template <typename T>
@@ -842,6 +928,20 @@ void launch_adjoint(const lbm_em *h, const void *src, void *dst, int64_t t, cons
     fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
 
+void free_handle(lbm_em *h);
+
+// Remove the incident line (its run, table and phasors).
+void drop_line(lbm_em *h) {
+    if (!h->line) return;
+    free_handle(h->line);
+    h->line = nullptr;
+    hfree(h->line_tmp);
+    hfree(h->line_tab);
+    hfree(h->line_acc);
+    h->line_tmp = h->line_tab = nullptr;
+    h->line_acc = nullptr;
+}
+
 void free_handle(lbm_em *h) {
     if (!h) return;
     (void)hipSetDevice(h->dev);
@@ -853,6 +953,7 @@ void free_handle(lbm_em *h) {
     hfree(h->eps);
     hfree(h->mu);
     hfree(h->pec);
+    drop_line(h);
     hfree(h->acc);
     hfree(h->t_dev);
     hfree(h->ck);
@@ -1115,6 +1216,72 @@ lbm_em_status lbm_em_set_pec(lbm_em_handle hh, const uint8_t *mask, int32_t wher
     });
 }
 
+lbm_em_status lbm_em_set_incident_line(lbm_em_handle hh, int32_t enable) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "the incident line needs a 2-D (TM/TE) handle");
+        if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
+        if (h->adj_set) fail(LBM_EM_EUNSUPPORTED, "the adjoint uses the companion run, not an incident line");
+        select_device(h);
+        sync(h);
+        drop_line(h);
+        drop_graphs(h);
+        if (!enable) return;
+        if (!h->src_on) fail(LBM_EM_ESTATE, "set the source first");
+        if (h->t != 0) fail(LBM_EM_ESTATE, "set the incident line before stepping (or after a reset)");
+        const double *k = h->pw.khat;
+        int axis = -1;
+        if (std::fabs(std::fabs(k[0]) - 1.0) <= 1e-12 && std::fabs(k[1]) <= 1e-12) axis = 0;
+        else if (std::fabs(std::fabs(k[1]) - 1.0) <= 1e-12 && std::fabs(k[0]) <= 1e-12) axis = 1;
+        if (axis < 0) fail(LBM_EM_EINVAL, "the incident line needs incidence along +-x or +-y");
+        lbm_em_config lc = h->cfg;
+        lc.nx = axis == 0 ? h->cfg.nx : 1;
+        lc.ny = axis == 0 ? 1 : h->cfg.ny;
+        lc.absorb[0] = axis == 0 ? h->cfg.absorb[0] : 0;
+        lc.absorb[1] = axis == 0 ? 0 : h->cfg.absorb[1];
+        lc.absorb[2] = 0;
+        lc.stream = (void *)h->stream;
+        lbm_em *l = nullptr;
+        lbm_em_status st = lbm_em_create(&lc, &l);
+        if (st != LBM_EM_OK) fail(st, std::string("incident line: ") + g_last_error);
+        h->line = l;
+        h->line_axis = axis;
+        st = lbm_em_set_source(l, &h->pw);
+        if (st != LBM_EM_OK) {
+            const std::string msg = g_last_error;
+            drop_line(h);
+            fail(st, "incident line: " + msg);
+        }
+        try {
+            const int64_t n = axis == 0 ? h->cfg.nx : h->cfg.ny;
+            const size_t tab = (size_t)2 * 11 * n * h->elem;
+            hip_check(hipMalloc(&h->line_tmp, (size_t)l->plane * l->nplanes * l->elem), "hipMalloc line");
+            hip_check(hipMalloc(&h->line_tab, tab), "hipMalloc line");
+            hip_check(hipMalloc(&h->line_acc, (size_t)n * 12 * sizeof(double)), "hipMalloc line");
+            hip_check(hipMemsetAsync(h->line_tab, 0, tab, h->stream), "hipMemset line");
+            hip_check(hipMemsetAsync(h->line_acc, 0, (size_t)n * 12 * sizeof(double), h->stream), "hipMemset line");
+            sync(h);
+        } catch (...) {
+            drop_line(h);
+            throw;
+        }
+    });
+}
+
+lbm_em_status lbm_em_get_line_phasors(lbm_em_handle hh, double *out, int32_t *n) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!n) fail(LBM_EM_EINVAL, "null count");
+        if (!h->line) fail(LBM_EM_ESTATE, "no incident line");
+        *n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        if (!out) return;
+        select_device(h);
+        hip_check(hipMemcpyAsync(out, h->line_acc, (size_t)*n * 12 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                  "D2H");
+        sync(h);
+    });
+}
+
 lbm_em_status lbm_em_set_source(lbm_em_handle hh, const lbm_em_plane_wave *pw) {
     return guarded([&] {
         lbm_em *h = check_handle(hh);
@@ -1138,6 +1305,8 @@ lbm_em_status lbm_em_set_source(lbm_em_handle hh, const lbm_em_plane_wave *pw) {
         if (t_ramp > 1e7) fail(LBM_EM_EINVAL, "ramp longer than 1e7 steps");
         if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         select_device(h);
+        sync(h);
+        drop_line(h);       // a new source ends the incident line (set it again)
         // Tables, in one allocation: (cos, sin)(2 pi k / T) for k < T (FP64);
         // the ramp g(t) = sin^2(pi t / (2 t_ramp)) for t < t_ramp (FP64);
         // (cos, sin)(2 pi u_a) per column, row and slab, u_a = khat_a (a -
@@ -1220,6 +1389,10 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle hh, const int32_t lo[3], const int32
         const size_t bytes = (size_t)(h->nnodes + 1) * 12 * sizeof(double);
         hip_check(hipMalloc(&h->acc, bytes), "hipMalloc dft");
         hip_check(hipMemsetAsync(h->acc, 0, bytes, h->stream), "hipMemset dft");
+        if (h->line) {
+            const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+            hip_check(hipMemsetAsync(h->line_acc, 0, (size_t)n * 12 * sizeof(double), h->stream), "hipMemset line dft");
+        }
         h->dft_set = true;
         drop_graphs(h);
     });
@@ -1548,9 +1721,21 @@ lbm_em_status lbm_em_farfield(lbm_em_handle hh, lbm_em_handle inc, const double 
             th[i] = theta_deg[i] * M_PI / 180.0;
             ph[i] = phi_deg ? phi_deg[i] * M_PI / 180.0 : 0.0;
         }
-        double *d_out = nullptr;
+        double *d_out = nullptr, *d_line = nullptr;
         hip_check(hipMalloc(&d_out, (size_t)n_angles * 4 * sizeof(double)), "hipMalloc");
-        const double amp = farfield_P(h, inc, th.data(), ph.data(), n_angles, d_out);
+        const double *acc_inc = inc ? inc->acc : nullptr;
+        if (!inc && h->line) {
+            // the incident line's phasors at every contour node and the probe
+            try {
+                d_line = line_incident(h);
+            } catch (...) {
+                hfree(d_out);
+                throw;
+            }
+            acc_inc = d_line;
+        }
+        const double amp = farfield_P(h, acc_inc, th.data(), ph.data(), n_angles, d_out);
+        hfree(d_line);
         if (!(amp > 0.0)) {
             hfree(d_out);
             fail(LBM_EM_ESTATE, "incident amplitude at the probe node is zero (the wave has not arrived)");
@@ -1576,6 +1761,7 @@ lbm_em_status lbm_em_adjoint_setup(lbm_em_handle hh, lbm_em_handle inc, const do
         lbm_em *h = check_handle(hh);
         if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "the adjoint supports 2-D (TM/TE) handles");
         if (h->mu) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1");
+        if (h->line) fail(LBM_EM_EUNSUPPORTED, "the adjoint uses the companion run, not an incident line");
         if (!inc) fail(LBM_EM_EINVAL, "the objective needs the incident (eps = 1) companion handle");
         if (!theta_deg || n_angles < 1) fail(LBM_EM_EINVAL, "need at least one angle");
         if (!dlo || !dhi) fail(LBM_EM_EINVAL, "null design rectangle");
@@ -1637,7 +1823,7 @@ lbm_em_status lbm_em_forward_checkpointed(lbm_em_handle hh, int64_t n, double *J
         hfree(h->adj_P);
         h->adj_P = nullptr;
         hip_check(hipMalloc(&h->adj_P, (size_t)na * 4 * sizeof(double)), "hipMalloc");
-        const double amp = farfield_P(h, h->adj_inc, h->adj_theta.data(), nullptr, na, h->adj_P);
+        const double amp = farfield_P(h, h->adj_inc->acc, h->adj_theta.data(), nullptr, na, h->adj_P);
         if (!(amp > 0.0)) fail(LBM_EM_ESTATE, "incident amplitude at the probe node is zero (the wave has not arrived)");
         std::vector<double> P((size_t)na * 4);
         hip_check(hipMemcpyAsync(P.data(), h->adj_P, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");

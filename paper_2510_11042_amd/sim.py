@@ -122,6 +122,21 @@ class Simulation:
         self._pec_set = True
         self._has_mu = True
 
+    def set_incident_line(self, enable=True):
+        """Exact incident line for incidence along +-x or +-y (see
+        lbm_em_set_incident_line): call after set_source, before stepping;
+        farfield(incident=None) then uses the line instead of a companion."""
+        L.check(L.lib().lbm_em_set_incident_line(self._h, 1 if enable else 0))
+
+    def line_phasors(self):
+        """The incident line's phasors, (n, 6) complex (Ex, Ey, Ez, Hx, Hy, Hz)."""
+        n = C.c_int32()
+        L.check(L.lib().lbm_em_get_line_phasors(self._h, None, C.byref(n)))
+        out = np.zeros(n.value * 12)
+        L.check(L.lib().lbm_em_get_line_phasors(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+        out = out.reshape(-1, 12)
+        return out[:, 0::2] + 1j * out[:, 1::2]
+
     def set_source(self, lam, khat, ehat, amplitude=1.0, ramp_periods=3.0, center=None):
         pw = L.PlaneWave()
         pw.lam = float(lam)
@@ -276,7 +291,8 @@ class Simulation:
 
     def farfield(self, theta_deg, phi_deg=None, incident=None):
         """|S|^2 at angles measured from the incidence direction (2-D: in
-        the plane; 3-D: phi about khat from ehat)."""
+        the plane; 3-D: phi about khat from ehat).  incident: the companion
+        run; None uses the incident line if one is set."""
         th = np.ascontiguousarray(theta_deg, dtype=np.float64).ravel()
         ph = None if phi_deg is None else np.ascontiguousarray(
             np.broadcast_to(phi_deg, th.shape), dtype=np.float64)

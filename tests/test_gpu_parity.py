@@ -692,3 +692,181 @@ def test_pec_api_limits(gpu):
     step_many([a, b], 2)
     for h in (te, s3, a, b):
         h.close()
+
+
+def _line_case(nx, ny, theta, pol):
+    kh, eh = W.plane_wave_2d(theta, pol)
+    return np.round(kh, 15), eh
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("theta,pol", [(0.0, "TM"), (90.0, "TE"), (180.0, "TE")])
+def test_incident_line_fields_match_oracle(gpu, prec, theta, pol):
+    """Exact incident line (layer rule that damps only the scattered part)
+    on a ragged 83 x 61 grid absorbing on both axes with dielectric and
+    magnetic blobs: fields every few steps and the line's phasors against
+    the oracle's line, default two-step launches, eager and graph steps."""
+    nx, ny, Wd = 83, 61, 10
+    eps, mu = _mu_maps(nx, ny, Wd)
+    kh, eh = _line_case(nx, ny, theta, pol)
+    axis = 0 if abs(kh[0]) == 1.0 else 1
+    say("line", prec, theta, pol)
+    s, o = make_pair(gpu, nx, ny, 1, pol, prec, (Wd, Wd, 0), eps, 12.0, kh, eh, ramp=1.0)
+    s.set_permeability(mu)
+    o.set_mu(mu)
+    lo, hi = (20, 15, 0), (62, 45, 0)
+    s.set_ntff(lo, hi, 150, 36)
+    cells = np.arange(nx * ny)
+    o.set_dft(cells, 150, 36)
+    s.set_incident_line(True)
+    o.set_incident_line(axis)
+    for n in (1, 9, 190):
+        s.step(n)
+        o.step(n)
+        compare_fields(s, o, prec, f"line t={o.t}")
+    Lg, Lo = s.line_phasors(), o.get_line_dft()
+    err = np.abs(Lg - Lo).max() / np.abs(Lo).max()
+    say("line phasors err", err)
+    assert err <= (1e-11 if prec == "fp64" else 1e-4)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_incident_line_reproduced_exactly(gpu, prec, pol):
+    """A background-only grid with the incident line is the line at every
+    row, bit for bit: its fields do not depend on y and its contour phasors
+    equal the line's phasors at the node coordinates (one and two steps per
+    launch)."""
+    nx, ny = 150, 90
+    kh, eh = W.plane_wave_2d(0.0, pol)
+    for fuse in (1, 2):
+        s = gpu(nx, ny, 1, pol=pol, precision=prec, absorb=(20, 12, 0), sigma_max=W.SIGMA_MAX)
+        s.set_source(16.0, kh, eh, 1.0, 1.0)
+        s.set_ntff((30, 25, 0), (110, 60, 0), 200, 48)
+        s.set_incident_line(True)
+        s.set_fusion(fuse)
+        s.step(249)
+        E, H = s.fields()
+        assert np.abs(E).max() > 0.1
+        assert np.array_equal(E, np.broadcast_to(E[:, :1], E.shape))
+        assert np.array_equal(H, np.broadcast_to(H[:, :1], H.shape))
+        X, probe = s.phasors()
+        L = s.line_phasors()
+        nodes = [(x, y) for y in range(25, 61) for x in range(30, 111)
+                 if x in (30, 110) or y in (25, 60)]
+        assert np.array_equal(X, L[[x for x, _ in nodes]])
+        assert np.array_equal(probe, L[(30 + 110) // 2])
+        s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_incident_line_two_steps_bit_identical(gpu, prec):
+    """With the incident line, two steps per launch (every tile) reproduce
+    one step per launch bit for bit, fields and phasors."""
+    nx, ny = 203, 77
+    rng = np.random.default_rng(9)
+    eps = 1.0 + (rng.random((1, ny, nx)) < 0.2) * rng.uniform(0.2, 3.0, (1, ny, nx))
+    eps[:, :, :12] = 1.0
+    eps[:, :, -12:] = 1.0
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    runs = []
+    for fuse, tile in [(1, (0, 0))] + [(2, t) for t in X2_TILES[prec]]:
+        s = gpu(nx, ny, 1, pol="TM", precision=prec, absorb=(11, 9, 0), sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(eps)
+        s.set_source(10.0, kh, eh, 1.0, 1.0)
+        s.set_ntff((60, 20, 0), (140, 56, 0), 100, 30)
+        s.set_incident_line(True)
+        s.set_fusion(fuse, tile)
+        for n in (3, 131, 1):
+            s.step(n)
+        runs.append((s.fields(), s.phasors(), s.line_phasors()))
+        say("line fusion", prec, fuse, tile, s.t)
+        s.close()
+    (E1, H1), (X1, p1), L1 = runs[0]
+    for (E2, H2), (X2, p2), L2 in runs[1:]:
+        assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
+        assert np.array_equal(X1, X2) and np.array_equal(p1, p2) and np.array_equal(L1, L2)
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_incident_line_cylinder_intensity(gpu, pol):
+    """|S|^2 with the incident line as the incident field (no companion run):
+    against the oracle's line-based intensity (FP64 1e-10, FP32 1e-3) and
+    against the GPU companion-based intensity (2e-4: the two differ only in
+    how the layers force the incident wave)."""
+    case = W.cylinder_case(2.25, pol, n=192, a=10.5, lam=32.0, W=32, steps=2400, half=19.5)
+    kh, eh = W.plane_wave_2d(0.0, pol)
+    th = np.arange(0, 360, 1.0)
+    o = Oracle(case.nx, case.ny, 1, case.absorb, W.SIGMA_MAX)
+    o.set_eps(case.eps)
+    o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    nodes = ntff.box_nodes(case.box_lo, case.box_hi)
+    pr = run.probe_node(case.box_lo, case.box_hi)
+    cells = np.concatenate([ntff.linear_index(nodes, (case.nx, case.ny)),
+                            ntff.linear_index(np.array([pr]), (case.nx, case.ny))])
+    o.set_dft(cells, *case.window)
+    o.set_incident_line(0)
+    o.step(case.steps)
+    X, Lx = o.get_dft(), o.get_line_dft()
+    S_o = run.intensity_2d(case, {"nodes": nodes, "phasors": X[:-1], "probe": X[-1]},
+                           {"phasors": Lx[nodes[:, 0]], "probe": Lx[pr[0]]}, th)
+    for prec, stol in (("fp64", 1e-10), ("fp32", 1e-3)):
+        s = gpu(case.nx, case.ny, 1, pol=pol, precision=prec, absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(case.eps)
+        s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+        s.set_incident_line(True)
+        s.step(case.steps)
+        S_g = s.farfield(th)
+        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
+        say(pol, prec, "line |S|^2 vs oracle", serr)
+        assert serr <= stol
+        if prec == "fp32":
+            tot = _gpu_case(gpu, case, prec)
+            inc = _gpu_case(gpu, W.vacuum_companion(case), prec)
+            S_c = tot.farfield(th, incident=inc)
+            d = np.sqrt(np.mean((S_g - S_c) ** 2)) / S_c.max()
+            say(pol, "line vs companion", d)
+            assert d < 2e-4
+        s.close()
+
+
+def test_incident_line_api_limits(gpu):
+    """The line needs a 2-D handle, a source along an axis and t = 0; a new
+    source removes it; batches and the adjoint refuse a handle with one."""
+    from paper_2510_11042_amd import LbmEmError, step_many
+
+    n = 64
+    s = gpu(n, n, 1, pol="TM", precision="fp32", absorb=(12, 12, 0), sigma_max=W.SIGMA_MAX)
+    with pytest.raises(LbmEmError):
+        s.set_incident_line(True)                    # no source yet
+    kh, eh = W.plane_wave_2d(30.0, "TM")
+    s.set_source(16.0, kh, eh, 1.0, 1.0)
+    with pytest.raises(LbmEmError):
+        s.set_incident_line(True)                    # oblique
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    s.set_source(16.0, kh, eh, 1.0, 1.0)
+    s.set_incident_line(True)
+    other = gpu(n, n, 1, pol="TM", precision="fp32", absorb=(12, 12, 0), sigma_max=W.SIGMA_MAX)
+    other.set_source(16.0, kh, eh, 1.0, 1.0)
+    with pytest.raises(LbmEmError):
+        step_many([s, other], 2)
+    s.set_ntff((20, 20, 0), (43, 43, 0), 48, 48)
+    with pytest.raises(LbmEmError):
+        s.adjoint_setup(other, [0.0], (28, 28), (35, 35))
+    s.step(3)
+    with pytest.raises(LbmEmError):
+        s.set_incident_line(True)                    # t > 0
+    s.set_source(16.0, kh, eh, 1.0, 1.0)             # removes the line
+    with pytest.raises(LbmEmError):
+        s.line_phasors()
+    s.reset()
+    s.set_incident_line(True)
+    s.step(2)
+    s3 = gpu(8, 8, 8, pol="3D", precision="fp32", absorb=(0, 0, 0), sigma_max=W.SIGMA_MAX)
+    s3.set_source(4.0, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+    with pytest.raises(LbmEmError):
+        s3.set_incident_line(True)
+    for h in (s, other, s3):
+        h.close()
