@@ -100,6 +100,9 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { typedef float2 type; };
 template <> struct Cplx<double> { typedef double2 type; };
 
+// Steps of the incident line kept in its table: one captured graph chunk.
+constexpr int kLineSlots = 64;
+
 template <typename T>
 struct StepArgs {
     int nx, ny, nz;
@@ -135,8 +138,8 @@ struct StepArgs {
     int dlo[2], dhi[2];
     int64_t hist_t0;
     // exact incident line (2-D, incidence along axis line_axis, line_n cells
-    // on it): post-collision populations of the line at step t in slot t & 1
-    // (2 slots x 11 planes x line_n).  The grid's kernels read line_tab; the
+    // on it): post-collision populations of the line at step t in slot
+    // t mod kLineSlots (kLineSlots x 11 planes x line_n).  The grid's kernels read line_tab; the
     // line's own kernel writes line_rec and its phasors line_acc (line_n x 12).
     const T *line_tab;
     T *line_rec;
@@ -493,7 +496,7 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
     }
     collide2d<T, POL>(F, f);
     if (LREC) {
-        T *r = a.line_rec + (int64_t)(t & 1) * 11 * a.line_n + (a.line_axis == 0 ? x : y);
+        T *r = a.line_rec + (int64_t)(t & (kLineSlots - 1)) * 11 * a.line_n + (a.line_axis == 0 ? x : y);
 #pragma unroll
         for (int i = 0; i < 11; ++i) r[(int64_t)i * a.line_n] = f[i];
     }
@@ -628,7 +631,7 @@ __device__ inline void step2d_cells(const StepArgs<T> &a, int x0, int y, const S
 #pragma unroll
         for (int i = 0; i < 11; ++i) f[i] = v[i][k];
         const T *fl = nullptr;
-        if (LINE) fl = a.line_tab + (int64_t)(st.t & 1) * 11 * a.line_n + (a.line_axis == 0 ? x : y);
+        if (LINE) fl = a.line_tab + (int64_t)(st.t & (kLineSlots - 1)) * 11 * a.line_n + (a.line_axis == 0 ? x : y);
         if (MU)
             cell_update2d<T, POL, false, false, true, LINE, LREC>(a, st, x, y, e[k], recip(e[k]), sigma2d<T>(a, x, y),
                                                                   f, x0 + k < a.nx, T(0), T(0), m[k], recip(m[k]), fl,
@@ -672,6 +675,64 @@ __global__ void __launch_bounds__(1024) k_line(StepArgs<T> a0, StepArgs<T> a1, i
         }
         if (s + 1 < nsteps) __syncthreads();   // a workgroup barrier orders the global writes too
     }
+}
+
+// The same line steps with the line's state held in LDS for a whole run of
+// nsteps (up to one graph chunk): one block, at most 2 * 1024 cells; the
+// state is read from a.src once and written to dst at the end (dst may be
+// a.src).  Pulls follow the grid's rules: on the line axis from the
+// neighbours (clamped on an absorbing axis, wrapped on a periodic one), the
+// movers of the other axis (a single periodic cell) from the cell itself.
+template <typename T, int POL>
+__global__ void __launch_bounds__(1024) k_line_lds(StepArgs<T> a, T *dst, int nsteps) {
+    extern __shared__ unsigned char line_raw[];
+    T *S = reinterpret_cast<T *>(line_raw);     // 11 planes x n
+    const int n = a.line_n, ax = a.line_axis, NT = blockDim.x, tid = threadIdx.x;
+    const int64_t P = a.plane;
+    const int64_t cstride = ax == 0 ? 1 : a.sy;  // the line's cells in its own layout
+    const int Wl = a.W[ax];
+    for (int k = tid; k < 11 * n; k += NT) S[k] = a.src[(k / n) * P + (k % n) * cstride];
+    __syncthreads();
+    const int64_t t0 = step_time(a.t_base, a.t_off);
+    for (int s = 0; s < nsteps; ++s) {
+        const StepConst<T> st = step_const(a, t0 + s);
+        T out[2][11];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int u = tid + c * NT;
+            if (u >= n) continue;
+            const int lo = pull_lo(u, n, Wl), hi = pull_hi(u, n, Wl);
+            T f[11];
+#pragma unroll
+            for (int i = 0; i < 11; ++i) f[i] = S[i * n + u];
+            if (ax == 0) {            // +x movers from u - 1, -x movers from u + 1
+                f[0] = S[0 * n + lo];
+                f[4] = S[4 * n + lo];
+                f[1] = S[1 * n + hi];
+                f[5] = S[5 * n + hi];
+            } else {                  // +y movers from u - 1, -y movers from u + 1
+                f[2] = S[2 * n + lo];
+                f[6] = S[6 * n + lo];
+                f[3] = S[3 * n + hi];
+                f[7] = S[7 * n + hi];
+            }
+            const int x = ax == 0 ? u : 0, y = ax == 0 ? 0 : u;
+            cell_update2d<T, POL, false, false, false, false, true>(a, st, x, y, T(1), recip(T(1)),
+                                                                    sigma2d<T>(a, x, y), f, true);
+#pragma unroll
+            for (int i = 0; i < 11; ++i) out[c][i] = f[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int u = tid + c * NT;
+            if (u >= n) continue;
+#pragma unroll
+            for (int i = 0; i < 11; ++i) S[i * n + u] = out[c][i];
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < 11 * n; k += NT) dst[(k / n) * P + (k % n) * cstride] = S[k];
 }
 
 // Batched persistent step: one launch advances many 2-D instances of
@@ -793,7 +854,7 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             for (int k = tid; k < 2 * 11 * nu; k += NT) {
                 const int j = k % nu, r = k / nu;           // r = step (0, 1) * 11 + plane
                 const int u = fold(lu0 + j, na, a.W[ax]);
-                lslab[r * NL + j] = a.line_tab[((int64_t)((t + r / 11) & 1) * 11 + r % 11) * na + u];
+                lslab[r * NL + j] = a.line_tab[((int64_t)((t + r / 11) & (kLineSlots - 1)) * 11 + r % 11) * na + u];
             }
             __syncthreads();
         }

@@ -54,6 +54,7 @@ lbm_em_status guarded(F &&f) {
 }
 
 constexpr int kGraphChunk = 64;   // steps per captured graph
+static_assert(kGraphChunk == kLineSlots, "the incident line's table holds one graph chunk");
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -254,12 +255,42 @@ void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t
     else if constexpr (sizeof(T) == 4) launch_step_vx<T, 4>(a, h, s);
 }
 
-// The incident line's steps for the grid launch that follows (nsteps = 1 or
-// 2 from step t_base + t_off): parity p -> p ^ 1 like the grid, through the
-// line's middle buffer when it takes two.
+// Largest line (in cells) whose state the LDS kernel holds: 64 KB of LDS
+// and two cells per thread.
+bool line_in_lds(const lbm_em *h) {
+    const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+    return n <= 2048 && 11 * n * (int64_t)h->elem <= 65536;
+}
+
+// The incident line's steps for the grid launches that follow: nsteps from
+// step t_base + t_off, leaving the line at parity p ^ 1 (one grid launch
+// follows) or p (a graph chunk, an even number of launches: flip = false).
+// Lines that fit in LDS run all steps in one block with the state in LDS;
+// longer ones take at most two steps per launch through global memory and
+// the line's middle buffer.
 template <typename T>
-void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s, int nsteps) {
+void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s, int nsteps,
+                   bool flip = true) {
     const lbm_em *l = h->line;
+    if (line_in_lds(h)) {
+        StepArgs<T> a = make_args<T>(l, l->buf[parity], nullptr);
+        a.t_base = t_base;
+        a.t_off = t_off;
+        a.dft_on = h->dft_set ? 1 : 0;
+        a.win0 = h->win0;
+        a.winlen = h->winlen;
+        a.line_rec = (T *)h->line_tab;
+        a.line_acc = h->line_acc;
+        a.line_axis = h->line_axis;
+        a.line_n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        T *dst = (T *)l->buf[flip ? parity ^ 1 : parity];
+        const size_t lds = (size_t)11 * a.line_n * sizeof(T);
+        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_line_lds<T, TM>), dim3(1), dim3(1024), lds, s, a, dst, nsteps);
+        else hipLaunchKernelGGL((k_line_lds<T, TE>), dim3(1), dim3(1024), lds, s, a, dst, nsteps);
+        hip_check(hipGetLastError(), "k_line_lds");
+        return;
+    }
+    if (nsteps > 2 || !flip) fail(LBM_EM_EINVAL, "internal: global-memory line steps are per launch");
     StepArgs<T> a0 = make_args<T>(l, l->buf[parity], nsteps == 2 ? h->line_tmp : l->buf[parity ^ 1]);
     StepArgs<T> a1 = make_args<T>(l, h->line_tmp, l->buf[parity ^ 1]);
     for (StepArgs<T> *a : {&a0, &a1}) {
@@ -279,16 +310,18 @@ void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t
     hip_check(hipGetLastError(), "k_line");
 }
 
-void launch_line(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s, int nsteps) {
-    if (h->cfg.precision == LBM_EM_FP32) launch_line_t<float>(h, parity, t_base, t_off, s, nsteps);
-    else launch_line_t<double>(h, parity, t_base, t_off, s, nsteps);
+void launch_line(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s, int nsteps,
+                 bool flip = true) {
+    if (h->cfg.precision == LBM_EM_FP32) launch_line_t<float>(h, parity, t_base, t_off, s, nsteps, flip);
+    else launch_line_t<double>(h, parity, t_base, t_off, s, nsteps, flip);
 }
 
 // One step.  dft = false (autotune timing, adjoint recompute): no DFT and
-// no incident-line step (the line's table is left as it is).
+// no incident-line step (the line's table is left as it is).  line = false:
+// the caller has already advanced the incident line over these steps.
 void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
-                 bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
-    if (h->line && dft) launch_line(h, parity, t_base, t_off, s, 1);
+                 bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0, bool line = true) {
+    if (h->line && dft && line) launch_line(h, parity, t_base, t_off, s, 1);
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
     if (h->cfg.precision == LBM_EM_FP32) launch_step_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
@@ -389,9 +422,9 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
 }
 
 void launch_step2(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_off, hipStream_t s,
-                  bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0) {
+                  bool dft = true, void *hist = nullptr, int64_t hist_t0 = 0, bool line = true) {
     if ((h->mu || h->line) && hist) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1 and no incident line");
-    if (h->line && dft) launch_line(h, parity, t_base, t_off, s, 2);
+    if (h->line && dft && line) launch_line(h, parity, t_base, t_off, s, 2);
     const void *src = h->buf[parity];
     void *dst = h->buf[parity ^ 1];
     if (h->cfg.precision == LBM_EM_FP32) launch_step2_t<float>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
@@ -435,14 +468,17 @@ hipGraphExec_t build_graph(lbm_em *h, int p) {
         hip_check(e, "hipStreamBeginCapture");
     }
     int par = p;
+    // an incident line held in LDS takes the whole chunk in one launch up front
+    const bool line_chunk = h->line && line_in_lds(h);
+    if (line_chunk) launch_line(h, p, h->t_dev, 0, cs, kGraphChunk, false);
     if (h->fuse == 2) {
         for (int k = 0; k < kGraphChunk; k += 2) {
-            launch_step2(h, par, h->t_dev, k, cs);
+            launch_step2(h, par, h->t_dev, k, cs, true, nullptr, 0, !line_chunk);
             par ^= 1;
         }
     } else {
         for (int k = 0; k < kGraphChunk; ++k) {
-            launch_step(h, par, h->t_dev, k, cs);
+            launch_step(h, par, h->t_dev, k, cs, true, nullptr, 0, !line_chunk);
             par ^= 1;
         }
     }
@@ -1254,7 +1290,7 @@ lbm_em_status lbm_em_set_incident_line(lbm_em_handle hh, int32_t enable) {
         }
         try {
             const int64_t n = axis == 0 ? h->cfg.nx : h->cfg.ny;
-            const size_t tab = (size_t)2 * 11 * n * h->elem;
+            const size_t tab = (size_t)kLineSlots * 11 * n * h->elem;
             hip_check(hipMalloc(&h->line_tmp, (size_t)l->plane * l->nplanes * l->elem), "hipMalloc line");
             hip_check(hipMalloc(&h->line_tab, tab), "hipMalloc line");
             hip_check(hipMalloc(&h->line_acc, (size_t)n * 12 * sizeof(double)), "hipMalloc line");

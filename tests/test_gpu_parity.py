@@ -870,3 +870,25 @@ def test_incident_line_api_limits(gpu):
         s3.set_incident_line(True)
     for h in (s, other, s3):
         h.close()
+
+
+@pytest.mark.parametrize("prec,nx", [("fp64", 800), ("fp32", 1600)])
+def test_incident_line_long_line_matches_oracle(gpu, prec, nx):
+    """A line too long for the LDS-resident line kernel (FP64 beyond 744
+    cells, FP32 beyond 1489) takes the global-memory path, one or two steps
+    per grid launch: fields against the oracle, eager steps and graph
+    chunks, two steps per launch."""
+    ny, Wd = 24, 6
+    y, x = np.mgrid[0:ny, 0:nx]
+    eps = np.ones((1, ny, nx))
+    eps[0][((x - nx / 2) ** 2 + (y - ny / 2) ** 2) < 8 ** 2] = 2.5
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    say("long line", prec, nx)
+    s, o = make_pair(gpu, nx, ny, 1, "TM", prec, (20, Wd, 0), eps, 12.0, kh, eh, ramp=1.0)
+    s.set_incident_line(True)
+    o.set_incident_line(0)
+    for n in (1, 9, 140):
+        s.step(n)
+        o.step(n)
+        compare_fields(s, o, prec, f"long line t={o.t}")
+    s.close()
