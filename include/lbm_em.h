@@ -42,7 +42,7 @@ typedef enum {
     LBM_EM_ENOMEM = -2,       /* device allocation failed                         */
     LBM_EM_EDEVICE = -3,      /* no HIP device or a HIP runtime error             */
     LBM_EM_ESTATE = -4,       /* call not valid in the handle's current state     */
-    LBM_EM_EUNSUPPORTED = -5  /* valid request this build does not implement      */
+    LBM_EM_EUNSUPPORTED = -5  /* valid request the library does not implement     */
 } lbm_em_status;
 
 typedef struct lbm_em *lbm_em_handle;

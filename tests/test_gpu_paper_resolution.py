@@ -15,7 +15,7 @@ Measured here (FP32) vs the paper's value:
   cylinder eps 2, a/lambda = 10    2.6e-3   (1.3e-3)
   cylinder a/lambda = 1, eps 5     1.5e-3   (1.0e-3)
   cylinder a/lambda = 1, eps 10    2.5e-3   (2.3e-3)
-  cylinder a/lambda = 1, eps 20    2.5e-2   (6.6e-3)  -- see the design doc
+  cylinder a/lambda = 1, eps 20    2.5e-2   (6.6e-3)  -- converged; the staircase interface at 50 cells per interior wavelength
   sphere eps 2, a/lambda = 1       0.9 / 0.9 / 1.4e-3 at phi 0/45/90
                                    (1.9 / 2.0 / 1.8e-3)
   PEC cylinder, a/lambda = 0.1     1.8e-2   (1.5e-2)   min/max 0.411/1.03  (0.428/1.05)
