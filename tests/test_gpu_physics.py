@@ -86,13 +86,16 @@ def test_cylinder_1024_vs_mie(P, pol):
         s.close()
 
 
-def test_sphere_384_vs_mie(P):
-    """384^3 sphere, x = 6 at lambda = 24, eps 2.25, W = 24, 4000 steps, FP32,
-    k along +z, E along +x; |S(theta, phi)|^2 in the planes phi = 0, 45, 90."""
-    case = W.sphere_case(n=384)
+@pytest.mark.parametrize("n", [384, 512])
+def test_sphere_vs_mie(P, n):
+    """384^3 and 512^3 sphere, x = 6 at lambda = 24, eps 2.25, W = 24, 4000
+    steps, FP32, k along +z, E along +x; |S(theta, phi)|^2 in the planes
+    phi = 0, 45, 90."""
+    case = W.sphere_case(n=n)
+    say("sphere", n)
     sims = []
     for e in (np.ones(1), case.eps):
-        s = P.Simulation(384, 384, 384, pol="3D", precision="fp32", absorb=(case.W,) * 3,
+        s = P.Simulation(n, n, n, pol="3D", precision="fp32", absorb=(case.W,) * 3,
                          sigma_max=W.SIGMA_MAX)
         if e.size > 1:
             s.set_permittivity(e)
@@ -109,7 +112,9 @@ def test_sphere_384_vs_mie(P):
         ref = mie.sphere_S2(th, phi, k * aeq, 1.5)
         e = nrms(S, ref)
         say("sphere phi", phi, "nRMS vs Mie(a_eq)", e, "max", S.max(), ref.max(), "a_eq", aeq)
-        assert e < 0.02     # measured 1.1-1.2 % at lambda_eps = 16 cells
+        assert e < 0.02     # measured 1.1-1.2 % at lambda_eps = 16 cells (384^3)
+    for s in sims:
+        s.close()
 
 
 @pytest.mark.parametrize("theta,pol", [(0.0, "TM"), (30.0, "TM"), (0.0, "TE"), (30.0, "TE")])
