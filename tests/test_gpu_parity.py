@@ -892,3 +892,47 @@ def test_incident_line_long_line_matches_oracle(gpu, prec, nx):
         o.step(n)
         compare_fields(s, o, prec, f"long line t={o.t}")
     s.close()
+
+
+def test_edge_cases_and_errors(gpu):
+    """Degenerate and invalid inputs: zero steps, negative steps, a 1 x 1
+    periodic grid, empty or misplaced DFT windows and contours, the far field
+    before its window ends, invalid permittivities."""
+    from paper_2510_11042_amd import LbmEmError
+
+    n = 48
+    kh, eh = W.plane_wave_2d(0.0, "TM")
+    s = gpu(n, n, 1, pol="TM", precision="fp32", absorb=(8, 8, 0), sigma_max=W.SIGMA_MAX)
+    s.set_source(12.0, kh, eh, 1.0, 1.0)
+    s.step(30)
+    E0, H0 = s.fields()
+    s.step(0)                                           # a no-op
+    assert s.t == 30
+    E1, H1 = s.fields()
+    assert np.array_equal(E0, E1) and np.array_equal(H0, H1)
+    with pytest.raises(LbmEmError):
+        s.step(-1)
+    with pytest.raises(LbmEmError):
+        s.set_ntff((10, 10, 0), (30, 30, 0), 40, 0)     # empty window
+    with pytest.raises(LbmEmError):
+        s.set_ntff((0, 10, 0), (30, 30, 0), 40, 36)     # box touches the grid edge
+    with pytest.raises(LbmEmError):
+        s.set_ntff((10, 10, 0), (11, 30, 0), 40, 36)    # thinner than 3 nodes
+    s.set_ntff((10, 10, 0), (37, 37, 0), 40, 36)
+    with pytest.raises(LbmEmError):
+        s.farfield([0.0, 90.0])                         # window not completed
+    for bad in (0.5, np.nan, np.inf):
+        eps = np.ones((1, n, n))
+        eps[0, 5, 5] = bad
+        with pytest.raises(LbmEmError):
+            s.set_permittivity(eps)
+    s.step(50)
+    S = s.farfield([0.0, 90.0])                         # no incident: normalised by the amplitude
+    assert np.all(np.isfinite(S))
+    s.close()
+    # a single periodic cell, no source: nothing moves, nothing is created
+    one = gpu(1, 1, 1, pol="TE", precision="fp64", absorb=(0, 0, 0), sigma_max=W.SIGMA_MAX)
+    one.step(65)
+    E, H = one.fields()
+    assert one.t == 65 and not np.any(E) and not np.any(H)
+    one.close()
