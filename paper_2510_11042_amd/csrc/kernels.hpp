@@ -849,12 +849,25 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         const bool line_tile = a.src_on && ((a.W[0] && (x0 - 1 < a.W[0] || x0 + TX + 1 > a.nx - a.W[0])) ||
                                             (a.W[1] && (y0 - 1 < a.W[1] || y0 + TY + 1 > a.ny - a.W[1])));
         if (LINE && line_tile) {
+            // a fixed number of loads per thread, all in flight before the
+            // first LDS store (rows past the tile's extent along a y line
+            // are loaded too, folded into the grid, and never read)
             const int ax = a.line_axis, na = a.line_n;
-            const int nu = (ax == 0 ? TX : TY) + 2;
-            for (int k = tid; k < 2 * 11 * nu; k += NT) {
-                const int j = k % nu, r = k / nu;           // r = step (0, 1) * 11 + plane
-                const int u = fold(lu0 + j, na, a.W[ax]);
-                lslab[r * NL + j] = a.line_tab[((int64_t)((t + r / 11) & (kLineSlots - 1)) * 11 + r % 11) * na + u];
+            constexpr int NLOAD = 2 * 11 * NL, J = (NLOAD + NT - 1) / NT;
+            T lv[J];
+#pragma unroll
+            for (int q = 0; q < J; ++q) {
+                const int k = tid + q * NT;
+                if (k < NLOAD) {
+                    const int j = k % NL, r = k / NL;       // r = step (0, 1) * 11 + plane
+                    const int u = fold(lu0 + j, na, a.W[ax]);
+                    lv[q] = a.line_tab[((int64_t)((t + r / 11) & (kLineSlots - 1)) * 11 + r % 11) * na + u];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < J; ++q) {
+                const int k = tid + q * NT;
+                if (k < NLOAD) lslab[k] = lv[q];
             }
             __syncthreads();
         }
