@@ -360,9 +360,11 @@ void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
 }
 
 // 3-D two-step tiles (one cell per thread; the LDS holds two planes of the
-// tile's x/y movers: 136 KB for 64 x 16 FP32 and 32 x 16 FP64).
-#define LBM_X3_TILES_F32(M) M(64, 16) M(64, 8) M(32, 16)
-#define LBM_X3_TILES_F64(M) M(32, 16) M(32, 8) M(16, 16)
+// tile's x/y movers: 136 KB for 64 x 16 FP32 and 32 x 16 FP64, 148 KB for
+// 256 x 4 FP32 and 128 x 4 FP64).  Wide tiles spend fewer 128-byte lines on
+// the ring columns.
+#define LBM_X3_TILES_F32(M) M(64, 16) M(64, 8) M(32, 16) M(128, 8) M(256, 4)
+#define LBM_X3_TILES_F64(M) M(32, 16) M(32, 8) M(16, 16) M(64, 8) M(128, 4)
 
 // z chunk of the 3-D two-step kernel: each block marches zc planes plus two
 // extra ones; pick the chunk count that minimises rounds x (zc + 2).
@@ -1126,8 +1128,9 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
                 h->fty = 16;
             } else {
                 h->fuse = 2;      // z march, one-plane lag (k_step3d_x2)
-                h->ftx = c.precision == LBM_EM_FP32 ? 64 : 32;
-                h->fty = 16;
+                // wide tiles: fewer 128-byte lines spent on the ring columns
+                h->ftx = 128;
+                h->fty = c.precision == LBM_EM_FP32 ? 8 : 4;
             }
             h->sy = round_up(c.nx, 64);
             h->sz = h->sy * c.ny;
@@ -1522,8 +1525,8 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
             if (!fused_tile_ok(h->dim, h->cfg.precision, tile_x, tile_y))
                 fail(LBM_EM_EINVAL,
-                     h->dim == 3 ? (h->cfg.precision == LBM_EM_FP32 ? "3-D FP32 two-step tile must be 64x16, 64x8 or 32x16"
-                                                                    : "3-D FP64 two-step tile must be 32x16, 32x8 or 16x16")
+                     h->dim == 3 ? (h->cfg.precision == LBM_EM_FP32 ? "3-D FP32 two-step tile must be 64x16, 64x8, 32x16, 128x8 or 256x4"
+                                                                    : "3-D FP64 two-step tile must be 32x16, 32x8, 16x16, 64x8 or 128x4")
                      : h->cfg.precision == LBM_EM_FP32
                          ? "FP32 two-step tile must be 64x16, 128x8, 128x16, 256x8, 256x16 or 128x32"
                          : "FP64 two-step tile must be 32x16, 64x8, 64x16, 128x8, 128x16 or 64x32");
