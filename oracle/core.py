@@ -125,12 +125,12 @@ class Oracle:
         lib().oracle_clear_source(self._h)
 
     def set_incident_line(self, axis):
-        """Exact incident line along axis 0 (x) or 1 (y), None to remove it
+        """Exact incident line along axis 0 (x), 1 (y) or 2 (z), None to remove it
         (lbm_oracle.c: the one-row auxiliary run and its layer rule).  Call
         after set_source and before stepping."""
         rc = lib().oracle_set_incident_line(self._h, -1 if axis is None else int(axis))
         if rc != 0:
-            raise ValueError("the incident line needs a 2-D grid and a source along that axis")
+            raise ValueError("the incident line needs a source along that axis")
         self._line_n = 0 if axis is None else self.n[int(axis)]
 
     def get_line_dft(self):

@@ -49,7 +49,7 @@
  *     imposes no incident wave on it.  The adjoint does not cover PEC cells.
  *   - Exact incident line (a total-field / scattered-field-like forcing for
  *     axis-aligned incidence, which section 4 names as future work): an
- *     auxiliary one-row run along the incidence axis (same layers on that
+ *     auxiliary one-cell-wide run along the incidence axis (same layers on that
  *     axis, background medium, same source) is advanced with the grid.  In a
  *     background layer cell the update becomes
  *         f' = f* + sigma (f_l* - f*) + sigma_a (f^eq_ref - f_l*),
@@ -304,7 +304,7 @@ void oracle_set_dft(lbm_oracle *o, int64_t n, const int64_t *cells, int64_t win0
     }
 }
 
-/* Exact incident line along axis (0: x, 1: y) for a 2-D grid whose source
+/* Exact incident line along axis (0: x, 1: y, 2: z) for a grid whose source
  * propagates along that axis; axis < 0 removes it.  The line starts from a
  * zero state at the grid's current time, so set it before stepping.  The
  * line records its fields at all its cells over the DFT window of the most
@@ -317,10 +317,12 @@ int oracle_set_incident_line(lbm_oracle *o, int axis) {
         o->line = NULL;
     }
     if (axis < 0) return 0;
-    if (axis > 1 || o->n[2] != 1 || !o->src_on || fabs(fabs(o->khat[axis]) - 1.0) > 1e-12) return -1;
+    if (axis > 2 || !o->src_on || fabs(fabs(o->khat[axis]) - 1.0) > 1e-12) return -1;
     const int na = o->n[axis];
-    lbm_oracle *l = oracle_create(axis == 0 ? na : 1, axis == 0 ? 1 : na, 1, axis == 0 ? o->W[0] : 0,
-                                  axis == 0 ? 0 : o->W[1], 0, o->sigma_max);
+    int ln[3] = {1, 1, 1}, lw[3] = {0, 0, 0};
+    ln[axis] = na;
+    lw[axis] = o->W[axis];
+    lbm_oracle *l = oracle_create(ln[0], ln[1], ln[2], lw[0], lw[1], lw[2], o->sigma_max);
     if (!l) return -1;
     oracle_set_source(l, o->lambda, o->khat, o->ehat, o->amp, o->t_ramp, o->rc);
     l->t = o->t;

@@ -213,6 +213,22 @@ def test_incident_line_is_exact(theta, pol, axis):
         assert np.array_equal(X, np.broadcast_to(L[:, None, :], X.shape))
 
 
+@pytest.mark.parametrize("kz", [1.0, -1.0])
+def test_incident_line_is_exact_3d(kz):
+    """The same for a 3-D grid absorbing on all faces, incidence along +-z:
+    every x-y plane reproduces the line's cell at its z, bit for bit."""
+    n = (20, 16, 40)
+    o = Oracle(*n, (4, 4, 8), W.SIGMA_MAX)
+    o.set_source(10.0, [0, 0, kz], [1.0, 0, 0], 1.0, 1.0)
+    o.set_dft(np.arange(n[0] * n[1] * n[2]), 90, 30)
+    o.set_incident_line(2)
+    o.step(120)
+    X = o.get_dft().reshape(n[2], n[1], n[0], 6)
+    L = o.get_line_dft()
+    assert np.abs(L).max() > 0.5
+    assert np.array_equal(X, np.broadcast_to(L[:, None, None, :], X.shape))
+
+
 @pytest.mark.slow
 def test_incident_line_cylinder_matches_companion():
     """The line's phasors as the incident field of the NTFF: |S(theta)|^2 of
