@@ -234,9 +234,30 @@ def line_extra(Simulation, W, torch, steps=1600):
         torch.cuda.synchronize()
         out["with_line" if line else "without"] = e0.elapsed_time(e1) / steps * 1e3
         s.close()
-    return {"workload": "cylinder-1024x1024-eps2.25-TM", "us_per_step": out,
-            "line_overhead": out["with_line"] / out["without"] - 1.0,
-            "note": "the line replaces the full vacuum companion run (one more 1024^2 grid)"}
+    res = {"workload": "cylinder-1024x1024-eps2.25-TM", "us_per_step": out,
+           "line_overhead": out["with_line"] / out["without"] - 1.0,
+           "note": "the line replaces the full vacuum companion run (one more grid of the same size)"}
+    # the same on the 384^3 sphere (incidence along z)
+    case = W.sphere_case(n=384, steps=200, with_eps=True)
+    out3 = {}
+    for line in (False, True):
+        s = Simulation(384, 384, 384, pol="3D", precision="fp32", absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(case.eps)
+        s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
+        if line:
+            s.set_incident_line(True)
+        s.step(64)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(128)
+        e1.record()
+        torch.cuda.synchronize()
+        out3["with_line" if line else "without"] = e0.elapsed_time(e1) / 128
+        s.close()
+    res["sphere_384_ms_per_step"] = out3
+    res["sphere_line_overhead"] = out3["with_line"] / out3["without"] - 1.0
+    return res
 
 
 def batched_extra(P, W, torch, steps=6000):

@@ -152,8 +152,9 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_
 
 /* Exact incident line (a total-field / scattered-field-like forcing, which
  * the paper names as future work in section 4) for a 2-D handle whose
- * source propagates along +-x or +-y (|khat| components within 1e-12 of
- * axis-aligned): a one-row (one-column) run along that axis, with the same
+ * source propagates along +-x or +-y, or a 3-D handle with incidence along
+ * +-z (khat components within 1e-12 of axis-aligned): a one-cell-wide run
+ * along that axis, with the same
  * layers on it and the same source, advances with the grid (one small
  * launch before each grid launch).  In background layer cells (eps_r =
  * mu_r = 1) the layer then damps only the scattered part,
@@ -166,8 +167,11 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_
  * enable = 0 removes the line.  Set it after the source and before stepping
  * (t = 0, or after a reset); a new source removes it.  Batches and the
  * adjoint refuse a handle with a line.
- * Errors: EUNSUPPORTED for 3-D handles or after adjoint_setup, ESTATE
- * without a source, at t > 0 or while batched, EINVAL for other directions. */
+ * A 3-D line is held in LDS and must fit 64 KB (FP32 nz <= 606, FP64
+ * nz <= 303).
+ * Errors: EUNSUPPORTED after adjoint_setup or for a 3-D line that does not
+ * fit, ESTATE without a source, at t > 0 or while batched, EINVAL for other
+ * directions. */
 lbm_em_status lbm_em_set_incident_line(lbm_em_handle h, int32_t enable);
 
 /* The incident line's phasors: out[(u*6 + c)*2 + {0,1}] = (re, im) of

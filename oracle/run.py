@@ -70,8 +70,9 @@ def intensity_2d(case, total, incident, theta_rel_deg):
                             th, case.pol, center, amp)
 
 
-def run_3d(case, sigma_max, ramp_periods, eps=None, steps=None):
-    """Sphere-type 3-D run: k along +z, E along +x (section 3.4)."""
+def run_3d(case, sigma_max, ramp_periods, eps=None, steps=None, line=False):
+    """Sphere-type 3-D run: k along +z, E along +x (section 3.4); line: with
+    the exact incident line (its phasors returned as "line")."""
     steps = case.steps if steps is None else steps
     n = case.n
     W = case.W
@@ -84,9 +85,14 @@ def run_3d(case, sigma_max, ramp_periods, eps=None, steps=None):
                             ntff.linear_index(np.array([pr]), (n, n, n))])
     w0, wl = case.window
     o.set_dft(cells, w0, wl)
+    if line:
+        o.set_incident_line(2)
     o.step(steps)
     X = o.get_dft()
-    return {"nodes": nodes, "phasors": X[:-1], "probe": X[-1], "oracle": o}
+    out = {"nodes": nodes, "phasors": X[:-1], "probe": X[-1], "oracle": o}
+    if line:
+        out["line"] = o.get_line_dft()
+    return out
 
 
 def intensity_3d(case, total, incident, theta_deg, phi_deg):

@@ -735,6 +735,7 @@ __global__ void __launch_bounds__(1024) k_line_lds(StepArgs<T> a, T *dst, int ns
     for (int k = tid; k < 11 * n; k += NT) dst[(k / n) * P + (k % n) * cstride] = S[k];
 }
 
+
 // Batched persistent step: one launch advances many 2-D instances of
 // different sizes.  The work list is every (instance, tile) pair, tiles of
 // bx*VX x by cells, instances one after another; a grid sized to the chip
@@ -1142,12 +1143,25 @@ __device__ inline T sigma3d(const StepArgs<T> &a, int x, int y, int z) {
 // 3-D per-cell update (moments, DFT sample, collision, layer/source);
 // inv_eps = 1/eps and sig = sigma3d(x, y, z) from the caller; record: the
 // cell is in the domain and owned by this thread (DFT samples).
-template <typename T>
+template <typename T, bool LINE = false, bool LREC = false>
 __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, int z, T eps,
-                                     T inv_eps, T sig, T f[27], bool record) {
+                                     T inv_eps, T sig, T f[27], bool record, const T *fl = nullptr,
+                                     int fl_stride = 0) {
     T E[3], H[3];
     fields3d(f, inv_eps, E, H);
-    if (st.dft && record) {
+    if (LREC) {
+        if (st.dft && record) {
+            // line phasors, one node per line cell
+            double *pa = a.line_acc + (int64_t)(a.line_axis == 0 ? x : a.line_axis == 1 ? y : z) * 12;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pa[2 * c] += (double)E[c] * st.cr;
+                pa[2 * c + 1] += (double)E[c] * st.ci;
+                pa[6 + 2 * c] += (double)H[c] * st.cr;
+                pa[6 + 2 * c + 1] += (double)H[c] * st.ci;
+            }
+        }
+    } else if (st.dft && record) {
         const double G[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
         dft_accumulate<0x3f>(a, st, 3, x, y, z, G);
     }
@@ -1167,9 +1181,16 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
 #pragma unroll
         for (int k = 0; k < 3; ++k) f[24 + k] = fma(r, E[k], -f[24 + k]);
     }
+    if (LREC) {
+        T *rp = a.line_rec + (int64_t)(st.t & (kLineSlots - 1)) * 27 * a.line_n +
+                (a.line_axis == 0 ? x : a.line_axis == 1 ? y : z);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) rp[(int64_t)i * a.line_n] = f[i];
+    }
     if (sig > T(0)) {
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
-        if (a.src_on && eps == T(1)) {
+        const bool background = a.src_on && eps == T(1);
+        if (background) {
             const T w = plane_wave<T, 3>(a, st, x, y, z);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -1179,8 +1200,21 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
         }
         T qr[27];
         equilibrium3d(Er, Hr, eps, T(1), qr);
+        if (LINE && background) {
+            // exact incident line (see cell_update2d); fl: the line's
+            // post-collision populations of this step at this coordinate
+            const int ax = a.line_axis, u = ax == 0 ? x : ax == 1 ? y : z;
+            const int nax = ax == 0 ? a.nx : ax == 1 ? a.ny : a.nz;
+            const T sa = sigma_axis<T>(u, nax, a.W[ax], a.inv_w[ax], a.sigma_max);
 #pragma unroll
-        for (int i = 0; i < 27; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
+            for (int i = 0; i < 27; ++i) {
+                const T l = fl[i * fl_stride];
+                f[i] = fma(sa, qr[i] - l, fma(sig, l - f[i], f[i]));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 27; ++i) f[i] = fma(sig, qr[i] - f[i], f[i]);
+        }
     }
 }
 
@@ -1207,7 +1241,8 @@ __device__ inline void pull3d(const StepArgs<T> &a, int x, int y, int z, T f[27]
     e = *at(a.eps, c);
 }
 
-template <typename T, int VX>
+// LINE: the layer follows the exact incident line a.line_tab.
+template <typename T, int VX, bool LINE = false>
 __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
     const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VX;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -1271,7 +1306,12 @@ __global__ void __launch_bounds__(256) k_step3d(StepArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < 27; ++i) f[i] = v[i][j];
         const int xj = x0 + j < a.nx ? x0 + j : a.nx - 1;
-        cell_update3d<T>(a, st, xj, y, z, e[j], recip(e[j]), sigma3d<T>(a, xj, y, z), f, x0 + j < a.nx);
+        const T *fl = nullptr;
+        if (LINE)
+            fl = a.line_tab + (int64_t)(st.t & (kLineSlots - 1)) * 27 * a.line_n +
+                 (a.line_axis == 0 ? xj : a.line_axis == 1 ? y : z);
+        cell_update3d<T, LINE>(a, st, xj, y, z, e[j], recip(e[j]), sigma3d<T>(a, xj, y, z), f, x0 + j < a.nx, fl,
+                               a.line_n);
 #pragma unroll
         for (int i = 0; i < 27; ++i) v[i][j] = f[i];
     }
@@ -1313,12 +1353,17 @@ struct X3Lds {
     T yp[4][TY + 1][TX];   // -y movers (planes 12..15): tile row oy at oy, ring row below at TY
 };
 
-template <typename T, int TX, int TY>
+// LINE: exact incident line along z (the only direction a 3-D line takes):
+// its values depend on the plane alone, so each iteration stages the next
+// iteration's 2 x 27 values in LDS before its second barrier.
+template <typename T, int TX, int TY, bool LINE = false>
 __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
     constexpr int NT = TX * TY;
     constexpr int NR = 2 * TX + 2 * TY;
     static_assert(NR <= NT, "ring larger than the block");
+    static_assert(NT >= 54, "line staging needs 54 threads");
     __shared__ X3Lds<T, TX, TY> L[2];
+    __shared__ T lz[2][2][27];   // [plane parity][step t, t+1][population]
     const int tiles = a.tiles_x * a.tiles_y;
     // XCD-banded order: neighbouring tiles of a chunk share an L2, so the
     // ring cells' reads of a neighbour's plane hit it
@@ -1349,6 +1394,19 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
     rest[0] = rest[1] = rest[2] = T(0);
     const int64_t P = a.plane;
     const uint32_t sy = (uint32_t)a.sy, sz = (uint32_t)a.sz;
+    // the line's populations of step t on plane p and of step t+1 on plane
+    // p - 1, for iteration p, into lz[p & 1]
+    auto stage_line = [&](int p) {
+        if (tid < 54) {
+            const int st1 = tid / 27, i = tid % 27;
+            const int zz = st1 ? fold(p - 1, a.nz, a.W[2]) : fold(p, a.nz, a.W[2]);
+            lz[p & 1][st1][i] = a.line_tab[((int64_t)((t + st1) & (kLineSlots - 1)) * 27 + i) * a.line_n + zz];
+        }
+    };
+    if (LINE) {
+        stage_line(zb - 1);
+        __syncthreads();
+    }
 
     for (int p = zb - 1; p <= ze; ++p) {
         const int pf = fold(p, a.nz, a.W[2]);
@@ -1357,7 +1415,7 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
         T f[27], e;
         pull3d<T>(a, xf, yf, pf, f, e);
         const T ie = recip(e), sgp = sigma3d<T>(a, xf, yf, pf);
-        cell_update3d<T>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze);
+        cell_update3d<T, LINE>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze, lz[p & 1][0], 1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             B.xm[k][oy][ox + 1] = f[k];
@@ -1369,7 +1427,8 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
         if (ring) {
             T g[27], ge;
             pull3d<T>(a, rxf, ryf, pf, g, ge);
-            cell_update3d<T>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf), g, false);
+            cell_update3d<T, LINE>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf), g, false,
+                                   lz[p & 1][0], 1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (tid < TX) B.ym[k][0][tid] = g[8 + k];
@@ -1400,13 +1459,14 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
             h[24] = rest[0];
             h[25] = rest[1];
             h[26] = rest[2];
-            cell_update3d<T>(a, s1, xf, yf, q, ep, ip, sg, h, own);
+            cell_update3d<T, LINE>(a, s1, xf, yf, q, ep, ip, sg, h, own, lz[p & 1][1], 1);
             if (own) {
                 const uint32_t c = (uint32_t)q * sz + (uint32_t)y * sy + (uint32_t)x;
 #pragma unroll
                 for (int i = 0; i < 27; ++i) *at(a.dst + i * P, c) = h[i];
             }
         }
+        if (LINE && p < ze) stage_line(p + 1);
         __syncthreads();
         // plane p becomes the previous plane
 #pragma unroll
@@ -1421,6 +1481,47 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
         ip = ie;
         sg = sgp;
     }
+}
+
+// The 3-D incident line (along z; the line handle is 1 x 1 x n) held in
+// LDS for nsteps: the same per-cell update as the grid's cells, pulling
+// the +z movers from u - 1 and the -z movers from u + 1, the x/y movers
+// (a single periodic cell) from the cell itself.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_line3d_lds(StepArgs<T> a, T *dst, int nsteps) {
+    extern __shared__ unsigned char line_raw3[];
+    T *S = reinterpret_cast<T *>(line_raw3);    // 27 planes x n
+    const int n = a.line_n, NT = blockDim.x, tid = threadIdx.x;
+    const int64_t P = a.plane, cstride = a.sz;
+    const int Wl = a.W[2];
+    for (int k = tid; k < 27 * n; k += NT) S[k] = a.src[(k / n) * P + (k % n) * cstride];
+    __syncthreads();
+    const int64_t t0 = step_time(a.t_base, a.t_off);
+    for (int s = 0; s < nsteps; ++s) {
+        const StepConst<T> st = step_const(a, t0 + s);
+        T out[27];
+        const int u = tid;
+        if (u < n) {
+            const int lo = pull_lo(u, n, Wl), hi = pull_hi(u, n, Wl);
+            T f[27];
+#pragma unroll
+            for (int i = 0; i < 27; ++i) f[i] = S[i * n + u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                f[16 + k] = S[(16 + k) * n + lo];
+                f[20 + k] = S[(20 + k) * n + hi];
+            }
+            cell_update3d<T, false, true>(a, st, 0, 0, u, T(1), recip(T(1)), sigma3d<T>(a, 0, 0, u), f, true);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) out[i] = f[i];
+        }
+        __syncthreads();
+        if (u < n)
+#pragma unroll
+            for (int i = 0; i < 27; ++i) S[i * n + u] = out[i];
+        __syncthreads();
+    }
+    for (int k = tid; k < 27 * n; k += NT) dst[(k / n) * P + (k % n) * cstride] = S[k];
 }
 
 // ---------------------------------------------------------------------------

@@ -155,6 +155,11 @@ void select_device(const lbm_em *h) { hip_check(hipSetDevice(h->dev), "hipSetDev
 
 void sync(const lbm_em *h) { hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize"); }
 
+// Cells of the incident line: the grid's extent along the line's axis.
+int64_t line_len(const lbm_em *h) {
+    return h->line_axis == 0 ? h->cfg.nx : h->line_axis == 1 ? h->cfg.ny : h->cfg.nz;
+}
+
 template <typename T>
 StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     StepArgs<T> a{};
@@ -201,7 +206,7 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     if (h->line) {
         a.line_tab = (const T *)h->line_tab;
         a.line_axis = h->line_axis;
-        a.line_n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        a.line_n = line_len(h);
     }
     return a;
 }
@@ -221,7 +226,7 @@ void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
         if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, true>), grid, block, 0, s, a);
         else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE, VX, false, true>), grid, block, 0, s, a);
         else fail(LBM_EM_EUNSUPPORTED, "a permeability map needs a 2-D (TM/TE) handle");
-    } else if (a.line_tab) {
+    } else if (a.line_tab && h->dim == 2) {
         if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, false, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_step2d<T, TE, VX, false, false, true>), grid, block, 0, s, a);
     } else if (h->cfg.pol == LBM_EM_TM) {
@@ -230,6 +235,8 @@ void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
     } else if (h->cfg.pol == LBM_EM_TE) {
         if (rec) hipLaunchKernelGGL((k_step2d<T, TE, VX, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_step2d<T, TE, VX>), grid, block, 0, s, a);
+    } else if (a.line_tab) {
+        hipLaunchKernelGGL((k_step3d<T, VX, true>), grid, block, 0, s, a);
     } else {
         hipLaunchKernelGGL((k_step3d<T, VX>), grid, block, 0, s, a);
     }
@@ -255,11 +262,11 @@ void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t
     else if constexpr (sizeof(T) == 4) launch_step_vx<T, 4>(a, h, s);
 }
 
-// Largest line (in cells) whose state the LDS kernel holds: 64 KB of LDS
-// and two cells per thread.
+// Largest line (in cells) whose state the LDS kernels hold: 64 KB of LDS,
+// two cells per thread (2-D) or one (3-D).
 bool line_in_lds(const lbm_em *h) {
-    const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
-    return n <= 2048 && 11 * n * (int64_t)h->elem <= 65536;
+    const int64_t n = line_len(h);
+    return n <= (h->dim == 2 ? 2048 : 1024) && h->nplanes * n * (int64_t)h->elem <= 65536;
 }
 
 // The incident line's steps for the grid launches that follow: nsteps from
@@ -282,15 +289,16 @@ void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t
         a.line_rec = (T *)h->line_tab;
         a.line_acc = h->line_acc;
         a.line_axis = h->line_axis;
-        a.line_n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        a.line_n = line_len(h);
         T *dst = (T *)l->buf[flip ? parity ^ 1 : parity];
-        const size_t lds = (size_t)11 * a.line_n * sizeof(T);
+        const size_t lds = (size_t)h->nplanes * a.line_n * sizeof(T);
         if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_line_lds<T, TM>), dim3(1), dim3(1024), lds, s, a, dst, nsteps);
-        else hipLaunchKernelGGL((k_line_lds<T, TE>), dim3(1), dim3(1024), lds, s, a, dst, nsteps);
+        else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_line_lds<T, TE>), dim3(1), dim3(1024), lds, s, a, dst, nsteps);
+        else hipLaunchKernelGGL((k_line3d_lds<T>), dim3(1), dim3(1024), lds, s, a, dst, nsteps);
         hip_check(hipGetLastError(), "k_line_lds");
         return;
     }
-    if (nsteps > 2 || !flip) fail(LBM_EM_EINVAL, "internal: global-memory line steps are per launch");
+    if (nsteps > 2 || !flip || h->dim != 2) fail(LBM_EM_EINVAL, "internal: global-memory line steps are per 2-D launch");
     StepArgs<T> a0 = make_args<T>(l, l->buf[parity], nsteps == 2 ? h->line_tmp : l->buf[parity ^ 1]);
     StepArgs<T> a1 = make_args<T>(l, h->line_tmp, l->buf[parity ^ 1]);
     for (StepArgs<T> *a : {&a0, &a1}) {
@@ -301,7 +309,7 @@ void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t
         a->line_rec = (T *)h->line_tab;
         a->line_acc = h->line_acc;
         a->line_axis = h->line_axis;
-        a->line_n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        a->line_n = line_len(h);
     }
     a0.t_off = t_off;
     a1.t_off = t_off + 1;
@@ -394,7 +402,10 @@ void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
     dim3 grid((unsigned)(tiles * ((a.nz + zc - 1) / zc)), 1, 1);
 #define LBM_X3(TX, TY)                                                                      \
     if (tx == TX && ty == TY) {                                                             \
-        hipLaunchKernelGGL((k_step3d_x2<T, TX, TY>), grid, dim3(TX * TY), 0, s, a, zc);     \
+        if (a.line_tab)                                                                     \
+            hipLaunchKernelGGL((k_step3d_x2<T, TX, TY, true>), grid, dim3(TX * TY), 0, s, a, zc); \
+        else                                                                                \
+            hipLaunchKernelGGL((k_step3d_x2<T, TX, TY>), grid, dim3(TX * TY), 0, s, a, zc); \
         return;                                                                             \
     }
     if constexpr (sizeof(T) == 4) { LBM_X3_TILES_F32(LBM_X3) }
@@ -813,19 +824,20 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
 // The incident line's phasors laid out like the contour accumulators (one
 // row of 12 per box node, then the probe), in a new device buffer.
 double *line_incident(lbm_em *h) {
-    const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+    const int64_t n = line_len(h);
     std::vector<double> L((size_t)n * 12), out((size_t)(h->nnodes + 1) * 12);
     hip_check(hipMemcpyAsync(L.data(), h->line_acc, L.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "D2H");
     sync(h);
     const Box &b = h->box;
-    for (int y = b.lo[1]; y <= b.hi[1]; ++y)
-        for (int x = b.lo[0]; x <= b.hi[0]; ++x) {
-            if (!on_box(b, 2, x, y, 0)) continue;
-            const int64_t node = box_node_index(b, 2, x, y, 0);
-            const int u = h->line_axis == 0 ? x : y;
-            std::memcpy(&out[(size_t)node * 12], &L[(size_t)u * 12], 12 * sizeof(double));
-        }
-    const int up = h->line_axis == 0 ? h->probe[0] : h->probe[1];
+    for (int z = b.lo[2]; z <= b.hi[2]; ++z)
+        for (int y = b.lo[1]; y <= b.hi[1]; ++y)
+            for (int x = b.lo[0]; x <= b.hi[0]; ++x) {
+                if (!on_box(b, h->dim, x, y, z)) continue;
+                const int64_t node = box_node_index(b, h->dim, x, y, z);
+                const int u = h->line_axis == 0 ? x : h->line_axis == 1 ? y : z;
+                std::memcpy(&out[(size_t)node * 12], &L[(size_t)u * 12], 12 * sizeof(double));
+            }
+    const int up = h->probe[h->line_axis];
     std::memcpy(&out[(size_t)h->nnodes * 12], &L[(size_t)up * 12], 12 * sizeof(double));
     double *d = nullptr;
     hip_check(hipMalloc(&d, out.size() * sizeof(double)), "hipMalloc");
@@ -906,7 +918,7 @@ void reset_state(lbm_em *h) {
     h->cur = 0;
     if (h->line) {
         reset_state(h->line);
-        const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        const int64_t n = line_len(h);
         hip_check(hipMemsetAsync(h->line_acc, 0, (size_t)n * 12 * sizeof(double), h->stream), "hipMemset line dft");
     }
 }
@@ -1258,7 +1270,6 @@ lbm_em_status lbm_em_set_pec(lbm_em_handle hh, const uint8_t *mask, int32_t wher
 lbm_em_status lbm_em_set_incident_line(lbm_em_handle hh, int32_t enable) {
     return guarded([&] {
         lbm_em *h = check_handle(hh);
-        if (h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "the incident line needs a 2-D (TM/TE) handle");
         if (h->batch_refs) fail(LBM_EM_ESTATE, "handle is part of a batch; destroy the batch first");
         if (h->adj_set) fail(LBM_EM_EUNSUPPORTED, "the adjoint uses the companion run, not an incident line");
         select_device(h);
@@ -1270,15 +1281,22 @@ lbm_em_status lbm_em_set_incident_line(lbm_em_handle hh, int32_t enable) {
         if (h->t != 0) fail(LBM_EM_ESTATE, "set the incident line before stepping (or after a reset)");
         const double *k = h->pw.khat;
         int axis = -1;
-        if (std::fabs(std::fabs(k[0]) - 1.0) <= 1e-12 && std::fabs(k[1]) <= 1e-12) axis = 0;
-        else if (std::fabs(std::fabs(k[1]) - 1.0) <= 1e-12 && std::fabs(k[0]) <= 1e-12) axis = 1;
-        if (axis < 0) fail(LBM_EM_EINVAL, "the incident line needs incidence along +-x or +-y");
+        for (int ax = 0; ax < 3; ++ax)
+            if (std::fabs(std::fabs(k[ax]) - 1.0) <= 1e-12 && std::fabs(k[(ax + 1) % 3]) <= 1e-12 &&
+                std::fabs(k[(ax + 2) % 3]) <= 1e-12)
+                axis = ax;
+        if (h->dim == 2 && axis != 0 && axis != 1)
+            fail(LBM_EM_EINVAL, "the incident line needs incidence along +-x or +-y");
+        if (h->dim == 3 && axis != 2) fail(LBM_EM_EINVAL, "a 3-D incident line needs incidence along +-z");
+        h->line_axis = axis;
+        if (h->dim == 3 && !line_in_lds(h))
+            fail(LBM_EM_EUNSUPPORTED, "a 3-D incident line must fit 64 KB of LDS (FP32 nz <= 606, FP64 nz <= 303)");
         lbm_em_config lc = h->cfg;
-        lc.nx = axis == 0 ? h->cfg.nx : 1;
-        lc.ny = axis == 0 ? 1 : h->cfg.ny;
-        lc.absorb[0] = axis == 0 ? h->cfg.absorb[0] : 0;
-        lc.absorb[1] = axis == 0 ? 0 : h->cfg.absorb[1];
-        lc.absorb[2] = 0;
+        const int n3[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz};
+        lc.nx = axis == 0 ? n3[0] : 1;
+        lc.ny = axis == 1 ? n3[1] : 1;
+        lc.nz = axis == 2 ? n3[2] : 1;
+        for (int ax = 0; ax < 3; ++ax) lc.absorb[ax] = ax == axis ? h->cfg.absorb[ax] : 0;
         lc.stream = (void *)h->stream;
         lbm_em *l = nullptr;
         lbm_em_status st = lbm_em_create(&lc, &l);
@@ -1292,8 +1310,8 @@ lbm_em_status lbm_em_set_incident_line(lbm_em_handle hh, int32_t enable) {
             fail(st, "incident line: " + msg);
         }
         try {
-            const int64_t n = axis == 0 ? h->cfg.nx : h->cfg.ny;
-            const size_t tab = (size_t)kLineSlots * 11 * n * h->elem;
+            const int64_t n = line_len(h);
+            const size_t tab = (size_t)kLineSlots * h->nplanes * n * h->elem;
             hip_check(hipMalloc(&h->line_tmp, (size_t)l->plane * l->nplanes * l->elem), "hipMalloc line");
             hip_check(hipMalloc(&h->line_tab, tab), "hipMalloc line");
             hip_check(hipMalloc(&h->line_acc, (size_t)n * 12 * sizeof(double)), "hipMalloc line");
@@ -1312,7 +1330,7 @@ lbm_em_status lbm_em_get_line_phasors(lbm_em_handle hh, double *out, int32_t *n)
         lbm_em *h = check_handle(hh);
         if (!n) fail(LBM_EM_EINVAL, "null count");
         if (!h->line) fail(LBM_EM_ESTATE, "no incident line");
-        *n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+        *n = line_len(h);
         if (!out) return;
         select_device(h);
         hip_check(hipMemcpyAsync(out, h->line_acc, (size_t)*n * 12 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
@@ -1429,7 +1447,7 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle hh, const int32_t lo[3], const int32
         hip_check(hipMalloc(&h->acc, bytes), "hipMalloc dft");
         hip_check(hipMemsetAsync(h->acc, 0, bytes, h->stream), "hipMemset dft");
         if (h->line) {
-            const int64_t n = h->line_axis == 0 ? h->cfg.nx : h->cfg.ny;
+            const int64_t n = line_len(h);
             hip_check(hipMemsetAsync(h->line_acc, 0, (size_t)n * 12 * sizeof(double), h->stream), "hipMemset line dft");
         }
         h->dft_set = true;

@@ -834,7 +834,7 @@ def test_incident_line_cylinder_intensity(gpu, pol):
 
 
 def test_incident_line_api_limits(gpu):
-    """The line needs a 2-D handle, a source along an axis and t = 0; a new
+    """The line needs a source along an axis (z in 3-D) and t = 0; a new
     source removes it; batches and the adjoint refuse a handle with one."""
     from paper_2510_11042_amd import LbmEmError, step_many
 
@@ -866,9 +866,9 @@ def test_incident_line_api_limits(gpu):
     s.set_incident_line(True)
     s.step(2)
     s3 = gpu(8, 8, 8, pol="3D", precision="fp32", absorb=(0, 0, 0), sigma_max=W.SIGMA_MAX)
-    s3.set_source(4.0, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+    s3.set_source(4.0, [1.0, 0, 0], [0, 0, 1.0], 1.0, 1.0)
     with pytest.raises(LbmEmError):
-        s3.set_incident_line(True)
+        s3.set_incident_line(True)                   # 3-D lines run along z only
     for h in (s, other, s3):
         h.close()
 
@@ -937,3 +937,91 @@ def test_edge_cases_and_errors(gpu):
     E, H = one.fields()
     assert one.t == 65 and not np.any(E) and not np.any(H)
     one.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_incident_line_3d_matches_oracle(gpu, prec):
+    """3-D incident line (incidence along +z): fields of a small dielectric
+    sphere grid absorbing on all faces against the oracle with its line,
+    one and two steps per launch, eager steps and graph chunks; then |S|^2
+    from the line's phasors against the oracle's line-based intensity."""
+    n = 48
+    case = W.sphere_case(n=n, x_size=2.5, lam=12.0, eps_in=2.25, W=8, steps=360, half=8.5)
+    say("3d line", prec)
+    for fuse in (1, 2):
+        s, o = make_pair(gpu, n, n, n, "3D", prec, (8, 8, 8), case.eps, case.lam, [0, 0, 1.0], [1.0, 0, 0],
+                         ramp=1.0)
+        s.set_incident_line(True)
+        s.set_fusion(fuse)
+        o.set_incident_line(2)
+        for k in (1, 9, 130):
+            s.step(k)
+            o.step(k)
+            compare_fields(s, o, prec, f"3d line fuse {fuse} t={o.t}")
+        s.close()
+    tot_o = run.run_3d(case, W.SIGMA_MAX, 1.0, line=True)
+    L = tot_o["line"]
+    pr = run.probe_node(case.box_lo, case.box_hi)
+    inc_o = {"phasors": L[tot_o["nodes"][:, 2]], "probe": L[pr[2]]}
+    s = gpu(n, n, n, pol="3D", precision=prec, absorb=(8, 8, 8), sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+    s.set_ntff(case.box_lo, case.box_hi, *case.window)
+    s.set_incident_line(True)
+    s.step(case.steps)
+    th = np.arange(0, 180.01, 1.0)
+    for phi in (0.0, 90.0):
+        S_o = run.intensity_3d(case, tot_o, inc_o, th, np.full_like(th, phi))
+        S_g = s.farfield(th, np.full_like(th, phi))
+        err = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
+        say("3d line phi", phi, prec, err)
+        assert err <= (1e-10 if prec == "fp64" else 1e-3)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_incident_line_3d_exact_and_tiles(gpu, prec):
+    """A background-only 3-D grid with the line is the line on every x-y
+    plane, bit for bit; and every 3-D two-step tile reproduces one step per
+    launch bit for bit with the line on a dielectric grid."""
+    nx, ny, nz = 70, 36, 44
+    s = gpu(nx, ny, nz, pol="3D", precision=prec, absorb=(6, 6, 8), sigma_max=W.SIGMA_MAX)
+    s.set_source(10.0, [0, 0, -1.0], [0, 1.0, 0], 1.0, 1.0)
+    s.set_incident_line(True)
+    s.step(131)
+    E, H = s.fields()
+    assert np.abs(E).max() > 0.1
+    assert np.array_equal(E, np.broadcast_to(E[:, :1, :1], E.shape))
+    assert np.array_equal(H, np.broadcast_to(H[:, :1, :1], H.shape))
+    s.close()
+    rng = np.random.default_rng(13)
+    eps = 1.0 + (rng.random((nz, ny, nx)) < 0.1) * rng.uniform(0.2, 2.0, (nz, ny, nx))
+    runs = []
+    for fuse, tile in [(1, (0, 0))] + [(2, t) for t in X3_TILES[prec]]:
+        s = gpu(nx, ny, nz, pol="3D", precision=prec, absorb=(6, 6, 8), sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(eps)
+        s.set_source(10.0, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+        s.set_incident_line(True)
+        s.set_fusion(fuse, tile)
+        s.step(67)
+        runs.append(s.fields())
+        say("3d line fusion", prec, fuse, tile)
+        s.close()
+    for E2, H2 in runs[1:]:
+        assert np.array_equal(runs[0][0], E2) and np.array_equal(runs[0][1], H2)
+
+
+def test_incident_line_3d_limits(gpu):
+    """A 3-D line needs incidence along z and must fit 64 KB of LDS."""
+    from paper_2510_11042_amd import LbmEmError
+
+    s = gpu(16, 16, 16, pol="3D", precision="fp32", absorb=(4, 4, 4), sigma_max=W.SIGMA_MAX)
+    s.set_source(8.0, [1.0, 0, 0], [0, 0, 1.0], 1.0, 1.0)
+    with pytest.raises(LbmEmError):
+        s.set_incident_line(True)
+    s.close()
+    s = gpu(8, 8, 700, pol="3D", precision="fp32", absorb=(0, 0, 20), sigma_max=W.SIGMA_MAX)
+    s.set_source(8.0, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+    with pytest.raises(LbmEmError):
+        s.set_incident_line(True)
+    s.close()
