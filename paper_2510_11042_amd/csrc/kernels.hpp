@@ -452,8 +452,13 @@ __device__ inline T sigma2d(const StepArgs<T> &a, int x, int y) {
 // permeability mu (inv_mu = 1/mu).  LINE: background layer cells follow the
 // exact incident line (see below).  LREC: this is the line's own update; it
 // records the post-collision populations and the phasors of every cell.
+// MODE (without MU / LINE / LREC, which keep collision then layer): 0 the
+// plain collision where sig = 0 and the one-pass collision + layer where
+// sig > 0; 1 the one-pass form for every cell (the caller's cells include
+// layer cells; for sig = 0 it reproduces the plain collision bit for bit);
+// 2 the plain collision only (the caller guarantees sig = 0).
 template <typename T, int POL, bool HIST = false, bool PH = false, bool MU = false, bool LINE = false,
-          bool LREC = false>
+          bool LREC = false, int MODE = 0>
 __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, T eps,
                                      T inv_eps, T sig, T f[11], bool record, T ur = T(0), T ui = T(0),
                                      T mu = T(1), T inv_mu = T(1), const T *fl = nullptr, int fl_stride = 0) {
@@ -493,6 +498,48 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
             h[2 * cell] = (T(6) * f[8] - F[0]) * inv_eps;
             h[2 * cell + 1] = (T(6) * f[9] - F[1]) * inv_eps;
         }
+    }
+    if (!LINE && !LREC && !MU) {
+        // Collision and layer in one pass: with f* = 2 f^eq(F) - f and
+        // f' = f* + sig (f^eq(R) - f*), linearity of f^eq gives
+        // f' = f^eq(G) - s f, G = 2F + sig (R - 2F), s = 1 - sig; written as
+        // fma(1/6, combo(G), -(s f)), which for sig = 0 (G = 2F exactly,
+        // s f = f exactly, 1/6 = (1/3)/2 exactly) is the plain collision's
+        // fma(1/3, combo(F), -f) bit for bit.
+        if (MODE == 2 || (MODE == 0 && !(sig > T(0)))) {
+            collide2d<T, POL>(F, f);
+            return;
+        }
+        T R[3] = {0, 0, 0};
+        if (a.src_on && eps == T(1) && (!MU || mu == T(1))) {
+            const T w = PH ? st.gs * ur - st.gc * ui : plane_wave<T, 2>(a, st, x, y, 0);
+            if (POL == TM) { R[0] = w * a.ehat[2]; R[1] = w * a.hhat[0]; R[2] = w * a.hhat[1]; }
+            else { R[0] = w * a.ehat[0]; R[1] = w * a.ehat[1]; R[2] = w * a.hhat[2]; }
+        }
+        T G[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T F2 = F[k] + F[k];
+            G[k] = fma(sig, R[k] - F2, F2);
+        }
+        const T sc = T(1) - sig, c = T(1) / T(6);
+        T q[11];
+        if (POL == TM) {
+            const T Ez = G[0], Hx = G[1], Hy = G[2];
+            q[0] = Ez - Hy; q[1] = Ez + Hy; q[2] = Ez + Hx; q[3] = Ez - Hx;
+            q[4] = q[5] = q[9] = Hx;
+            q[6] = q[7] = q[10] = Hy;
+            q[8] = Ez;
+        } else {
+            const T Ex = G[0], Ey = G[1], Hz = G[2];
+            q[0] = q[1] = q[8] = Ex;
+            q[2] = Ex - Hz; q[3] = Ex + Hz; q[4] = Ey + Hz; q[5] = Ey - Hz;
+            q[6] = q[7] = q[9] = Ey;
+            q[10] = Hz;
+        }
+#pragma unroll
+        for (int i = 0; i < 11; ++i) f[i] = fma(c, q[i], -(sc * f[i]));
+        return;
     }
     collide2d<T, POL>(F, f);
     if (LREC) {
@@ -814,7 +861,9 @@ __device__ inline void lds_store(T *p, const T (&i)[N]) { store_aligned<T, N>(p,
 template <int TX, int TY>
 __host__ __device__ constexpr int x2_line_n() { return (TX > TY ? TX : TY) + 2; }
 
-template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false>
+// OWN: cell_update2d's MODE for the tile's own cells (1: the tile has layer
+// cells, 2: it has none, 0: decide per cell); ring cells decide per cell.
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false, int OWN = 0>
 __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t,
                                       T *lslab = nullptr) {
     const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
@@ -901,9 +950,10 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             T f[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) f[i] = v[i][k];
-            cell_update2d<T, POL, HIST, true, MU, LINE>(a, s0, xf, yf, e[k], ip[k], sg[k], f,
-                                                        x + k < a.nx && y < a.ny, ur[k], ui[k], mp[k], imp[k],
-                                                        lslab + ((a.line_axis == 0 ? x + k : y) - lu0), NL);
+            cell_update2d<T, POL, HIST, true, MU, LINE, false, OWN>(a, s0, xf, yf, e[k], ip[k], sg[k], f,
+                                                                    x + k < a.nx && y < a.ny, ur[k], ui[k], mp[k],
+                                                                    imp[k], lslab + ((a.line_axis == 0 ? x + k : y) - lu0),
+                                                                    NL);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
             zp[0][k] = f[8];
@@ -1006,9 +1056,10 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
             f[8] = zp[0][k];
             f[9] = zp[1][k];
             f[10] = zp[2][k];
-            cell_update2d<T, POL, HIST, true, MU, LINE>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx, ur[k],
-                                                        ui[k], mp[k], imp[k],
-                                                        lslab + 11 * NL + ((a.line_axis == 0 ? x + k : y) - lu0), NL);
+            cell_update2d<T, POL, HIST, true, MU, LINE, false, OWN>(a, s1, xf, y, ep[k], ip[k], sg[k], f, x + k < a.nx,
+                                                                    ur[k], ui[k], mp[k], imp[k],
+                                                                    lslab + 11 * NL + ((a.line_axis == 0 ? x + k : y) - lu0),
+                                                                    NL);
 #pragma unroll
             for (int i = 0; i < 11; ++i) v[i][k] = f[i];
         }
@@ -1038,8 +1089,14 @@ __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<
     __shared__ X2Lds<T, TX, TY> lds;
     __shared__ T lslab[LINE ? 2 * 11 * x2_line_n<TX, TY>() : 1];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE>(a, lds, (tile % a.tiles_x) * TX, (tile / a.tiles_x) * TY,
-                                                   step_time(a.t_base, a.t_off), lslab);
+    const int x0 = (tile % a.tiles_x) * TX, y0 = (tile / a.tiles_x) * TY;
+    const int64_t t = step_time(a.t_base, a.t_off);
+    // tiles with layer cells take the one-pass collision + layer for every
+    // own cell, the others the plain collision (block-uniform choice)
+    const bool in_layer = (a.W[0] && (x0 < a.W[0] || x0 + TX > a.nx - a.W[0])) ||
+                          (a.W[1] && (y0 < a.W[1] || y0 + TY > a.ny - a.W[1]));
+    if (in_layer) step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE, 1>(a, lds, x0, y0, t, lslab);
+    else step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE, 2>(a, lds, x0, y0, t, lslab);
 }
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).
@@ -1078,8 +1135,11 @@ __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<
         const int inst = tile_inst[w];
         const StepArgs<T> &a = descs[inst];
         const int local = w - tile_first[inst];
-        const int tx = local % a.tiles_x, ty = local / a.tiles_x;
-        step2d_x2_tile<T, POL, TX, TY>(a, lds, tx * TX, ty * TY, t);
+        const int x0 = (local % a.tiles_x) * TX, y0 = (local / a.tiles_x) * TY;
+        const bool in_layer = (a.W[0] && (x0 < a.W[0] || x0 + TX > a.nx - a.W[0])) ||
+                              (a.W[1] && (y0 < a.W[1] || y0 + TY > a.ny - a.W[1]));
+        if (in_layer) step2d_x2_tile<T, POL, TX, TY, false, false, false, 1>(a, lds, x0, y0, t);
+        else step2d_x2_tile<T, POL, TX, TY, false, false, false, 2>(a, lds, x0, y0, t);
         __syncthreads();
     }
 }
