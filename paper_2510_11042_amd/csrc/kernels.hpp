@@ -1225,7 +1225,46 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
         const double G[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
         dft_accumulate<0x3f>(a, st, 3, x, y, z, G);
     }
+    if (!LINE && !LREC && sig > T(0)) {
+        // layer cell: collision and relaxation towards the incident
+        // equilibrium in one pass.  Both are linear in (E, H), so
+        //   f' = (1 - sig)(2 f^eq(E, H) - f) + sig f^eq(E_ref, H_ref)
+        //      = f^eq(G_E, G_H) - (1 - sig) f,   G = 2 F + sig (F_ref - 2 F),
+        // one fused multiply-add per population and no second equilibrium
+        // held in registers
+        T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
+        if (a.src_on && eps == T(1)) {
+            const T w = plane_wave<T, 3>(a, st, x, y, z);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Er[k] = w * a.ehat[k];
+                Hr[k] = w * a.hhat[k];
+            }
+        }
+        T GE[3], GH[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T E2 = E[k] + E[k], H2 = H[k] + H[k];
+            GE[k] = fma(sig, Er[k] - E2, E2);
+            GH[k] = fma(sig, Hr[k] - H2, H2);
+        }
+        const T c = T(1) / T(6), sc = T(1) - sig, r = eps - T(1);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const T cv[3] = {T(C3[d][0]), T(C3[d][1]), T(C3[d][2])};
+            T cxh[3];
+            cross3(cv, GH, cxh);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) f[4 * d + k] = fma(c, GE[k] - cxh[k], -(sc * f[4 * d + k]));
+            f[4 * d + 3] = fma(c, cv[0] * GH[0] + cv[1] * GH[1] + cv[2] * GH[2], -(sc * f[4 * d + 3]));
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[24 + k] = fma(r, GE[k], -(sc * f[24 + k]));
+        return;
+    }
     // collision f <- 2 f^eq - f, one fused multiply-add per population
+    // (for sig = 0 the one-pass form above rounds identically: the factor 2
+    // is exact and 1/6 is 1/3 halved)
     {
         const T c = T(1) / T(3);
         const T r = T(2) * (eps - T(1));
