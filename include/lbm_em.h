@@ -193,7 +193,12 @@ lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
  * its own grid size, permittivity, source and contour.  Results are
  * bit-identical to lbm_em_step on each handle.  Uses the launch settings of
  * hs[0]; with two steps per launch, the tile with the fewest padded cells
- * over all instances (hs[0]'s own tile when it is among the best).
+ * over the batched instances (hs[0]'s own tile when it is among the best).
+ * An instance that fills the device by itself (two steps per launch, here
+ * and on the handle, and at least one of its own two-step tiles per compute
+ * unit) is advanced by the single-instance kernels instead, as a group of
+ * its own: the persistent launch pays only for instances too small to fill
+ * the chip.
  * EUNSUPPORTED for 3-D handles and handles with a permeability map.
  * (One-shot form of the batch calls below.) */
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);
@@ -213,7 +218,8 @@ lbm_em_status lbm_em_batch_step(lbm_em_batch b, int64_t n);
 lbm_em_status lbm_em_batch_set_grid(lbm_em_batch b, int32_t grid);
 /* Cache budget for grouping in bytes; 0 = all instances in one group. */
 lbm_em_status lbm_em_batch_set_cache_budget(lbm_em_batch b, int64_t bytes);
-/* Number of groups of the current plan. */
+/* Number of groups of the current plan (an instance advanced by its own
+ * kernels counts as one group). */
 lbm_em_status lbm_em_batch_groups(lbm_em_batch b, int32_t *groups);
 lbm_em_status lbm_em_batch_destroy(lbm_em_batch b);
 

@@ -123,10 +123,15 @@ struct lbm_em {
 // Instances are packed, in order, into groups whose state fits a cache
 // budget (the 256 MB Infinity Cache by default); each group is advanced the
 // requested number of steps before the next one, so a group's working set
-// stays cache resident.  Instances are independent, so the grouping does
-// not change any result.
+// stays cache resident.  An instance that fills the device on its own (two
+// steps per launch, at least one tile of its own two-step tile per compute
+// unit) forms a group by itself that the single-instance kernels advance:
+// the persistent kernel only pays where instances are too small to fill
+// the chip.  Instances are independent and every kernel runs the same
+// per-cell update, so neither choice changes any result.
 struct BatchGroup {
     int first = 0, count = 0;              // instance range
+    bool direct = false;                   // one instance, stepped by its own kernels
     void *descs[2] = {nullptr, nullptr};   // StepArgs per instance, for buffer parity 0 / 1
     int *tile_inst = nullptr, *tile_first = nullptr;
     int ntiles = 0, grid = 0;
@@ -664,6 +669,14 @@ void free_batch(lbm_em_batch_s *b) {
 }
 
 // (Re)build the groups for the current cache budget and grid setting.
+// The instance fills the device by itself: two steps per launch (like the
+// batch) with at least one of its own two-step tiles per compute unit.
+bool batch_direct(const lbm_em_batch_s *b, const lbm_em *h) {
+    if (b->fuse != 2 || h->fuse != 2) return false;
+    const int64_t tiles = (int64_t)((h->cfg.nx + h->ftx - 1) / h->ftx) * ((h->cfg.ny + h->fty - 1) / h->fty);
+    return tiles >= b->cus;
+}
+
 void plan_batch(lbm_em_batch_s *b) {
     if (b->stream) hip_check(hipStreamSynchronize(b->stream), "sync");
     free_groups(b);
@@ -672,11 +685,19 @@ void plan_batch(lbm_em_batch_s *b) {
     while (i < n) {
         BatchGroup g;
         g.first = i;
+        if (batch_direct(b, b->hs[i])) {
+            g.count = 1;
+            g.direct = true;
+            b->groups.push_back(g);
+            ++i;
+            continue;
+        }
         int64_t bytes = 0;
         do {
             bytes += handle_bytes(b->hs[i]);
             ++i;
-        } while (i < n && (b->budget <= 0 || bytes + handle_bytes(b->hs[i]) <= b->budget));
+        } while (i < n && !batch_direct(b, b->hs[i]) &&
+                 (b->budget <= 0 || bytes + handle_bytes(b->hs[i]) <= b->budget));
         g.count = i - g.first;
         b->groups.push_back(g);
         if (b->precision == LBM_EM_FP32) fill_group<float>(b, b->groups.back());
@@ -713,6 +734,8 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
         b->fuse = h0->fuse;
         b->ftx = h0->ftx;
         b->fty = h0->fty;
+        hip_check(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev), "attribute");
+        b->cus = std::max(1, b->cus);
         if (b->fuse == 2) {
             // Two-step tile of the batch: the fewest padded cells over the
             // instances (small, uneven grids waste much of a large tile);
@@ -722,6 +745,7 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
                 int64_t p = 0;
                 for (int i = 0; i < count; ++i) {
                     const lbm_em *h = hs[i];
+                    if (batch_direct(b, h)) continue;   // advanced by its own kernels
                     p += (int64_t)((h->cfg.nx + tx - 1) / tx) * tx * (int64_t)((h->cfg.ny + ty - 1) / ty) * ty;
                 }
                 return p;
@@ -748,8 +772,6 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
             b->hs.push_back(hs[i]);
             ++hs[i]->batch_refs;
         }
-        hip_check(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev), "attribute");
-        b->cus = std::max(1, b->cus);
         hip_check(hipMalloc(&b->t_dev, 64), "hipMalloc batch");
         plan_batch(b);
     } catch (...) {
@@ -790,6 +812,11 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
         if (h->t != h0->t || h->cur != h0->cur)
             fail(LBM_EM_ESTATE, "batched handles were stepped separately since the batch was made");
     (void)hipSetDevice(b->dev);
+    // a handle's launch shape may have changed since the plan was made
+    bool stale = false;
+    for (const auto &g : b->groups)
+        for (int i = 0; i < g.count; ++i) stale = stale || batch_direct(b, b->hs[g.first + i]) != g.direct;
+    if (stale) plan_batch(b);
     const int64_t t_start = h0->t;
     const int cur_start = h0->cur;
     int64_t t = t_start;
@@ -797,6 +824,10 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
     for (auto &g : b->groups) {
         t = t_start;
         cur = cur_start;
+        if (g.direct) {
+            do_steps(b->hs[g.first], n);
+            continue;
+        }
         int64_t chunks = use_graph ? n / kGraphChunk : 0;
         if (chunks > 0) {
             if (!g.graph[cur]) g.graph[cur] = build_batch_graph(b, g, cur);
@@ -815,9 +846,18 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
             rest -= adv;
         }
     }
+    // the buffer parity after n steps: graph chunks flip it an even number
+    // of times and every other launch once, in the batched and in the
+    // single-instance path alike
+    t = t_start + n;
+    const int64_t rest = use_graph ? n % kGraphChunk : n;
+    cur = cur_start ^ (int)((b->fuse == 2 ? rest / 2 + rest % 2 : rest) & 1);
     for (auto *h : b->hs) {
-        h->t = t;
-        h->cur = cur;
+        if (h->t != t || h->cur != cur) {
+            if (h->t != t_start) fail(LBM_EM_ESTATE, "batched instance left at an unexpected step");
+            h->t = t;
+            h->cur = cur;
+        }
     }
 }
 

@@ -88,6 +88,44 @@ def test_batch_equals_individual(lib, prec, tile, fuse):
     b.close()
 
 
+def test_batch_routes_large_instances_to_their_own_kernels(lib):
+    """An instance with at least one two-step tile per compute unit is
+    advanced by the single-instance kernels as a group of its own; when its
+    launch shape changes the batch re-plans it into the persistent launch.
+    Either way every instance matches individual stepping bit for bit."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 128
+    while (n // 128) * (n // 32) < cus:
+        n += 128
+    steps = 200
+    cases = _cases(91, 2, steps)
+    big = W.cylinder_case(2.25, "TM", n=n, a=25.5, lam=32.0, W=32, steps=steps)
+    cases.append(big)
+    say("batch with a large instance", n, cus, [c.nx for c in cases])
+    solo = [_make(lib, c, "fp32") for c in cases]
+    for s in solo:
+        s.step(steps)
+    grouped = [_make(lib, c, "fp32") for c in cases]
+    grouped[-1].set_fusion(2, (128, 32))
+    b = lib.Batch(grouped)
+    assert b.groups == 2                 # the two small instances, then the large one alone
+    b.step(131)                          # graph chunks, an eager pair and an odd step
+    grouped[-1].set_fusion(1)            # no longer eligible: re-planned into the batch
+    b.step(69)
+    assert b.groups == 1
+    for s, g in zip(solo, grouped):
+        assert g.t == s.t == steps
+        Es, Hs = s.fields()
+        Eg, Hg = g.fields()
+        assert np.array_equal(Es, Eg) and np.array_equal(Hs, Hg)
+        Xs, ps = s.phasors()
+        Xg, pg = g.phasors()
+        assert np.array_equal(Xs, Xg) and np.array_equal(ps, pg)
+    b.close()
+
+
 def test_step_many_and_grid_size(lib):
     cases = _cases(7, 3, 90)
     say("step_many")
