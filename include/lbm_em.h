@@ -218,6 +218,17 @@ lbm_em_status lbm_em_batch_step(lbm_em_batch b, int64_t n);
 lbm_em_status lbm_em_batch_set_grid(lbm_em_batch b, int32_t grid);
 /* Cache budget for grouping in bytes; 0 = all instances in one group. */
 lbm_em_status lbm_em_batch_set_cache_budget(lbm_em_batch b, int64_t bytes);
+/* Autotuner of the batch: times `launches` two-step launches of every
+ * two-step tile over the instances the persistent kernel advances and keeps
+ * the fastest tile (the padded-cell choice of batch_create is a heuristic:
+ * wider tiles move whole 128-byte lines at the cost of padding).  Timed
+ * launches read the current buffers and write the spare ones with the DFT
+ * off, so no instance changes; results after tuning are bit-identical for
+ * every tile.  *best_us (may be NULL): microseconds per step of all batched
+ * instances with the chosen tile, 0 when nothing is timed (one step per
+ * launch, or every instance advanced by its own kernels).  EINVAL for
+ * launches < 1, ESTATE when the handles' time steps have diverged. */
+lbm_em_status lbm_em_batch_autotune(lbm_em_batch b, int32_t launches, double *best_us);
 /* Number of groups of the current plan (an instance advanced by its own
  * kernels counts as one group). */
 lbm_em_status lbm_em_batch_groups(lbm_em_batch b, int32_t *groups);

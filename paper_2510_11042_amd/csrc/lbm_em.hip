@@ -544,14 +544,16 @@ void do_steps(lbm_em *h, int64_t n) {
 
 int64_t handle_bytes(const lbm_em *h) { return (int64_t)h->plane * (2 * h->nplanes + 1) * (int64_t)h->elem; }
 
+// dft = false: descriptors for timing launches (no DFT accumulation).
 template <typename T>
-void fill_group(lbm_em_batch_s *b, BatchGroup &g) {
+void fill_group(lbm_em_batch_s *b, BatchGroup &g, bool dft) {
     std::vector<int> first;
     for (int par = 0; par < 2; ++par) {
         std::vector<StepArgs<T>> d(g.count);
         for (int i = 0; i < g.count; ++i) {
             const lbm_em *h = b->hs[g.first + i];
             d[i] = make_args<T>(h, h->buf[par], h->buf[par ^ 1]);
+            if (!dft) d[i].dft_on = 0;
             if (b->fuse == 2) {
                 d[i].tiles_x = (h->cfg.nx + b->ftx - 1) / b->ftx;
                 d[i].tiles_y = (h->cfg.ny + b->fty - 1) / b->fty;
@@ -677,7 +679,7 @@ bool batch_direct(const lbm_em_batch_s *b, const lbm_em *h) {
     return tiles >= b->cus;
 }
 
-void plan_batch(lbm_em_batch_s *b) {
+void plan_batch(lbm_em_batch_s *b, bool dft = true) {
     if (b->stream) hip_check(hipStreamSynchronize(b->stream), "sync");
     free_groups(b);
     const int n = (int)b->hs.size();
@@ -700,8 +702,8 @@ void plan_batch(lbm_em_batch_s *b) {
                  (b->budget <= 0 || bytes + handle_bytes(b->hs[i]) <= b->budget));
         g.count = i - g.first;
         b->groups.push_back(g);
-        if (b->precision == LBM_EM_FP32) fill_group<float>(b, b->groups.back());
-        else fill_group<double>(b, b->groups.back());
+        if (b->precision == LBM_EM_FP32) fill_group<float>(b, b->groups.back(), dft);
+        else fill_group<double>(b, b->groups.back(), dft);
     }
     hip_check(hipStreamSynchronize(b->stream), "sync");
 }
@@ -1547,6 +1549,77 @@ lbm_em_status lbm_em_batch_set_cache_budget(lbm_em_batch b, int64_t bytes) {
         if (bytes < 0) fail(LBM_EM_EINVAL, "budget must be >= 0");
         b->budget = bytes;
         plan_batch(b);
+    });
+}
+
+lbm_em_status lbm_em_batch_autotune(lbm_em_batch b, int32_t launches, double *best_us) {
+    return guarded([&] {
+        if (!b) fail(LBM_EM_EINVAL, "null batch");
+        if (launches < 1) fail(LBM_EM_EINVAL, "launches must be >= 1");
+        lbm_em *h0 = b->hs[0];
+        for (auto *h : b->hs)
+            if (h->t != h0->t || h->cur != h0->cur)
+                fail(LBM_EM_ESTATE, "batched handles were stepped separately since the batch was made");
+        (void)hipSetDevice(b->dev);
+        std::vector<std::pair<int, int>> cands;
+        if (b->fuse == 2) {
+#define LBM_X2_BCAND(TX, TY) cands.push_back({TX, TY});
+            if (b->precision == LBM_EM_FP32) { LBM_X2_TILES_F32(LBM_X2_BCAND) }
+            else { LBM_X2_TILES_F64(LBM_X2_BCAND) }
+#undef LBM_X2_BCAND
+        }
+        bool timed = false;
+        for (const auto &g : b->groups) timed = timed || !g.direct;
+        const int keep_tx = b->ftx, keep_ty = b->fty;
+        double best = 0.0;
+        if (!cands.empty() && timed) {
+            hipEvent_t e0, e1;
+            hip_check(hipEventCreate(&e0), "hipEventCreate");
+            hip_check(hipEventCreate(&e1), "hipEventCreate");
+            int btx = keep_tx, bty = keep_ty;
+            best = 1e30;
+            try {
+                for (const auto &c : cands) {
+                    b->ftx = c.first;
+                    b->fty = c.second;
+                    plan_batch(b, false);
+                    // timed launches read the current buffers and write the
+                    // spare ones with the DFT off: no state changes
+                    auto run = [&](int reps) {
+                        for (const auto &g : b->groups)
+                            if (!g.direct)
+                                for (int i = 0; i < reps; ++i)
+                                    launch_batch(b, g, h0->cur, nullptr, h0->t, b->stream, 2);
+                    };
+                    run(1);
+                    hip_check(hipEventRecord(e0, b->stream), "hipEventRecord");
+                    run(launches);
+                    hip_check(hipEventRecord(e1, b->stream), "hipEventRecord");
+                    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0.f;
+                    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    const double us = 1e3 * (double)ms / launches / 2;   // per step, all batched instances
+                    if (us < best) {
+                        best = us;
+                        btx = c.first;
+                        bty = c.second;
+                    }
+                }
+            } catch (...) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                b->ftx = keep_tx;
+                b->fty = keep_ty;
+                plan_batch(b);
+                throw;
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            b->ftx = btx;
+            b->fty = bty;
+        }
+        plan_batch(b);
+        if (best_us) *best_us = best;
     });
 }
 

@@ -337,6 +337,14 @@ class Batch:
     def set_grid(self, blocks):
         L.check(L.lib().lbm_em_batch_set_grid(self._b, int(blocks)))
 
+    def autotune(self, launches=10):
+        """Time every two-step tile on the batched instances (no state
+        change) and keep the fastest; returns microseconds per step of all
+        batched instances (see lbm_em_batch_autotune)."""
+        us = C.c_double()
+        L.check(L.lib().lbm_em_batch_autotune(self._b, int(launches), C.byref(us)))
+        return us.value
+
     def set_cache_budget(self, nbytes):
         """Group instances so each group's state fits nbytes (0: one group)."""
         L.check(L.lib().lbm_em_batch_set_cache_budget(self._b, int(nbytes)))

@@ -126,6 +126,36 @@ def test_batch_routes_large_instances_to_their_own_kernels(lib):
     b.close()
 
 
+def test_batch_autotune_keeps_state_and_results(lib):
+    """Tuning the batch's tile changes no instance, and stepping with the
+    chosen tile still reproduces individual stepping bit for bit (DFT
+    window included)."""
+    steps = 200
+    cases = _cases(5, 4, steps)
+    say("batch autotune", [c.nx for c in cases])
+    solo = [_make(lib, c, "fp32") for c in cases]
+    for s in solo:
+        s.step(steps)
+    grouped = [_make(lib, c, "fp32") for c in cases]
+    b = lib.Batch(grouped)
+    b.step(110)                          # tune mid-run, inside no DFT window yet
+    before = [g.fields() for g in grouped]
+    us = b.autotune(launches=3)
+    assert us > 0
+    for g, (E, H) in zip(grouped, before):
+        assert g.t == 110
+        E2, H2 = g.fields()
+        assert np.array_equal(E, E2) and np.array_equal(H, H2)
+    b.step(steps - 110)
+    for s, g in zip(solo, grouped):
+        assert g.t == s.t == steps
+        assert np.array_equal(s.fields()[0], g.fields()[0]) and np.array_equal(s.fields()[1], g.fields()[1])
+        Xs, ps = s.phasors()
+        Xg, pg = g.phasors()
+        assert np.array_equal(Xs, Xg) and np.array_equal(ps, pg)
+    b.close()
+
+
 def test_step_many_and_grid_size(lib):
     cases = _cases(7, 3, 90)
     say("step_many")
