@@ -198,7 +198,10 @@ lbm_em_status lbm_em_step(lbm_em_handle h, int64_t n);
  * and on the handle, and at least one of its own two-step tiles per compute
  * unit) is advanced by the single-instance kernels instead, as a group of
  * its own: the persistent launch pays only for instances too small to fill
- * the chip.
+ * the chip.  Two or more such instances alternate over two side streams
+ * that the batch forks from the handles' stream and joins back into it
+ * within the call, so two independent kernels overlap; work queued on the
+ * handles' stream afterwards sees every instance advanced.
  * EUNSUPPORTED for 3-D handles and handles with a permeability map.
  * (One-shot form of the batch calls below.) */
 lbm_em_status lbm_em_step_many(const lbm_em_handle *hs, int32_t count, int64_t n);

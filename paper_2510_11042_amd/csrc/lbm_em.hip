@@ -147,6 +147,11 @@ struct lbm_em_batch_s {
     hipStream_t stream = nullptr;
     int dev = 0, cus = 1, grid_override = 0;
     int64_t budget = 0;
+    // instances on their own kernels alternate over two side streams forked
+    // from and joined back into `stream`: two independent step kernels
+    // overlap each other's load, compute and store phases
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -511,15 +516,17 @@ hipGraphExec_t build_graph(lbm_em *h, int p) {
     return ge;
 }
 
-void do_steps(lbm_em *h, int64_t n) {
+// `on`: the stream to order the work on (default: the handle's own).
+void do_steps(lbm_em *h, int64_t n, hipStream_t on = nullptr) {
     select_device(h);
+    hipStream_t st = on ? on : h->stream;
     int64_t chunks = n / kGraphChunk;
     if (chunks > 0) {
         if (!h->graph[h->cur]) h->graph[h->cur] = build_graph(h, h->cur);
-        hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, h->stream, h->t_dev, h->t);
+        hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, st, h->t_dev, h->t);
         hip_check(hipGetLastError(), "k_set_time");
         for (int64_t c = 0; c < chunks; ++c) {
-            hip_check(hipGraphLaunch(h->graph[h->cur], h->stream), "hipGraphLaunch");
+            hip_check(hipGraphLaunch(h->graph[h->cur], st), "hipGraphLaunch");
             // a chunk flips the buffers an even number of times (32 fused
             // or 64 single launches): the parity is unchanged
         }
@@ -528,14 +535,14 @@ void do_steps(lbm_em *h, int64_t n) {
     int64_t rest = n - chunks * kGraphChunk;
     if (h->fuse == 2) {
         for (; rest >= 2; rest -= 2) {
-            launch_step2(h, h->cur, nullptr, h->t, h->stream);
+            launch_step2(h, h->cur, nullptr, h->t, st);
             hip_check(hipGetLastError(), "fused step kernel launch");
             h->cur ^= 1;
             h->t += 2;
         }
     }
     for (int64_t k = 0; k < rest; ++k) {
-        launch_step(h, h->cur, nullptr, h->t, h->stream);
+        launch_step(h, h->cur, nullptr, h->t, st);
         hip_check(hipGetLastError(), "step kernel launch");
         h->cur ^= 1;
         h->t += 1;
@@ -666,6 +673,12 @@ void free_batch(lbm_em_batch_s *b) {
     else (void)hipDeviceSynchronize();
     free_groups(b);
     hfree(b->t_dev);
+    for (int k = 0; k < 2; ++k) {
+        if (b->side[k]) (void)hipStreamSynchronize(b->side[k]);
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     for (lbm_em *h : b->hs) --h->batch_refs;
     delete b;
 }
@@ -823,11 +836,24 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
     const int cur_start = h0->cur;
     int64_t t = t_start;
     int cur = cur_start;
+    int ndirect = 0;
+    for (const auto &g : b->groups) ndirect += g.direct ? 1 : 0;
+    const bool two = ndirect >= 2 && n > 0;
+    if (two) {
+        for (int k = 0; k < 2; ++k) {
+            if (!b->side[k]) hip_check(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking), "hipStreamCreate");
+            if (!b->join[k]) hip_check(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming), "hipEventCreate");
+        }
+        if (!b->fork) hip_check(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventRecord(b->fork, b->stream), "hipEventRecord");
+        for (int k = 0; k < 2; ++k) hip_check(hipStreamWaitEvent(b->side[k], b->fork, 0), "hipStreamWaitEvent");
+    }
+    int jd = 0;
     for (auto &g : b->groups) {
         t = t_start;
         cur = cur_start;
         if (g.direct) {
-            do_steps(b->hs[g.first], n);
+            do_steps(b->hs[g.first], n, two ? b->side[jd++ & 1] : nullptr);
             continue;
         }
         int64_t chunks = use_graph ? n / kGraphChunk : 0;
@@ -848,6 +874,11 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
             rest -= adv;
         }
     }
+    if (two)
+        for (int k = 0; k < 2; ++k) {
+            hip_check(hipEventRecord(b->join[k], b->side[k]), "hipEventRecord");
+            hip_check(hipStreamWaitEvent(b->stream, b->join[k], 0), "hipStreamWaitEvent");
+        }
     // the buffer parity after n steps: graph chunks flip it an even number
     // of times and every other launch once, in the batched and in the
     // single-instance path alike

@@ -126,6 +126,42 @@ def test_batch_routes_large_instances_to_their_own_kernels(lib):
     b.close()
 
 
+def test_batch_overlaps_large_instances_on_two_streams(lib):
+    """Several instances on their own kernels run on two side streams of
+    the batch; each still matches individual stepping bit for bit, and the
+    batch's stream has joined them when the step call returns."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 128
+    while (n // 128) * (n // 32) < cus:
+        n += 128
+    steps = 200
+    cases = [W.cylinder_case(e, "TM", n=n, a=25.5, lam=32.0, W=32, steps=steps) for e in (1.5, 2.25, 4.0)]
+    cases.insert(1, _cases(13, 1, steps)[0])
+    say("batch with three large instances", n, cus, [c.nx for c in cases])
+    solo = [_make(lib, c, "fp32") for c in cases]
+    for s in solo:
+        s.step(steps)
+    grouped = [_make(lib, c, "fp32") for c in cases]
+    for g, c in zip(grouped, cases):
+        if c.nx == n:
+            g.set_fusion(2, (128, 32))
+    b = lib.Batch(grouped)
+    assert b.groups == 4
+    b.step(131)
+    b.step(69)
+    for s, g in zip(solo, grouped):
+        assert g.t == s.t == steps
+        Es, Hs = s.fields()
+        Eg, Hg = g.fields()
+        assert np.array_equal(Es, Eg) and np.array_equal(Hs, Hg)
+        Xs, ps = s.phasors()
+        Xg, pg = g.phasors()
+        assert np.array_equal(Xs, Xg) and np.array_equal(ps, pg)
+    b.close()
+
+
 def test_batch_autotune_keeps_state_and_results(lib):
     """Tuning the batch's tile changes no instance, and stepping with the
     chosen tile still reproduces individual stepping bit for bit (DFT
