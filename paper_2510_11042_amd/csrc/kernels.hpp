@@ -2039,7 +2039,7 @@ struct AdjWeightArgs {
     double *G;             // (nnodes) x 6 x (re, im)
 };
 
-__global__ void k_adjoint_weights2d(AdjWeightArgs a) {
+static __global__ void k_adjoint_weights2d(AdjWeightArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.nnodes) return;
     const Box &b = a.box;
@@ -2166,7 +2166,7 @@ __global__ void k_fill(T *p, int64_t n, T v) {
 
 // Plain streaming copy, 16 bytes per thread (measured bandwidth ceiling and
 // counter calibration).
-__global__ void __launch_bounds__(256) k_copy16(const float4 *__restrict__ a, float4 *__restrict__ b, int64_t n) {
+static __global__ void __launch_bounds__(256) k_copy16(const float4 *__restrict__ a, float4 *__restrict__ b, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
 }
@@ -2179,10 +2179,10 @@ __global__ void k_compare(const T *a, const T *b, int64_t n, int *flag) {
 }
 
 // Device step counter for graph replays (vector store from one lane).
-__global__ void k_set_time(int64_t *t, int64_t value) {
+static __global__ void k_set_time(int64_t *t, int64_t value) {
     if (threadIdx.x == 0) t[0] = value;
 }
-__global__ void k_advance_time(int64_t *t, int64_t by) {
+static __global__ void k_advance_time(int64_t *t, int64_t by) {
     if (threadIdx.x == 0) t[0] = t[0] + by;
 }
 
@@ -2214,7 +2214,7 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__global__ void __launch_bounds__(256) k_ntff(NtffArgs a) {
+static __global__ void __launch_bounds__(256) k_ntff(NtffArgs a) {
     const int ang = blockIdx.x;
     const double th = a.theta[ang], ph = a.phi[ang];
     const double ct = cos(th), st = sin(th), cp = cos(ph), sp = sin(ph);

@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/lbm_em.h"
-#include "kernels.hpp"
+#include "launch.hpp"
 
 using namespace lbm;
 
@@ -221,37 +221,6 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     return a;
 }
 
-template <typename T, int VX>
-void launch_step_vx(const StepArgs<T> &a, const lbm_em *h, hipStream_t s) {
-    dim3 block(h->bx, h->by, 1);
-    const int gx = (h->cfg.nx + VX - 1) / VX;
-    dim3 grid((unsigned)((gx + h->bx - 1) / h->bx), (unsigned)((h->cfg.ny + h->by - 1) / h->by),
-              (unsigned)h->cfg.nz);
-    const bool rec = a.hist != nullptr;
-    if (rec && (a.mu || a.line_tab)) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1 and no incident line");
-    if (a.mu && a.line_tab) {
-        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step2d<T, TE, VX, false, true, true>), grid, block, 0, s, a);
-    } else if (a.mu) {
-        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, true>), grid, block, 0, s, a);
-        else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_step2d<T, TE, VX, false, true>), grid, block, 0, s, a);
-        else fail(LBM_EM_EUNSUPPORTED, "a permeability map needs a 2-D (TM/TE) handle");
-    } else if (a.line_tab && h->dim == 2) {
-        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_step2d<T, TM, VX, false, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step2d<T, TE, VX, false, false, true>), grid, block, 0, s, a);
-    } else if (h->cfg.pol == LBM_EM_TM) {
-        if (rec) hipLaunchKernelGGL((k_step2d<T, TM, VX, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step2d<T, TM, VX>), grid, block, 0, s, a);
-    } else if (h->cfg.pol == LBM_EM_TE) {
-        if (rec) hipLaunchKernelGGL((k_step2d<T, TE, VX, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step2d<T, TE, VX>), grid, block, 0, s, a);
-    } else if (a.line_tab) {
-        hipLaunchKernelGGL((k_step3d<T, VX, true>), grid, block, 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_step3d<T, VX>), grid, block, 0, s, a);
-    }
-}
-
 template <typename T>
 void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base,
                    int64_t t_off, hipStream_t s, bool dft, void *hist, int64_t hist_t0) {
@@ -267,9 +236,9 @@ void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t
             a.dhi[k] = h->dhi[k];
         }
     }
-    if (h->vx == 1) launch_step_vx<T, 1>(a, h, s);
-    else if (h->vx == 2) launch_step_vx<T, 2>(a, h, s);
-    else if constexpr (sizeof(T) == 4) launch_step_vx<T, 4>(a, h, s);
+    if (hist && (a.mu || a.line_tab)) fail(LBM_EM_EUNSUPPORTED, "the adjoint needs mu_r = 1 and no incident line");
+    if (a.mu && h->dim != 2) fail(LBM_EM_EUNSUPPORTED, "a permeability map needs a 2-D (TM/TE) handle");
+    launch_step1<T>(a, h->cfg.pol, h->vx, h->bx, h->by, s);
 }
 
 // Largest line (in cells) whose state the LDS kernels hold: 64 KB of LDS,
@@ -346,43 +315,7 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
     else launch_step_t<double>(h, src, dst, t_base, t_off, s, dft, hist, hist_t0);
 }
 
-// Two steps in one launch (2-D): reads src, writes f*(t+1) to dst.
-// Two-step tiles: TX x TY cells, TX a multiple of the 16-byte segment, one
-// segment per thread and 256, 512 or 1024 threads (see x2_tile_ok).
-#define LBM_X2_TILES_F32(M) M(64, 16) M(128, 8) M(128, 16) M(256, 8) M(256, 16) M(128, 32)
-#define LBM_X2_TILES_F64(M) M(32, 16) M(64, 8) M(64, 16) M(128, 8) M(128, 16) M(64, 32)
-
-template <typename T, int POL>
-void launch_step2_pol(StepArgs<T> a, int tx, int ty, hipStream_t s) {
-    a.tiles_x = (a.nx + tx - 1) / tx;
-    a.tiles_y = (a.ny + ty - 1) / ty;
-    dim3 grid((unsigned)(a.tiles_x * a.tiles_y), 1, 1);
-#define LBM_X2(TX, TY) \
-    if (tx == TX && ty == TY) {                                                                              \
-        if (a.hist)                                                                                          \
-            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
-        else if (a.mu && a.line_tab)                                                                         \
-            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, true, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
-        else if (a.mu)                                                                                       \
-            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
-        else if (a.line_tab)                                                                                 \
-            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY, false, false, true>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a); \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_step2d_x2<T, POL, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, s, a);  \
-        return;                                                                                              \
-    }
-    if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_X2) }
-    else { LBM_X2_TILES_F64(LBM_X2) }
-#undef LBM_X2
-    fail(LBM_EM_EINVAL, "unsupported two-step tile");
-}
-
-// 3-D two-step tiles (one cell per thread; the LDS holds two planes of the
-// tile's x/y movers: 136 KB for 64 x 16 FP32 and 32 x 16 FP64, 148 KB for
-// 256 x 4 FP32 and 128 x 4 FP64).  Wide tiles spend fewer 128-byte lines on
-// the ring columns.
-#define LBM_X3_TILES_F32(M) M(64, 16) M(64, 8) M(32, 16) M(128, 8) M(256, 4)
-#define LBM_X3_TILES_F64(M) M(32, 16) M(32, 8) M(16, 16) M(64, 8) M(128, 4)
+// Two steps in one launch: reads src, writes f*(t+1) to dst.
 
 // z chunk of the 3-D two-step kernel: each block marches zc planes plus two
 // extra ones; pick the chunk count that minimises rounds x (zc + 2).
@@ -409,19 +342,14 @@ void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
     a.tiles_y = (a.ny + ty - 1) / ty;
     const int tiles = a.tiles_x * a.tiles_y;
     const int zc = x3_chunk(a.nz, tiles, h->cus * std::max(1, 1024 / (tx * ty)));
-    dim3 grid((unsigned)(tiles * ((a.nz + zc - 1) / zc)), 1, 1);
-#define LBM_X3(TX, TY)                                                                      \
-    if (tx == TX && ty == TY) {                                                             \
-        if (a.line_tab)                                                                     \
-            hipLaunchKernelGGL((k_step3d_x2<T, TX, TY, true>), grid, dim3(TX * TY), 0, s, a, zc); \
-        else                                                                                \
-            hipLaunchKernelGGL((k_step3d_x2<T, TX, TY>), grid, dim3(TX * TY), 0, s, a, zc); \
-        return;                                                                             \
-    }
-    if constexpr (sizeof(T) == 4) { LBM_X3_TILES_F32(LBM_X3) }
-    else { LBM_X3_TILES_F64(LBM_X3) }
-#undef LBM_X3
-    fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
+    if (!launch_step3d_x2<T>(a, tx, ty, zc, s)) fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
+}
+
+template <typename T>
+void launch_step2_2d(StepArgs<T> a, int pol, int tx, int ty, hipStream_t s) {
+    a.tiles_x = (a.nx + tx - 1) / tx;
+    a.tiles_y = (a.ny + ty - 1) / ty;
+    if (!launch_step2d_x2<T>(a, pol, tx, ty, s)) fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
 
 template <typename T>
@@ -439,8 +367,7 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
             a.dhi[k] = h->dhi[k];
         }
     }
-    if (h->cfg.pol == LBM_EM_TM) launch_step2_pol<T, TM>(a, h->ftx, h->fty, s);
-    else if (h->cfg.pol == LBM_EM_TE) launch_step2_pol<T, TE>(a, h->ftx, h->fty, s);
+    if (h->cfg.pol == LBM_EM_TM || h->cfg.pol == LBM_EM_TE) launch_step2_2d<T>(a, h->cfg.pol, h->ftx, h->fty, s);
     else launch_step2_3d<T>(h, a, s);
 }
 
@@ -595,63 +522,26 @@ void fill_group(lbm_em_batch_s *b, BatchGroup &g, bool dft) {
     g.grid = std::min(g.ntiles, b->grid_override > 0 ? b->grid_override : b->cus * 32);
 }
 
-template <typename T, int VX>
-void launch_batch_vx(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
-                     hipStream_t s) {
-    dim3 block(b->bx, b->by, 1);
-    const StepArgs<T> *d = (const StepArgs<T> *)g.descs[par];
-    if (b->pol == LBM_EM_TM)
-        hipLaunchKernelGGL((k_step2d_batch<T, TM, VX>), dim3(g.grid), block, 0, s, d, g.tile_inst, g.tile_first,
-                           g.ntiles, t_base, t_off);
-    else
-        hipLaunchKernelGGL((k_step2d_batch<T, TE, VX>), dim3(g.grid), block, 0, s, d, g.tile_inst, g.tile_first,
-                           g.ntiles, t_base, t_off);
-}
-
-template <typename T, int POL>
-void launch_batch_x2_pol(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
-                         hipStream_t s, bool two) {
-    const StepArgs<T> *d = (const StepArgs<T> *)g.descs[par];
-#define LBM_X2B(TX, TY)                                                                                        \
-    if (b->ftx == TX && b->fty == TY) {                                                                         \
-        if (two)                                                                                                \
-            hipLaunchKernelGGL((k_step2d_x2_batch<T, POL, TX, TY>), dim3(g.grid), dim3(x2_threads<T, TX, TY>()), \
-                               0, s, d, g.tile_inst, g.tile_first, g.ntiles, t_base, t_off);                   \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_step2d_tile_batch<T, POL, TX, TY>), dim3(g.grid), dim3(x2_threads<T, TX, TY>()), \
-                               0, s, d,                                                                        \
-                               g.tile_inst, g.tile_first, g.ntiles, t_base, t_off);                            \
-        return;                                                                                                \
-    }
-    if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_X2B) }
-    else { LBM_X2_TILES_F64(LBM_X2B) }
-#undef LBM_X2B
-    fail(LBM_EM_EINVAL, "unsupported two-step tile");
-}
-
 // One launch of the batch.  With fused tiles (b->fuse == 2) `steps` is 2
 // (two-step kernel) or 1 (a single step on the same tiles).
+template <typename T>
+void launch_batch_t(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
+                    hipStream_t s, int steps) {
+    const StepArgs<T> *d = (const StepArgs<T> *)g.descs[par];
+    if (b->fuse == 2) {
+        if (!launch_batch_x2<T>(d, b->pol, b->ftx, b->fty, steps != 1, g.grid, g.tile_inst, g.tile_first, g.ntiles,
+                                t_base, t_off, s))
+            fail(LBM_EM_EINVAL, "unsupported two-step tile");
+    } else {
+        launch_batch1<T>(d, b->pol, b->vx, b->bx, b->by, g.grid, g.tile_inst, g.tile_first, g.ntiles, t_base, t_off,
+                         s);
+    }
+}
+
 void launch_batch(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
                   hipStream_t s, int steps = 0) {
-    if (b->fuse == 2) {
-        const bool two = steps != 1;
-        if (b->precision == LBM_EM_FP32) {
-            if (b->pol == LBM_EM_TM) launch_batch_x2_pol<float, TM>(b, g, par, t_base, t_off, s, two);
-            else launch_batch_x2_pol<float, TE>(b, g, par, t_base, t_off, s, two);
-        } else {
-            if (b->pol == LBM_EM_TM) launch_batch_x2_pol<double, TM>(b, g, par, t_base, t_off, s, two);
-            else launch_batch_x2_pol<double, TE>(b, g, par, t_base, t_off, s, two);
-        }
-        return;
-    }
-    if (b->precision == LBM_EM_FP32) {
-        if (b->vx == 1) launch_batch_vx<float, 1>(b, g, par, t_base, t_off, s);
-        else if (b->vx == 2) launch_batch_vx<float, 2>(b, g, par, t_base, t_off, s);
-        else launch_batch_vx<float, 4>(b, g, par, t_base, t_off, s);
-    } else {
-        if (b->vx == 1) launch_batch_vx<double, 1>(b, g, par, t_base, t_off, s);
-        else launch_batch_vx<double, 2>(b, g, par, t_base, t_off, s);
-    }
+    if (b->precision == LBM_EM_FP32) launch_batch_t<float>(b, g, par, t_base, t_off, s, steps);
+    else launch_batch_t<double>(b, g, par, t_base, t_off, s, steps);
 }
 
 void free_groups(lbm_em_batch_s *b) {
@@ -1026,29 +916,13 @@ void launch_adjoint(const lbm_em *h, const void *src, void *dst, int64_t t, cons
         a.dhi[k] = h->dhi[k];
     }
     if (!hist_prev) {
-        dim3 block(64, 4, 1);
-        dim3 grid((h->cfg.nx + 63) / 64, (h->cfg.ny + 3) / 4, 1);
-        if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_adjoint2d<T, TM>), grid, block, 0, h->stream, a);
-        else hipLaunchKernelGGL((k_adjoint2d<T, TE>), grid, block, 0, h->stream, a);
+        launch_adjoint1<T>(a, h->cfg.pol, h->stream);
         return;
     }
     // two steps (t, t - 1) on the handle's two-step tile
     a.hist_prev = (const T *)hist_prev;
-    const int tx = h->ftx, ty = h->fty;
-    a.tiles_x = (a.nx + tx - 1) / tx;
-    dim3 grid((unsigned)(a.tiles_x * ((a.ny + ty - 1) / ty)), 1, 1);
-#define LBM_ADJ2(TX, TY)                                                                                        \
-    if (tx == TX && ty == TY) {                                                                                 \
-        if (h->cfg.pol == LBM_EM_TM)                                                                            \
-            hipLaunchKernelGGL((k_adjoint2d_x2<T, TM, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, h->stream, a); \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_adjoint2d_x2<T, TE, TX, TY>), grid, dim3(x2_threads<T, TX, TY>()), 0, h->stream, a); \
-        return;                                                                                                 \
-    }
-    if constexpr (sizeof(T) == 4) { LBM_X2_TILES_F32(LBM_ADJ2) }
-    else { LBM_X2_TILES_F64(LBM_ADJ2) }
-#undef LBM_ADJ2
-    fail(LBM_EM_EINVAL, "unsupported two-step tile");
+    a.tiles_x = (a.nx + h->ftx - 1) / h->ftx;
+    if (!launch_adjoint_x2<T>(a, h->cfg.pol, h->ftx, h->fty, h->stream)) fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
 
 void free_handle(lbm_em *h);
