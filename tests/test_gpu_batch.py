@@ -233,3 +233,48 @@ def test_batch_rejects_mismatched_handles(lib):
     g[1].set_source(c[1].lam, [1.0, 0, 0], [0, 0, 1.0], 1.0, 1.0)
     for s in g:
         s.close()
+
+
+def _full_size(P, cases, prec="fp32"):
+    out = []
+    for c in cases:
+        kh, eh = W.plane_wave_2d(c.theta_deg, c.pol)
+        s = P.Simulation(c.nx, c.ny, 1, pol=c.pol, precision=prec, absorb=c.absorb, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(c.eps)
+        s.set_source(c.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+        s.set_ntff(c.box_lo, c.box_hi, *c.window)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("stress", [False, True])
+def test_seeded_64_instance_batch_equals_individual(lib, stress):
+    """The batched configuration at its real sizes: the 64 seeded instances
+    (sides 256..448; with stress=True sides drawn from 256..1536, 70 M
+    cells), the batch's own tuned tile, 330 steps (graph chunks, an odd
+    tail, the DFT window at steps 231..329 or the instance's last period)
+    against the same instances stepped one by one, bit for bit."""
+    steps = 330
+    cases = W.batch_cases(64, steps=steps, stress=stress)
+    say("64-instance batch", "stress" if stress else "seeded", sum(c.nx * c.ny for c in cases))
+    solo = _full_size(lib, cases)
+    for s in solo:
+        s.step(steps)
+    grouped = _full_size(lib, cases)
+    b = lib.Batch(grouped)
+    b.autotune()
+    say("groups", b.groups)
+    b.step(steps - 1)
+    b.step(1)
+    for i, (s, g) in enumerate(zip(solo, grouped)):
+        assert g.t == s.t == steps
+        Es, Hs = s.fields()
+        Eg, Hg = g.fields()
+        assert np.array_equal(Es, Eg) and np.array_equal(Hs, Hg), i
+        Xs, ps = s.phasors()
+        Xg, pg = g.phasors()
+        assert np.array_equal(Xs, Xg) and np.array_equal(ps, pg), i
+        s.close()
+    b.close()
+    for g in grouped:
+        g.close()

@@ -13,6 +13,7 @@ import pytest
 import workloads as W
 from oracle import ntff, run
 from oracle.core import Oracle
+from paritycheck import assert_intensity
 
 pytestmark = pytest.mark.gpu
 
@@ -231,9 +232,7 @@ def test_cylinder_pipeline_phasors_and_intensity(gpu, pol):
         assert perr <= ptol
         assert np.abs(probe - tot_o["probe"]).max() <= ptol * scale
         S_g = tot_g.farfield(th, incident=inc_g)
-        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
-        say(pol, prec, "|S|^2 normalised rms err", serr)
-        assert serr <= stol
+        assert_intensity(S_g, S_o, stol, f"pipeline {pol} {prec}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -258,9 +257,7 @@ def test_three_d_pipeline_intensity(gpu, prec):
     for phi in (0.0, 45.0, 90.0):
         S_o = run.intensity_3d(case, tot_o, inc_o, th, np.full_like(th, phi))
         S_g = sims[0].farfield(th, np.full_like(th, phi), incident=sims[1])
-        err = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
-        say("3d phi", phi, prec, err)
-        assert err <= (1e-10 if prec == "fp64" else 1e-3)
+        assert_intensity(S_g, S_o, 1e-10 if prec == "fp64" else 1e-3, f"3d phi {phi} {prec}")
 
 
 @pytest.mark.parametrize("pol", ["TM", "TE"])
@@ -512,9 +509,7 @@ def test_magnetic_cylinder_pipeline_intensity(gpu, pol):
         say(pol, prec, "magnetic phasor err", perr)
         assert perr <= ptol
         S_g = tot_g.farfield(th, incident=inc_g)
-        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
-        say(pol, prec, "magnetic |S|^2 normalised rms err", serr)
-        assert serr <= stol
+        assert_intensity(S_g, S_o, stol, f"magnetic {pol} {prec}")
 
 
 def test_permeability_api_limits(gpu):
@@ -660,9 +655,7 @@ def test_pec_cylinder_pipeline_intensity(gpu):
         say(prec, "pec phasor err", perr)
         assert perr <= ptol
         S_g = tot_g.farfield(th, incident=inc_g)
-        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
-        say(prec, "pec |S|^2 normalised rms err", serr)
-        assert serr <= stol
+        assert_intensity(S_g, S_o, stol, f"pec {prec}")
 
 
 def test_pec_api_limits(gpu):
@@ -820,9 +813,7 @@ def test_incident_line_cylinder_intensity(gpu, pol):
         s.set_incident_line(True)
         s.step(case.steps)
         S_g = s.farfield(th)
-        serr = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
-        say(pol, prec, "line |S|^2 vs oracle", serr)
-        assert serr <= stol
+        assert_intensity(S_g, S_o, stol, f"line {pol} {prec}")
         if prec == "fp32":
             tot = _gpu_case(gpu, case, prec)
             inc = _gpu_case(gpu, W.vacuum_companion(case), prec)
@@ -973,9 +964,7 @@ def test_incident_line_3d_matches_oracle(gpu, prec):
     for phi in (0.0, 90.0):
         S_o = run.intensity_3d(case, tot_o, inc_o, th, np.full_like(th, phi))
         S_g = s.farfield(th, np.full_like(th, phi))
-        err = np.sqrt(np.mean((S_g - S_o) ** 2)) / S_o.max()
-        say("3d line phi", phi, prec, err)
-        assert err <= (1e-10 if prec == "fp64" else 1e-3)
+        assert_intensity(S_g, S_o, 1e-10 if prec == "fp64" else 1e-3, f"3d line phi {phi} {prec}")
     s.close()
 
 
