@@ -273,6 +273,8 @@ class Simulation:
     def forward_checkpointed(self, n):
         J = C.c_double()
         L.check(L.lib().lbm_em_forward_checkpointed(self._h, int(n), C.byref(J)))
+        # the handle keeps only the latest forward pass for lbm_em_backward
+        self._forward_version = getattr(self, "_forward_version", 0) + 1
         return J.value
 
     def backward(self, device=False):
@@ -383,12 +385,19 @@ def far_field_objective():
             sim.set_permittivity(full)
             J = sim.forward_checkpointed(steps)
             ctx.sim = sim
+            ctx.version = sim._forward_version
             ctx.dev = eps_design.device
             ctx.dtype = eps_design.dtype
             return torch.tensor(J, dtype=torch.float64, device=eps_design.device)
 
         @staticmethod
         def backward(ctx, gJ):
+            # the library holds the adjoint state of the handle's latest
+            # forward pass only: a later forward (another J on the same
+            # handle) would silently give that pass's gradient
+            if getattr(ctx.sim, "_forward_version", None) != ctx.version:
+                raise RuntimeError("FarFieldIntensity.backward: the simulation ran another forward pass after "
+                                   "this one; its gradient is no longer available")
             g = ctx.sim.backward(device=ctx.dev.type == "cuda")
             g = torch.as_tensor(g, device=ctx.dev, dtype=torch.float64) * gJ
             return g.to(ctx.dtype), None, None, None

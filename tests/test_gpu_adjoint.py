@@ -64,7 +64,8 @@ def test_adjoint_matches_oracle_adjoint(P, pol):
     obj = FarFieldObjective(case, th, sigma_max=W.SIGMA_MAX, ramp_periods=1.0)
     J_o, g_o = obj.value_and_gradient(case.eps)
     g_o = g_o[0, 16:24, 16:24]
-    for prec, tol in (("fp64", 1e-9), ("fp32", 2e-3)):
+    # FP32: the stated 1e-3 gradient bar, tightened to 1e-4 (measured ~7e-6)
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
         inc, tot = _pair(P, case, prec, 1.0, theta=th, design=((16, 16), (23, 23)))
         J = tot.forward_checkpointed(case.steps)
         g = tot.backward()
@@ -129,6 +130,26 @@ def test_autograd_function(P):
     g2 = tot2.backward()
     assert abs(J.item() - J2) <= 1e-14 * J2
     assert np.allclose(d.grad.cpu().numpy(), g2, rtol=0, atol=1e-14 * np.abs(g2).max())
+
+
+def test_autograd_refuses_a_stale_forward(P):
+    """Two forward passes on one handle before backward: the first J's
+    backward must raise instead of returning the second pass's gradient."""
+    import torch
+
+    case = _tiny_case()
+    th = np.arange(10.0, 20.01, 0.5)
+    inc, tot = _pair(P, case, "fp64", 1.0, theta=th, design=((16, 16), (23, 23)))
+    F = P.far_field_objective()
+    full = torch.tensor(case.eps, dtype=torch.float64, device="cuda")
+    d1 = full[0, 16:24, 16:24].clone().requires_grad_(True)
+    d2 = (full[0, 16:24, 16:24] * 1.01).clone().requires_grad_(True)
+    J1 = F.apply(d1, tot, full, case.steps)
+    J2 = F.apply(d2, tot, full, case.steps)
+    with pytest.raises(RuntimeError, match="another forward pass"):
+        J1.backward()
+    J2.backward()
+    assert torch.isfinite(d2.grad).all() and d2.grad.abs().max() > 0
 
 
 def _fd(P, case, eps, th, design, cells, h, steps):
