@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the electromagnetic lattice Boltzmann hot path on one MI355X.
 
-One benchmark step = the whole 2-D circular-cylinder workload: grid 1024 x
-1024, radius 25.5 cells (x = 5), lambda = 32, 32-cell absorbing layer, 8000
-time steps with the last-period contour DFT, for eps_r in {1.5, 2.25, 4.0}
-and TM and TE incidence, plus the eps_r = 1 companion run of each
-polarisation, followed by the near-to-far-field transform at 0.5 degree
-resolution (720 angles) for the six scatterers.  FP32 state and arithmetic,
-FP64 DFT accumulators.  Inputs are resident in device memory before timing.
+One benchmark step = the 3-D dielectric-sphere workload (section 3.4):
+a sphere of size parameter x = 6 at lambda = 24 cells (a = 22.92), eps_r =
+2.25, plane wave along +z polarised along x, 24-cell absorbing layer, 4000
+time steps with the last-period contour DFT, on a 384^3 and a 512^3 grid,
+each with its eps_r = 1 companion run (the incident field), followed by the
+near-to-far-field transform in the scattering planes phi = 0, 45 and 90
+degrees at 0.5 degree resolution.  FP32 state and arithmetic, FP64 DFT
+accumulators.  Inputs are resident in device memory before timing; the
+state (2 x 6.1 GB and 2 x 14.5 GB per run) is far larger than the 256 MB
+Infinity Cache, so the step kernel streams from HBM.
 
 Reported value: lattice updates per second over the whole step (MLUPS).
-Also reported: the step kernel's achieved algorithmic bandwidth (92 B per
-cell per launch: the kernel advances two time steps per launch, reading and
-writing the 11-scalar state once) against the 8 TB/s HBM peak, extras (the same
-job with the TM and TE instances on two concurrent HIP streams, a 3-D sphere
-(384^3, 220 B per update), a batched and an inverse-design configuration),
-and the FP64 oracle timed on a
-bounded sample of the same workload on the host cores together with the
-GPU-vs-oracle field error on that sample.
+roofline: the 3-D two-step kernel k_step3d_x2, 220 B per cell per launch
+(the 27-scalar state read and written once per two time steps, eps read),
+against the 8 TB/s HBM peak.  Extras: the 2-D cylinder job (1024^2, eight
+solves, Infinity-Cache resident), two-stream and batched forms of it, the
+sphere with the exact incident line instead of the companion, the
+permeability and incident-line kernel variants, the batched configurations
+(seeded and stress) and the inverse-design configuration.  cpu_baseline:
+the FP64 oracle on a bounded sample of the sphere workload on the host
+cores, with the GPU-vs-oracle field error on that sample.
 """
 import argparse
 import hashlib
@@ -26,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -33,7 +39,9 @@ METRIC = "MLUPS and % HBM roofline (fwd, adjoint, batched) at stated accuracy vs
 HBM_PEAK_GBS = 8000.0
 BYTES_2D = 11 * 4 * 2 + 4      # reduced 2-D state read + written, eps read (FP32)
 BYTES_3D = 27 * 4 * 2 + 4
-KERNEL_SOURCES = ["paper_2510_11042_amd/csrc/kernels.hpp", "paper_2510_11042_amd/csrc/lbm_em.hip"]
+CSRC = os.path.join(ROOT, "paper_2510_11042_amd", "csrc")
+KERNEL_SOURCES = sorted(os.path.join("paper_2510_11042_amd", "csrc", f) for f in os.listdir(CSRC)
+                        if f.endswith((".hpp", ".hip", ".inc")))
 
 
 def kernel_hash():
@@ -58,7 +66,7 @@ def recorded_traffic(key, tile=None):
     return rec.get("bytes_per_launch")
 
 
-def cylinder_workload(Simulation, W, lbm_steps, tile=None, streams=None):
+def cylinder_workload(Simulation, W, lbm_steps, tile=None, streams=None, precision="fp32"):
     """The eight solves; with `streams` = {pol: stream handle} each
     polarisation's instances are ordered on their own HIP stream."""
     sims = []
@@ -68,7 +76,7 @@ def cylinder_workload(Simulation, W, lbm_steps, tile=None, streams=None):
             if eps_in == 1.0:
                 case = W.vacuum_companion(case)
             kh, eh = W.plane_wave_2d(0.0, pol)
-            s = Simulation(1024, 1024, 1, pol=pol, precision="fp32", absorb=case.absorb,
+            s = Simulation(1024, 1024, 1, pol=pol, precision=precision, absorb=case.absorb,
                            sigma_max=W.SIGMA_MAX, stream=streams[pol] if streams else None)
             s.set_permittivity(case.eps)
             s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
@@ -190,32 +198,108 @@ def batched_job_extra(P, W, torch, lbm_steps, theta, tiles):
             "groups": groups, "MLUPS": len(sims) * 1024 * 1024 * lbm_steps / dt / 1e6, "seconds": dt}
 
 
-def sphere_extra(Simulation, W, torch, steps=200):
-    case = W.sphere_case(n=384, steps=steps, with_eps=True)
-    s = Simulation(384, 384, 384, pol="3D", precision="fp32", absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
+def sphere_job(Simulation, W, n, lbm_steps, tile=None, precision="fp32"):
+    """The sphere (x = 6, lambda = 24, eps 2.25, W = 24) on an n^3 grid and
+    its eps = 1 companion, contour DFT over the last period."""
+    case = W.sphere_case(n=n, steps=lbm_steps)
+    sims = []
+    for eps in (case.eps, None):
+        s = Simulation(n, n, n, pol="3D", precision=precision, absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
+        if eps is not None:
+            s.set_permittivity(eps)
+        s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
+        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+        if tile:
+            s.set_fusion(2, tile)
+        sims.append(s)
+    case.eps = None              # the map lives on the device now
+    return case, sims
+
+
+SPHERE_PHI = (0.0, 45.0, 90.0)
+
+
+def run_sphere(jobs, lbm_steps, theta, torch, events):
+    """One benchmark step over the sphere jobs; appends (start, end event,
+    launches, cells) around the stepping of each grid size.  Runs too short
+    for the DFT window (profiling) skip the far field."""
+    out = {}
+    for case, (tot, inc) in jobs:
+        tot.reset()
+        inc.reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tot.step(lbm_steps)
+        inc.step(lbm_steps)
+        e1.record()
+        events.append((e0, e1, 2 * lbm_steps // tot.get_fusion(), case.n ** 3))
+        if lbm_steps >= case.window[0] + case.window[1]:
+            for phi in SPHERE_PHI:
+                out[(case.n, phi)] = tot.farfield(theta, np.full_like(theta, phi), incident=inc)
+    return out
+
+
+def sphere_line_extra(Simulation, W, torch, lbm_steps, theta):
+    """The 384^3 sphere with the exact incident line (along z) instead of the
+    companion run: one grid plus a line, whole job (stepping + far field)
+    timed, and |S|^2 against the companion-run result."""
+    n = 384
+    case = W.sphere_case(n=n, steps=lbm_steps)
+    s = Simulation(n, n, n, pol="3D", precision="fp32", absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
     s.set_permittivity(case.eps)
     s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
-    s.step(64)
+    s.set_ntff(case.box_lo, case.box_hi, *case.window)
+    s.set_incident_line(True)
+
+    def job():
+        s.reset()
+        s.step(lbm_steps)
+        return {phi: s.farfield(theta, np.full_like(theta, phi)) for phi in SPHERE_PHI}
+
+    job()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    s.step(steps)
-    e1.record()
+    t0 = time.perf_counter()
+    S = job()
     torch.cuda.synchronize()
-    fuse = s.get_fusion()           # steps per launch: the state moves once per launch
-    ms = e0.elapsed_time(e1) / steps * fuse
-    cells = 384 ** 3
-    res = {"workload": "sphere-384^3-eps2.25-x6-lambda24", "cells": cells, "launches": steps // fuse,
-           "steps_per_launch": fuse, "kernel": "k_step3d_x2" if fuse == 2 else "k_step3d",
-           "tile": list(s.get_fusion_tile()) if fuse == 2 else list(s.get_tile()),
-           "ms_per_launch": ms, "MLUPS": cells * fuse / (ms * 1e-3) / 1e6,
-           "algorithmic_bytes_per_launch": cells * BYTES_3D,
-           "achieved_GBs": cells * BYTES_3D / (ms * 1e-3) / 1e9}
-    res["frac_of_hbm_peak"] = res["achieved_GBs"] / HBM_PEAK_GBS
-    res["traffic"] = recorded_traffic(("k_step3d_x2" if fuse == 2 else "k_step3d") + "_fp32_384",
-                                      res["tile"] if fuse == 2 else None)
+    dt = time.perf_counter() - t0
     s.close()
-    return res
+    return {"workload": f"sphere-{n}^3 with the incident line, {lbm_steps} steps + NTFF",
+            "seconds": dt, "MLUPS": n ** 3 * lbm_steps / dt / 1e6}, S
+
+
+def cylinder_extra(Simulation, W, torch, lbm_steps, theta, steps=2):
+    """The 2-D circular-cylinder job (1024^2, a = 25.5, lambda = 32, W = 32,
+    8000 steps, eps in {1.5, 2.25, 4.0} x {TM, TE} + two companions, 720
+    angles).  Its state (2 x 46 MB + 4 MB per instance) sits in the 256 MB
+    Infinity Cache: the bandwidth is the cache's, not HBM's."""
+    sims = cylinder_workload(Simulation, W, lbm_steps)
+    run_workload(sims, lbm_steps, theta, torch, [])
+    torch.cuda.synchronize()
+    events = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_workload(sims, lbm_steps, theta, torch, events)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    fuse = sims[0][2].get_fusion()
+    step_ms = sum(a.elapsed_time(b) for a, b, _ in events)
+    launches = sum(n for _, _, n in events) / fuse
+    ms_per_launch = step_ms / launches
+    cells = 1024 * 1024
+    alg = cells * BYTES_2D
+    kname = "k_step2d_x2" if fuse == 2 else "k_step2d"
+    tiles = {p: list(s.get_fusion_tile()) for p, _, s in sims}
+    res = {"workload": "cylinder-1024x1024-a25.5-lambda32-W32-8000steps-eps{1.5,2.25,4.0}x{TM,TE}"
+                       "+vacuum-companions+NTFF720", "residency": "Infinity-Cache-resident (not HBM)",
+           "instances": len(sims), "seconds_per_job": wall,
+           "MLUPS": len(sims) * cells * lbm_steps / wall / 1e6, "kernel": kname, "tiles": tiles,
+           "ms_per_launch": ms_per_launch, "algorithmic_bytes_per_launch": alg,
+           "effective_cache_GBs": alg / (ms_per_launch * 1e-3) / 1e9,
+           "traffic": recorded_traffic(f"{kname}_fp32_1024", tiles["TM"] if fuse == 2 else None)}
+    for _, _, s in sims:
+        s.close()
+    return res, tiles if fuse == 2 else None
 
 
 def magnetic_extra(Simulation, W, torch, steps=1600):
@@ -298,11 +382,12 @@ def line_extra(Simulation, W, torch, steps=1600):
     return res
 
 
-def batched_extra(P, W, torch, steps=6000):
+def batched_extra(P, W, torch, steps=6000, stress=False):
     """64 seeded uneven instances (circle/hexagon, eps, size, lambda, angle),
     6000 steps: one Batch (persistent launch per step, graph replay) against
-    the same instances stepped one after another."""
-    cases = W.batch_cases(64, steps=steps)
+    the same instances stepped one after another.  stress: sides drawn from
+    256..1536 (70 M cells in all) instead of 256..448."""
+    cases = W.batch_cases(64, steps=steps, stress=stress)
     sims = []
     for c in cases:
         kh, eh = W.plane_wave_2d(c.theta_deg, c.pol)
@@ -334,7 +419,8 @@ def batched_extra(P, W, torch, steps=6000):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     fuse = sims[0].get_fusion()     # two steps per launch: the state moves once per two steps
-    res = {"workload": "64 seeded 2-D scatterers, sides 256-448, 6000 steps", "cells": cells,
+    res = {"workload": f"64 seeded 2-D scatterers, sides {'256-1536' if stress else '256-448'}, {steps} steps",
+           "cells": cells, "state_GB": cells * 2 * 11 * 4 / 1e9,
            "groups": b.groups, "MLUPS": cells * steps / t_batch / 1e6,
            "single_instance_MLUPS": cells * steps / t_single / 1e6, "steps_per_launch": fuse,
            "algorithmic_GBs": cells * steps / fuse * BYTES_2D / t_batch / 1e9}
@@ -402,55 +488,76 @@ def copy_ceiling(P):
     return g.value
 
 
-def cpu_baseline(Simulation, W, target_s=20.0):
-    """FP64 oracle on a bounded sample of the benchmark workload (the
-    eps_r = 2.25 TM cylinder at 1024^2, first N steps), timed on the host
-    cores; the GPU runs the same N steps and its fields are compared."""
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(Simulation, W, target_s=20.0, n=384):
+    """FP64 oracle (literal 42-scalar scheme, OpenMP on all host threads) on
+    a bounded sample of the benchmark workload: the 384^3 sphere, its first
+    steps; the GPU (FP32, the benchmark's launch configuration) runs the
+    same steps and its fields are compared with the oracle's."""
     import numpy as np
 
     from oracle import core as oracle_core
 
-    case = W.cylinder_case(2.25, "TM", n=1024, steps=8000)
-    kh, eh = W.plane_wave_2d(0.0, "TM")
-    o = oracle_core.Oracle(1024, 1024, 1, case.absorb, W.SIGMA_MAX)
+    case = W.sphere_case(n=n, steps=4000)
+    c = (n - 1) / 2.0
+    t_alloc = time.perf_counter()
+    o = oracle_core.Oracle(n, n, n, (case.W,) * 3, W.SIGMA_MAX)
     o.set_eps(case.eps)
-    o.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS, [511.5, 511.5, 0.0])
+    o.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS, [c, c, c])
+    t_alloc = time.perf_counter() - t_alloc
     t0 = time.perf_counter()
-    o.step(10)
-    rate = 10 / (time.perf_counter() - t0)
-    n = int(max(20, min(2000, rate * target_s))) - 10
+    o.step(1)
+    first = time.perf_counter() - t0
+    nsteps = int(max(2, min(400, target_s / max(first, 1e-3))))
     t0 = time.perf_counter()
-    o.step(n)
+    o.step(nsteps - 1)
     dt = time.perf_counter() - t0
-    total = n + 10
-    s = Simulation(1024, 1024, 1, pol="TM", precision="fp32", absorb=case.absorb, sigma_max=W.SIGMA_MAX)
+    total = nsteps
+    s = Simulation(n, n, n, pol="3D", precision="fp32", absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
     s.set_permittivity(case.eps)
-    s.set_source(case.lam, kh, eh, 1.0, W.RAMP_PERIODS)
+    s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
     s.step(total)
     Eg, Hg = s.fields()
-    Eo, Ho = o.fields()
-    num = np.sum((Eg - Eo) ** 2) + np.sum((Hg - Ho) ** 2)
-    den = np.sum(Eo ** 2) + np.sum(Ho ** 2)
     s.close()
-    return {"value": 1024 * 1024 * n / dt / 1e6, "unit": "MLUPS", "cores": oracle_core.threads(),
+    Eo, Ho = o.fields()
+    del o
+    num = float(np.sum((Eg - Eo) ** 2) + np.sum((Hg - Ho) ** 2))
+    den = float(np.sum(Eo ** 2) + np.sum(Ho ** 2))
+    model, ncpu = host_cpu()
+    return {"value": n ** 3 * (nsteps - 1) / dt / 1e6, "unit": "MLUPS", "cores": oracle_core.threads(),
             "kind": "oracle",
-            "sample": f"eps 2.25 TM cylinder 1024^2, steps {10}..{total} of 8000, FP64 literal 42-scalar "
-                      f"scheme, {dt:.1f} s",
-            "gpu_vs_oracle_rel_l2_fields": float(np.sqrt(num / den)), "sample_steps": total}
+            "sample": f"eps 2.25 sphere {n}^3 (x = 6, lambda = 24, W = 24), steps 2..{total} of 4000 timed "
+                      f"({dt:.1f} s; {41.7 * (n / 384) ** 3:.1f} GB of FP64 literal 42-scalar state, allocated "
+                      f"in {t_alloc:.1f} s)",
+            "host_cpu": model, "nproc": ncpu,
+            "gpu_vs_oracle_rel_l2_fields": float(np.sqrt(num / den)) if den > 0 else None,
+            "sample_steps": total}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed benchmark steps")
+    ap.add_argument("--steps", type=int, default=1, help="timed benchmark steps")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--lbm-steps", type=int, default=8000, help="time steps per solve (workload: 8000)")
+    ap.add_argument("--lbm-steps", type=int, default=4000, help="time steps per solve (workload: 4000)")
+    ap.add_argument("--sizes", default="384,512", help="sphere grid sizes (workload: 384,512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="copy,streams,sphere,magnetic,line,batched,adjoint",
+    ap.add_argument("--extras", default="copy,cylinder,streams,sphere_line,magnetic,line,batched,stress,adjoint",
                     help="comma list of extra measurements to run")
     ap.add_argument("--tile", default=None,
-                    help="two-step tile TX,TY instead of autotuning (profiling runs)")
+                    help="3-D two-step tile TX,TY instead of the default (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -478,57 +585,78 @@ def main():
         print(json.dumps({"kernel": "k_copy16", "bytes_read_per_launch": 2 ** 30,
                           "bytes_written_per_launch": 2 ** 30, "launches": 4, "GBs": g.value}))
         return 0
-    theta = np.arange(0.0, 360.0, 0.5)
+    sizes = [int(v) for v in args.sizes.split(",")]
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-    sims = cylinder_workload(Simulation, W, args.lbm_steps, tile)
+    theta = np.arange(0.0, 180.01, 0.5)
+    jobs = [sphere_job(Simulation, W, n, args.lbm_steps, tile) for n in sizes]
+    print(f"bench: sphere jobs {sizes} ready", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
-        run_workload(sims, args.lbm_steps, theta, torch, [])
+        run_sphere(jobs, args.lbm_steps, theta, torch, [])
     torch.cuda.synchronize()
     events = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = run_workload(sims, args.lbm_steps, theta, torch, events)
+        res = run_sphere(jobs, args.lbm_steps, theta, torch, events)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    print(f"bench: {args.steps} timed steps in {wall:.1f} s", file=sys.stderr, flush=True)
     ms_per_step = wall * 1e3 / args.steps
-    cells = 1024 * 1024
-    updates = len(sims) * cells * args.lbm_steps
+    updates = sum(2 * case.n ** 3 * args.lbm_steps for case, _ in jobs)
     value = updates / (ms_per_step * 1e-3) / 1e6
 
     # the step kernel advances two time steps per launch (state read and
-    # written once per launch): 92 B per cell per launch are algorithmic
-    fuse = sims[0][2].get_fusion()
-    step_ms = sum(a.elapsed_time(b) for a, b, _ in events)
-    launches = sum(n for _, _, n in events) / fuse
-    ms_per_launch = step_ms / launches
-    alg_bytes = cells * BYTES_2D
-    achieved = alg_bytes / (ms_per_launch * 1e-3) / 1e9
-    kname = "k_step2d_x2" if fuse == 2 else "k_step2d"
-    tile = list(sims[0][2].get_fusion_tile()) if fuse == 2 else list(sims[0][2].get_tile())
-    traffic = recorded_traffic(f"{kname}_fp32_1024", tile if fuse == 2 else None)
+    # written once per launch): 220 B per cell per launch are algorithmic
+    tot0 = jobs[0][1][0]
+    fuse = tot0.get_fusion()
+    kname = "k_step3d_x2" if fuse == 2 else "k_step3d"
+    per_size = {}
+    for case, (tot, inc) in jobs:
+        ev = [(a, b, n) for a, b, n, c in events if c == case.n ** 3]
+        ms = sum(a.elapsed_time(b) for a, b, _ in ev) / sum(n for _, _, n in ev)
+        alg = case.n ** 3 * BYTES_3D
+        tl = list(tot.get_fusion_tile()) if fuse == 2 else list(tot.get_tile())
+        per_size[str(case.n)] = {
+            "ms_per_launch": ms, "algorithmic_bytes_per_launch": alg,
+            "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "tile": tl, "MLUPS_per_instance": case.n ** 3 * fuse / (ms * 1e-3) / 1e6,
+            "per_update_equivalent_GBs": alg * fuse / (ms * 1e-3) / 1e9,
+            "traffic": recorded_traffic(f"{kname}_fp32_{case.n}", tl if fuse == 2 else None)}
+    tot_ms = sum(a.elapsed_time(b) for a, b, _, _ in events)
+    tot_bytes = sum(n * c * BYTES_3D for _, _, n, c in events)
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+    traffics = [per_size[k]["traffic"] for k in per_size]
+    traffic = None
+    if all(t is not None for t in traffics):
+        # counter bytes over all launches of the step, per launch on average
+        nl = {str(case.n): sum(n for _, _, n, c in events if c == case.n ** 3) for case, _ in jobs}
+        traffic = sum(per_size[k]["traffic"] * nl[k] for k in per_size) / sum(nl.values())
     line = {
         "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "cylinder-1024x1024-a25.5-lambda32-W32-8000steps-eps{1.5,2.25,4.0}x{TM,TE}"
-                               "+vacuum-companions+NTFF720", "instances": len(sims),
-                   "lbm_steps": args.lbm_steps, "cells_per_instance": cells},
+        "config": {"workload": "sphere-x6-lambda24-eps2.25-W24-" + "+".join(f"{n}^3" for n in sizes) +
+                               f"-{args.lbm_steps}steps+vacuum-companions+NTFF-phi0/45/90-0.5deg",
+                   "instances": 2 * len(sizes), "lbm_steps": args.lbm_steps,
+                   "cells_per_instance": {str(n): n ** 3 for n in sizes}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kname + "<float,TM/TE>", "steps_per_launch": fuse,
-                     "tile": tile,
-                     "ms_per_launch": ms_per_launch,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "per_update_equivalent_GBs": alg_bytes * fuse / (ms_per_launch * 1e-3) / 1e9,
-                     "frac_note": "achieved counts the launch's minimal traffic (state read and written once per "
-                                  "launch, 92 B per cell); per_update_equivalent_GBs counts 92 B per cell update, "
-                                  "the bandwidth a one-step kernel would need for the same speed",
-                     "note": "state 2 x 46 MB + eps 4 MB per instance fits the 256 MB Infinity Cache"},
+                     "kernel": kname + "<float>", "steps_per_launch": fuse,
+                     "per_size": per_size,
+                     "frac_note": "achieved counts the launch's minimal traffic (the 27-scalar state read and "
+                                  "written once per launch, eps read: 220 B per cell), summed over every launch "
+                                  "of the timed steps and divided by their summed time (HIP events on the "
+                                  "library's stream around each run; the figure includes the gaps between "
+                                  "launches); per_update_equivalent_GBs counts 220 B per cell update",
+                     "note": "state 2 x 6.1 GB (384^3) and 2 x 14.5 GB (512^3) per run: HBM-resident"},
     }
-    # the computed intensities must be finite and positive
     for k, S in res.items():
         assert np.all(np.isfinite(S)) and S.max() > 0, k
+    line["config"]["S2_forward_backward"] = {f"{n}_phi{phi:g}": [float(S[0]), float(S[-1])]
+                                             for (n, phi), S in res.items()}
+    for case, (tot, inc) in jobs:
+        tot.close()
+        inc.close()
     if not args.no_extra:
         import paper_2510_11042_amd as P
 
@@ -536,24 +664,35 @@ def main():
         line["extra"] = {}
         if "copy" in want:
             line["roofline"]["measured_copy_GBs"] = copy_ceiling(P)
-        if "streams" in want and args.lbm_steps >= 2000:
-            tiles = {p: s.get_fusion_tile() for p, _, s in sims} if fuse == 2 else None
-            line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, args.lbm_steps, theta, tiles)
-            line["extra"]["batched_job"] = batched_job_extra(P, W, torch, args.lbm_steps, theta, tiles)
-        if "sphere" in want:
-            line["extra"]["sphere_3d"] = sphere_extra(Simulation, W, torch)
+        th2 = np.arange(0.0, 360.0, 0.5)
+        tiles = None
+        if "cylinder" in want:
+            line["extra"]["cylinder_2d"], tiles = cylinder_extra(Simulation, W, torch, 8000, th2)
+        if "streams" in want:
+            line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, 8000, th2, tiles)
+            line["extra"]["batched_job"] = batched_job_extra(P, W, torch, 8000, th2, tiles)
+        if "sphere_line" in want and 384 in sizes and args.lbm_steps >= 144:
+            r, S_line = sphere_line_extra(Simulation, W, torch, args.lbm_steps, theta)
+            d = {}
+            for phi in SPHERE_PHI:
+                if (384, phi) in res:
+                    ref = res[(384, phi)]
+                    d[f"phi{phi:g}"] = float(np.sqrt(np.mean((S_line[phi] - ref) ** 2)) / ref.max())
+            r["nrms_vs_companion_run"] = d
+            line["extra"]["sphere_384_incident_line"] = r
         if "magnetic" in want:
             line["extra"]["magnetic"] = magnetic_extra(Simulation, W, torch)
         if "line" in want:
             line["extra"]["incident_line"] = line_extra(Simulation, W, torch)
         if "batched" in want:
             line["extra"]["batched"] = batched_extra(P, W, torch)
+        if "stress" in want:
+            line["extra"]["batched_stress"] = batched_extra(P, W, torch, stress=True)
         if "adjoint" in want:
             line["extra"]["adjoint"] = adjoint_extra(P, W, torch)
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(Simulation, W)
-    for _, _, s in sims:
-        s.close()
     print(json.dumps(line), flush=True)
     return 0
 
