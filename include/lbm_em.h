@@ -300,6 +300,24 @@ lbm_em_status lbm_em_get_phasors(lbm_em_handle h, double *out, int32_t *n_nodes)
 lbm_em_status lbm_em_farfield(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
                               const double *phi_deg, int32_t n_angles, double *out_S2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * |S|^2 as lbm_em_farfield (same arguments, same arithmetic), with every
+ * device buffer of the call -- angles, far-field sums, |S|^2, the incident
+ * amplitude and, on a handle with an incident line, the line's phasors on
+ * the contour nodes -- in a static per-device array of the library
+ * (LBM_EM_FARFIELD_STATIC_MAX_ANGLES angles, contours of up to
+ * LBM_EM_FARFIELD_STATIC_MAX_NODES nodes: 3.4 MB, held by every device the
+ * library runs on until the process ends).  The call allocates no device or
+ * host memory and needs no workspace argument.  EINVAL beyond either
+ * maximum; otherwise the statuses of lbm_em_farfield.  Calls that overlap
+ * on one device share that array and race: issue them from one thread at a
+ * time per device.  Synchronises. */
+#define LBM_EM_FARFIELD_STATIC_MAX_ANGLES 4096
+#define LBM_EM_FARFIELD_STATIC_MAX_NODES 32768
+lbm_em_status lbm_em_farfield_static(lbm_em_handle h, lbm_em_handle incident, const double *theta_deg,
+                                     const double *phi_deg, int32_t n_angles, double *out_S2);
+
 /* ---------------------------------------------------------------------
  * Inverse design: gradient of a far-field objective with respect to eps_r
  * in a design rectangle, by the discrete adjoint of the step (2-D TM/TE).

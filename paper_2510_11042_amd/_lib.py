@@ -25,7 +25,7 @@ EXPORTS = [
     "lbm_em_batch_destroy", "lbm_em_set_tile", "lbm_em_get_tile", "lbm_em_set_fusion", "lbm_em_get_fusion",
     "lbm_em_autotune",
     "lbm_em_reset", "lbm_em_time", "lbm_em_get_fields",
-    "lbm_em_get_phasors", "lbm_em_farfield", "lbm_em_adjoint_setup", "lbm_em_forward_checkpointed",
+    "lbm_em_get_phasors", "lbm_em_farfield", "lbm_em_farfield_static", "lbm_em_adjoint_setup", "lbm_em_forward_checkpointed",
     "lbm_em_backward", "lbm_em_copy_bandwidth", "lbm_em_last_error",
 ]
 
@@ -90,6 +90,8 @@ def lib():
             "lbm_em_get_phasors": [H, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
             "lbm_em_farfield": [H, H, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
                                 C.POINTER(C.c_double)],
+            "lbm_em_farfield_static": [H, H, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
+                                       C.POINTER(C.c_double)],
         }
         sig["lbm_em_adjoint_setup"] = [H, H, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]

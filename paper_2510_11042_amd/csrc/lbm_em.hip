@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1037,6 +1038,96 @@ void check_unit(const double v[3], const char *name) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free far field (lbm_em_farfield_static).  Its device buffers --
+// the angles, the far-field combinations P, |S|^2, the incident amplitude
+// and the incident line's phasors on the contour nodes -- live in one
+// file-scope device array, one copy per device, so a call allocates nothing.
+// Host code addresses the array only through the pointer that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr int kFfMaxAngles = LBM_EM_FARFIELD_STATIC_MAX_ANGLES;
+constexpr int kFfMaxNodes = LBM_EM_FARFIELD_STATIC_MAX_NODES;
+constexpr size_t kFfAng = 0;                                   // theta [max], phi [max] (radians)
+constexpr size_t kFfP = kFfAng + 2 * (size_t)kFfMaxAngles;     // 4 per angle
+constexpr size_t kFfS2 = kFfP + 4 * (size_t)kFfMaxAngles;      // 1 per angle
+constexpr size_t kFfAmp = kFfS2 + (size_t)kFfMaxAngles;        // 1 (padded to 32)
+constexpr size_t kFfLine = kFfAmp + 32;                        // (nodes + 1) x 12
+constexpr size_t kFfDoubles = kFfLine + ((size_t)kFfMaxNodes + 1) * 12;
+
+__device__ __align__(256) double lbm_ff_scratch[kFfDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_ff_mutex;
+double *g_ff_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of lbm_ff_scratch (the current
+// device must be dev), looked up once per device.
+double *ff_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) fail(LBM_EM_EDEVICE, "device index out of range for the far-field scratch");
+    std::lock_guard<std::mutex> lock(g_ff_mutex);
+    if (!g_ff_ptr[dev]) {
+        void *p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(lbm_ff_scratch)), "hipGetSymbolAddress(far-field scratch)");
+        if (!p) fail(LBM_EM_EDEVICE, "far-field scratch has no device address");
+        g_ff_ptr[dev] = (double *)p;
+    }
+    return g_ff_ptr[dev];
+}
+
+// degrees -> radians in place (theta at ang[0..n), phi at ang[max..max+n);
+// without phi the second half is set to zero)
+__global__ void k_ff_angles(double *ang, int n, int has_phi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ang[i] = ang[i] * M_PI / 180.0;
+    ang[kFfMaxAngles + i] = has_phi ? ang[kFfMaxAngles + i] * M_PI / 180.0 : 0.0;
+}
+
+// the incident line's phasors at every contour node (and the probe, last)
+__global__ void k_ff_line_nodes(const double *line_acc, double *out, Box b, int dim, int axis, int probe_u,
+                                int64_t nnodes) {
+    const int64_t nbx = b.hi[0] - b.lo[0] + 1, nby = b.hi[1] - b.lo[1] + 1, nbz = b.hi[2] - b.lo[2] + 1;
+    const int64_t cells = nbx * nby * nbz;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= cells; c += (int64_t)gridDim.x * blockDim.x) {
+        if (c == cells) {
+            for (int k = 0; k < 12; ++k) out[nnodes * 12 + k] = line_acc[(int64_t)probe_u * 12 + k];
+            continue;
+        }
+        const int x = b.lo[0] + (int)(c % nbx), y = b.lo[1] + (int)((c / nbx) % nby), z = b.lo[2] + (int)(c / (nbx * nby));
+        if (!on_box(b, dim, x, y, z)) continue;
+        const int64_t node = box_node_index(b, dim, x, y, z);
+        const int u = axis == 0 ? x : axis == 1 ? y : z;
+        for (int k = 0; k < 12; ++k) out[node * 12 + k] = line_acc[(int64_t)u * 12 + k];
+    }
+}
+
+// |S|^2 = kappa |P|^2 / amp^2, amp = |u . v| of the incident probe phasor v
+// (the source amplitude without an incident field)
+__global__ void k_ff_finish(const double *P, const double *probe, double u0, double u1, double u2, double amplitude,
+                            double kappa, int n, double *S2, double *amp_out) {
+    double amp = amplitude;
+    if (probe) {
+        const double u[3] = {u0, u1, u2};
+        double re = 0, im = 0;
+        for (int k = 0; k < 3; ++k) {
+            re += u[k] * probe[2 * k];
+            im += u[k] * probe[2 * k + 1];
+        }
+        amp = sqrt(re * re + im * im);
+    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *amp_out = amp;
+    if (i >= n) return;
+    const double *q = P + 4 * (size_t)i;
+    const double p = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    S2[i] = kappa * p / (amp * amp);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *lbm_em_last_error(void) { return g_last_error.c_str(); }
@@ -1826,6 +1917,77 @@ lbm_em_status lbm_em_farfield(lbm_em_handle hh, lbm_em_handle inc, const double 
                        P[4 * i + 3] * P[4 * i + 3];
             out_S2[i] = kappa * p / (amp * amp);
         }
+    });
+}
+
+lbm_em_status lbm_em_farfield_static(lbm_em_handle hh, lbm_em_handle inc, const double *theta_deg,
+                                     const double *phi_deg, int32_t n_angles, double *out_S2) {
+    return guarded([&] {
+        lbm_em *h = check_handle(hh);
+        if (!theta_deg || !out_S2 || n_angles < 1) fail(LBM_EM_EINVAL, "bad angle / output arrays");
+        if (n_angles > kFfMaxAngles) fail(LBM_EM_EINVAL, "n_angles exceeds LBM_EM_FARFIELD_STATIC_MAX_ANGLES");
+        if (h->dim == 3 && !phi_deg) fail(LBM_EM_EINVAL, "3-D needs phi");
+        if (!h->dft_set) fail(LBM_EM_ESTATE, "no contour set");
+        if (h->t < h->win0 + h->winlen) fail(LBM_EM_ESTATE, "DFT window not completed");
+        if (inc) check_incident(h, inc);
+        const bool use_line = !inc && h->line;
+        if (use_line && h->nnodes > kFfMaxNodes) fail(LBM_EM_EINVAL, "contour exceeds LBM_EM_FARFIELD_STATIC_MAX_NODES");
+        select_device(h);
+        if (inc) sync(inc);
+        double *sc = ff_scratch(h->dev);
+        hipStream_t st = h->stream;
+        double *ang = sc + kFfAng, *P = sc + kFfP, *S2 = sc + kFfS2, *amp_d = sc + kFfAmp, *line = sc + kFfLine;
+        hip_check(hipMemcpyAsync(ang, theta_deg, (size_t)n_angles * sizeof(double), hipMemcpyHostToDevice, st), "H2D angles");
+        if (phi_deg)
+            hip_check(hipMemcpyAsync(ang + kFfMaxAngles, phi_deg, (size_t)n_angles * sizeof(double),
+                                     hipMemcpyHostToDevice, st), "H2D angles");
+        const unsigned ab = (unsigned)((n_angles + 255) / 256);
+        hipLaunchKernelGGL(k_ff_angles, dim3(ab), dim3(256), 0, st, ang, n_angles, phi_deg ? 1 : 0);
+        hip_check(hipGetLastError(), "k_ff_angles");
+        const double *acc_inc = inc ? inc->acc : nullptr;
+        if (use_line) {
+            const Box &b = h->box;
+            const int64_t cells = (int64_t)(b.hi[0] - b.lo[0] + 1) * (b.hi[1] - b.lo[1] + 1) * (b.hi[2] - b.lo[2] + 1);
+            const unsigned lb = (unsigned)std::min<int64_t>((cells + 256) / 256, 1024);
+            hipLaunchKernelGGL(k_ff_line_nodes, dim3(lb), dim3(256), 0, st, h->line_acc, line, b, h->dim, h->line_axis,
+                               h->probe[h->line_axis], h->nnodes);
+            hip_check(hipGetLastError(), "k_ff_line_nodes");
+            acc_inc = line;
+        }
+        NtffArgs a{};
+        a.acc = h->acc;
+        a.acc_inc = acc_inc;
+        a.box = h->box;
+        a.dim = h->dim;
+        a.pol = h->cfg.pol;
+        a.k = 2.0 * M_PI / h->pw.lambda;
+        const auto &c = h->cfg;
+        a.center[0] = (c.nx - 1) / 2.0;
+        a.center[1] = (c.ny - 1) / 2.0;
+        a.center[2] = h->dim == 3 ? (c.nz - 1) / 2.0 : 0.0;
+        for (int k = 0; k < 3; ++k) {
+            a.khat[k] = h->pw.khat[k];
+            a.ehat[k] = h->pw.ehat[k];
+            a.bhat[k] = h->hhat[k];
+        }
+        a.theta = ang;
+        a.phi = ang + kFfMaxAngles;
+        a.out = P;
+        hipLaunchKernelGGL(k_ntff, dim3(n_angles), dim3(256), 0, st, a);
+        hip_check(hipGetLastError(), "k_ntff");
+        const double k = a.k;
+        const double kappa = h->dim == 2 ? k * k / (8.0 * M_PI) : k * k * k * k / (16.0 * M_PI * M_PI);
+        const double *u = h->cfg.pol == LBM_EM_TE ? h->hhat : h->pw.ehat;
+        const double *probe = acc_inc ? acc_inc + h->nnodes * 12 + (h->cfg.pol == LBM_EM_TE ? 6 : 0) : nullptr;
+        hipLaunchKernelGGL(k_ff_finish, dim3(ab), dim3(256), 0, st, P, probe, u[0], u[1], u[2], h->pw.amplitude,
+                           kappa, n_angles, S2, amp_d);
+        hip_check(hipGetLastError(), "k_ff_finish");
+        double amp = 0.0;
+        hip_check(hipMemcpyAsync(&amp, amp_d, sizeof amp, hipMemcpyDeviceToHost, st), "D2H amplitude");
+        sync(h);
+        if (!(amp > 0.0)) fail(LBM_EM_ESTATE, "incident amplitude at the probe node is zero (the wave has not arrived)");
+        hip_check(hipMemcpyAsync(out_S2, S2, (size_t)n_angles * sizeof(double), hipMemcpyDeviceToHost, st), "D2H S2");
+        sync(h);
     });
 }
 
