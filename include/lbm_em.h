@@ -167,11 +167,12 @@ lbm_em_status lbm_em_set_ntff(lbm_em_handle h, const int32_t lo[3], const int32_
  * enable = 0 removes the line.  Set it after the source and before stepping
  * (t = 0, or after a reset); a new source removes it.  Batches and the
  * adjoint refuse a handle with a line.
- * A 3-D line is held in LDS and must fit 64 KB (FP32 nz <= 606, FP64
- * nz <= 303).
- * Errors: EUNSUPPORTED after adjoint_setup or for a 3-D line that does not
- * fit, ESTATE without a source, at t > 0 or while batched, EINVAL for other
- * directions. */
+ * A line whose state fits 64 KB (2-D: 11 scalars per cell; 3-D: 27, FP32
+ * nz <= 606, FP64 nz <= 303) is held in LDS for a whole 64-step graph
+ * chunk; a longer one takes one or two steps through global memory before
+ * each grid launch.
+ * Errors: EUNSUPPORTED after adjoint_setup, ESTATE without a source, at
+ * t > 0 or while batched, EINVAL for other directions. */
 lbm_em_status lbm_em_set_incident_line(lbm_em_handle h, int32_t enable);
 
 /* The incident line's phasors: out[(u*6 + c)*2 + {0,1}] = (re, im) of

@@ -1623,6 +1623,30 @@ __global__ void __launch_bounds__(1024) k_line3d_lds(StepArgs<T> a, T *dst, int 
     for (int k = tid; k < 27 * n; k += NT) dst[(k / n) * P + (k % n) * cstride] = S[k];
 }
 
+// The 3-D incident line's own steps through global memory (lines longer
+// than the LDS holds): one block walks the line's cells with the same pulls
+// and per-cell update as k_line3d_lds, one or two steps per launch (a0 / a1:
+// the arguments of the two steps, buffers swapped), recording each step's
+// post-collision populations for the grid launch that follows.  A barrier
+// separates the two steps (one workgroup: its release/acquire at workgroup
+// scope orders the first step's global writes).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_line3d(StepArgs<T> a0, StepArgs<T> a1, int nsteps) {
+    for (int s = 0; s < nsteps; ++s) {
+        const StepArgs<T> &a = s == 0 ? a0 : a1;
+        const StepConst<T> st = step_const(a, step_time(a.t_base, a.t_off));
+        const uint32_t sz = (uint32_t)a.sz;
+        for (int u = threadIdx.x; u < a.line_n; u += blockDim.x) {
+            T f[27], e;
+            pull3d<T>(a, 0, 0, u, f, e);    // x/y movers from the cell itself (a single periodic cell)
+            cell_update3d<T, false, true>(a, st, 0, 0, u, T(1), recip(T(1)), sigma3d<T>(a, 0, 0, u), f, true);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) *at(a.dst + i * a.plane, (uint32_t)u * sz) = f[i];
+        }
+        if (s + 1 < nsteps) __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Discrete adjoint of the 2-D step (inverse design).
 //

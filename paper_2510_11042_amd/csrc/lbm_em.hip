@@ -278,7 +278,7 @@ void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t
         hip_check(hipGetLastError(), "k_line_lds");
         return;
     }
-    if (nsteps > 2 || !flip || h->dim != 2) fail(LBM_EM_EINVAL, "internal: global-memory line steps are per 2-D launch");
+    if (nsteps > 2 || !flip) fail(LBM_EM_EINVAL, "internal: global-memory line steps are per grid launch");
     StepArgs<T> a0 = make_args<T>(l, l->buf[parity], nsteps == 2 ? h->line_tmp : l->buf[parity ^ 1]);
     StepArgs<T> a1 = make_args<T>(l, h->line_tmp, l->buf[parity ^ 1]);
     for (StepArgs<T> *a : {&a0, &a1}) {
@@ -294,7 +294,8 @@ void launch_line_t(const lbm_em *h, int parity, const int64_t *t_base, int64_t t
     a0.t_off = t_off;
     a1.t_off = t_off + 1;
     if (h->cfg.pol == LBM_EM_TM) hipLaunchKernelGGL((k_line<T, TM>), dim3(1), dim3(1024), 0, s, a0, a1, nsteps);
-    else hipLaunchKernelGGL((k_line<T, TE>), dim3(1), dim3(1024), 0, s, a0, a1, nsteps);
+    else if (h->cfg.pol == LBM_EM_TE) hipLaunchKernelGGL((k_line<T, TE>), dim3(1), dim3(1024), 0, s, a0, a1, nsteps);
+    else hipLaunchKernelGGL((k_line3d<T>), dim3(1), dim3(1024), 0, s, a0, a1, nsteps);
     hip_check(hipGetLastError(), "k_line");
 }
 
@@ -1327,8 +1328,6 @@ lbm_em_status lbm_em_set_incident_line(lbm_em_handle hh, int32_t enable) {
             fail(LBM_EM_EINVAL, "the incident line needs incidence along +-x or +-y");
         if (h->dim == 3 && axis != 2) fail(LBM_EM_EINVAL, "a 3-D incident line needs incidence along +-z");
         h->line_axis = axis;
-        if (h->dim == 3 && !line_in_lds(h))
-            fail(LBM_EM_EUNSUPPORTED, "a 3-D incident line must fit 64 KB of LDS (FP32 nz <= 606, FP64 nz <= 303)");
         lbm_em_config lc = h->cfg;
         const int n3[3] = {h->cfg.nx, h->cfg.ny, h->cfg.nz};
         lc.nx = axis == 0 ? n3[0] : 1;

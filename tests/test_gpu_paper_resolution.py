@@ -15,14 +15,19 @@ Measured here (FP32) vs the paper's value:
   cylinder eps 2, a/lambda = 10    2.6e-3   (1.3e-3)
   cylinder a/lambda = 1, eps 5     1.5e-3   (1.0e-3)
   cylinder a/lambda = 1, eps 10    2.5e-3   (2.3e-3)
-  cylinder a/lambda = 1, eps 20    2.5e-2   (6.6e-3)  -- converged; the staircase interface at 50 cells per interior wavelength
+  cylinder a/lambda = 1, eps 20    2.5e-2   (6.6e-3)  -- converged, 3.7x the paper's error: the staircase
+                                   interface at 50 cells per interior wavelength (a 4x thicker layer
+                                   changes it only to 2.2e-2); bound 3e-2 guards it
   sphere eps 2, a/lambda = 1       0.9 / 0.9 / 1.4e-3 at phi 0/45/90
                                    (1.9 / 2.0 / 1.8e-3)
+  sphere eps 2, a/lambda = 2       4.6 / 4.6 / 4.8e-3 at phi 0/45/90, 472^3, incident line
+                                   (0.18 at every phi)
   PEC cylinder, a/lambda = 0.1     1.8e-2   (1.5e-2)   min/max 0.411/1.03  (0.428/1.05)
   PEC cylinder, a/lambda = 1       2.7e-3   (3.0e-3)   min/max 1.68/34.2   (1.82/34.2)
   PEC cylinder, a/lambda = 10      3.7e-4   (7.2e-4)   min/max 7.27/2688   (8.81/2.6e3)
 The bounds are those values with a margin.
 """
+import os
 import sys
 
 import numpy as np
@@ -50,6 +55,11 @@ def P():
     return P
 
 
+# a/lambda = 2 sphere (keyed by lambda_eps/dx): measured 4.6 / 4.6 / 4.8e-3 at
+# lambda_eps/dx ~ 50 (the paper: 0.18); the finer grid must do at least as well
+SPHERE2_BOUND = {50: 6e-3, 100: 6e-3}
+
+
 def nrms(S, ref):
     return float(np.sqrt(np.mean((S - ref) ** 2)) / ref.max())
 
@@ -61,7 +71,7 @@ CYLINDERS = [
     (2.0, 100, 1000, 4, 100, 5e-3, 1.3e-3),
     (5.0, 112, 112, 10, 150, 3e-3, 1.0e-3),
     (10.0, 158, 158, 10, 150, 5e-3, 2.3e-3),
-    (20.0, 224, 224, 10, 150, 4e-2, 6.6e-3),
+    (20.0, 224, 224, 10, 150, 3e-2, 6.6e-3),
 ]
 
 
@@ -182,3 +192,71 @@ def test_sphere_at_paper_resolution(P):
         assert e < 3e-3
     for s in sims:
         s.close()
+
+
+def _sphere_with_line(P, lam, a, Wl, periods):
+    """Sphere eps 2 of radius a at wavelength lam (cells), L/a = 3 (Table
+    dielectric_sphere_er_2) plus a layer of Wl cells; the exact incident line
+    replaces the companion run (a companion of the larger grid would not
+    fit next to it).  Returns |S|^2 at phi = 0/45/90 over 0..180 degrees of
+    the last window and the drift to the window one period earlier."""
+    n = int(round(3 * a)) + 2 * Wl
+    T = int(round(3 * lam))
+    steps = periods * T
+    case = W.sphere_case(n=n, x_size=2 * np.pi * a / lam, lam=lam, eps_in=2.0, W=Wl, steps=steps,
+                         half=np.ceil(a) + 18 + 0.5)
+    say("sphere a/lambda = 2", n, lam, a, steps)
+    s = P.Simulation(n, n, n, pol="3D", precision="fp32", absorb=(Wl,) * 3, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(case.eps)
+    case.eps = None
+    s.set_source(lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
+    s.set_ntff(case.box_lo, case.box_hi, *case.window)
+    s.set_incident_line(True)
+    done = 0
+    while done < steps:             # progress lines for long runs
+        k = min(1024, steps - done)
+        s.step(k)
+        done += k
+        if n > 600:
+            import torch
+
+            torch.cuda.synchronize()
+            say(f"  step {done} / {steps}")
+    th = np.arange(0.0, 180.01, 0.5)
+    first = {ph: s.farfield(th, np.full_like(th, ph)) for ph in (0.0, 45.0, 90.0)}
+    s.set_ntff(case.box_lo, case.box_hi, steps, T)
+    s.step(T)
+    out = {}
+    for ph in (0.0, 45.0, 90.0):
+        S = s.farfield(th, np.full_like(th, ph))
+        ref = mie.sphere_S2(th, ph, 2 * np.pi * a / lam, np.sqrt(2.0))
+        out[ph] = (nrms(S, ref), nrms(S, first[ph]), S, ref)
+    s.close()
+    return out
+
+
+def test_sphere_a_over_lambda_2_at_paper_resolution(P):
+    """Sphere eps 2, a/lambda = 2 at the paper's lambda_eps/dx ~ 50 (a/dx =
+    141, L/a = 3; 472^3 with the layer).  The paper reports a normalised RMS
+    of 0.18 at every phi here and names a finer grid as future work."""
+    lam = 212.0 / 3.0                  # 3 lambda integral; lambda_eps = 49.97 cells
+    res = _sphere_with_line(P, lam, 2 * lam, 24, 26)
+    for ph, (e, drift, S, ref) in res.items():
+        say(f"  phi {ph}: nRMS {e:.3e} (paper 0.18), drift {drift:.1e}, back {S[-1]:.4g} vs {ref[-1]:.4g}")
+        assert drift < 1e-3
+        assert e < SPHERE2_BOUND[50]
+
+
+@pytest.mark.skipif(not os.environ.get("LBM_EM_LONG_TESTS"),
+                    reason="944^3 run of about 5 minutes; set LBM_EM_LONG_TESTS=1")
+def test_sphere_a_over_lambda_2_at_double_resolution(P):
+    """The same sphere at lambda_eps/dx ~ 100 (a/dx = 283; 944^3 with a
+    48-cell layer, 185 GB of FP32 state), the resolution the paper names as
+    future work in section 3.4."""
+    lam = 424.0 / 3.0
+    res = _sphere_with_line(P, lam, 2 * lam, 48, 26)
+    for ph, (e, drift, S, ref) in res.items():
+        say(f"  phi {ph}: nRMS {e:.3e} (paper at half this resolution 0.18), drift {drift:.1e}, "
+            f"back {S[-1]:.4g} vs {ref[-1]:.4g}")
+        assert drift < 1e-3
+        assert e < SPHERE2_BOUND[100]

@@ -1001,7 +1001,7 @@ def test_incident_line_3d_exact_and_tiles(gpu, prec):
 
 
 def test_incident_line_3d_limits(gpu):
-    """A 3-D line needs incidence along z and must fit 64 KB of LDS."""
+    """A 3-D line needs incidence along z."""
     from paper_2510_11042_amd import LbmEmError
 
     s = gpu(16, 16, 16, pol="3D", precision="fp32", absorb=(4, 4, 4), sigma_max=W.SIGMA_MAX)
@@ -1009,8 +1009,37 @@ def test_incident_line_3d_limits(gpu):
     with pytest.raises(LbmEmError):
         s.set_incident_line(True)
     s.close()
-    s = gpu(8, 8, 700, pol="3D", precision="fp32", absorb=(0, 0, 20), sigma_max=W.SIGMA_MAX)
-    s.set_source(8.0, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
-    with pytest.raises(LbmEmError):
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_incident_line_3d_global_memory_path(gpu, prec):
+    """A 3-D line longer than the LDS holds (700 cells along z; FP32 LDS
+    lines stop at 606, FP64 at 303) takes the global-memory path: a thin
+    column (8 x 8 x 700, x and y periodic) with a dielectric slab against
+    the oracle with its line, one and two steps per launch, eager steps and
+    graph chunks, and a background-only column equal to the line bit for
+    bit on every x-y plane."""
+    nx, ny, nz = 8, 8, 700
+    eps = np.ones((nz, ny, nx))
+    eps[300:340, :, :] = 2.25
+    eps[500:520, 2:6, 1:5] = 3.0
+    for fuse in (1, 2):
+        say("3d long line", prec, fuse)
+        s, o = make_pair(gpu, nx, ny, nz, "3D", prec, (0, 0, 20), eps, 12.0, [0, 0, 1.0], [1.0, 0, 0], ramp=1.0)
         s.set_incident_line(True)
+        s.set_fusion(fuse)
+        o.set_incident_line(2)
+        for k in (1, 9, 130, 600):
+            s.step(k)
+            o.step(k)
+            compare_fields(s, o, prec, f"3d long line fuse {fuse} t={o.t}")
+        s.close()
+    s = gpu(nx, ny, nz, pol="3D", precision=prec, absorb=(0, 0, 20), sigma_max=W.SIGMA_MAX)
+    s.set_source(12.0, [0, 0, -1.0], [0, 1.0, 0], 1.0, 1.0)
+    s.set_incident_line(True)
+    s.step(333)
+    E, H = s.fields()
+    assert np.abs(E).max() > 0.1
+    assert np.array_equal(E, np.broadcast_to(E[:, :1, :1], E.shape))
+    assert np.array_equal(H, np.broadcast_to(H[:, :1, :1], H.shape))
     s.close()
