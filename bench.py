@@ -40,8 +40,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES_2D = 11 * 4 * 2 + 4      # reduced 2-D state read + written, eps read (FP32)
 BYTES_3D = 27 * 4 * 2 + 4
 CSRC = os.path.join(ROOT, "paper_2510_11042_amd", "csrc")
+# the kernels and their launchers (the runtime lbm_em.hip is not hashed)
 KERNEL_SOURCES = sorted(os.path.join("paper_2510_11042_amd", "csrc", f) for f in os.listdir(CSRC)
-                        if f.endswith((".hpp", ".hip", ".inc")))
+                        if f.endswith((".hpp", ".inc")) or (f.startswith("k_") and f.endswith(".hip")))
 
 
 def kernel_hash():
@@ -208,7 +209,8 @@ def sphere_job(Simulation, W, n, lbm_steps, tile=None, precision="fp32"):
         if eps is not None:
             s.set_permittivity(eps)
         s.set_source(case.lam, [0, 0, 1.0], [1.0, 0, 0], 1.0, W.RAMP_PERIODS)
-        s.set_ntff(case.box_lo, case.box_hi, *case.window)
+        if case.window[0] >= 0:          # runs shorter than a period (profiling) record no DFT
+            s.set_ntff(case.box_lo, case.box_hi, *case.window)
         if tile:
             s.set_fusion(2, tile)
         sims.append(s)
@@ -234,7 +236,8 @@ def run_sphere(jobs, lbm_steps, theta, torch, events):
         inc.step(lbm_steps)
         e1.record()
         events.append((e0, e1, 2 * lbm_steps // tot.get_fusion(), case.n ** 3))
-        if lbm_steps >= case.window[0] + case.window[1]:
+        # profiling runs too short for the wave to reach the sphere skip the far field
+        if lbm_steps >= 1000 and lbm_steps >= case.window[0] + case.window[1]:
             for phi in SPHERE_PHI:
                 out[(case.n, phi)] = tot.farfield(theta, np.full_like(theta, phi), incident=inc)
     return out
