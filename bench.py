@@ -429,6 +429,10 @@ def batched_extra(P, W, torch, steps=6000, stress=False):
            "algorithmic_GBs": cells * steps / fuse * BYTES_2D / t_batch / 1e9}
     res["batched_over_single"] = res["MLUPS"] / res["single_instance_MLUPS"]
     res["autotune_us_per_step"] = tuned_us
+    # counter bytes of the batched kernel over all its launches / the
+    # algorithmic bytes of the same launches (profiles/, same kernel source)
+    rec = recorded_traffic("k_step2d_x2_batch_fp32_" + ("stress64" if stress else "seeded64"))
+    res["traffic_over_algorithmic"] = rec
     b.close()
     for s in sims:
         s.close()
@@ -559,6 +563,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extras", default="copy,cylinder,streams,sphere_line,magnetic,line,batched,stress,adjoint",
                     help="comma list of extra measurements to run")
+    ap.add_argument("--batch-steps", type=int, default=6000,
+                    help="time steps of the batched extras (workload: 6000; fewer for profiling runs)")
     ap.add_argument("--tile", default=None,
                     help="3-D two-step tile TX,TY instead of the default (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -688,9 +694,9 @@ def main():
         if "line" in want:
             line["extra"]["incident_line"] = line_extra(Simulation, W, torch)
         if "batched" in want:
-            line["extra"]["batched"] = batched_extra(P, W, torch)
+            line["extra"]["batched"] = batched_extra(P, W, torch, steps=args.batch_steps)
         if "stress" in want:
-            line["extra"]["batched_stress"] = batched_extra(P, W, torch, stress=True)
+            line["extra"]["batched_stress"] = batched_extra(P, W, torch, steps=args.batch_steps, stress=True)
         if "adjoint" in want:
             line["extra"]["adjoint"] = adjoint_extra(P, W, torch)
     if not args.no_cpu_baseline:
