@@ -21,7 +21,9 @@ Measured here (FP32) vs the paper's value:
   sphere eps 2, a/lambda = 1       0.9 / 0.9 / 1.4e-3 at phi 0/45/90
                                    (1.9 / 2.0 / 1.8e-3)
   sphere eps 2, a/lambda = 2       4.6 / 4.6 / 4.8e-3 at phi 0/45/90, 472^3, incident line
-                                   (0.18 at every phi)
+                                   (0.18 at every phi); at twice the resolution (944^3)
+                                   4.2 / 4.1 / 4.5e-3; backscatter 56-57 against the series' 162
+                                   at both resolutions (the paper too reports its largest error there)
   PEC cylinder, a/lambda = 0.1     1.8e-2   (1.5e-2)   min/max 0.411/1.03  (0.428/1.05)
   PEC cylinder, a/lambda = 1       2.7e-3   (3.0e-3)   min/max 1.68/34.2   (1.82/34.2)
   PEC cylinder, a/lambda = 10      3.7e-4   (7.2e-4)   min/max 7.27/2688   (8.81/2.6e3)
@@ -56,8 +58,8 @@ def P():
 
 
 # a/lambda = 2 sphere (keyed by lambda_eps/dx): measured 4.6 / 4.6 / 4.8e-3 at
-# lambda_eps/dx ~ 50 (the paper: 0.18); the finer grid must do at least as well
-SPHERE2_BOUND = {50: 6e-3, 100: 6e-3}
+# lambda_eps/dx ~ 50 (the paper: 0.18) and 4.2 / 4.1 / 4.5e-3 at ~100
+SPHERE2_BOUND = {50: 6e-3, 100: 5.5e-3}
 
 
 def nrms(S, ref):
