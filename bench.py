@@ -52,7 +52,7 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(key, tile=None):
+def recorded_traffic(key, tile=None, field="bytes_per_launch"):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/) for
     `key` and (two-step kernels) the tile, or None when absent or taken on
     a different kernel source."""
@@ -64,7 +64,7 @@ def recorded_traffic(key, tile=None):
     rec = json.load(open(path)).get(key)
     if not rec or rec.get("kernel_hash") != kernel_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get(field)
 
 
 def cylinder_workload(Simulation, W, lbm_steps, tile=None, streams=None, precision="fp32"):
@@ -397,7 +397,8 @@ def batched_extra(P, W, torch, steps=6000, stress=False):
         s = P.Simulation(c.nx, c.ny, 1, pol=c.pol, precision="fp32", absorb=c.absorb, sigma_max=W.SIGMA_MAX)
         s.set_permittivity(c.eps)
         s.set_source(c.lam, kh, eh, 1.0, W.RAMP_PERIODS)
-        s.set_ntff(c.box_lo, c.box_hi, *c.window)
+        if c.window[0] >= 0:             # runs shorter than a period (profiling) record no DFT
+            s.set_ntff(c.box_lo, c.box_hi, *c.window)
         sims.append(s)
     cells = sum(c.nx * c.ny for c in cases)
     for s in sims:
@@ -431,8 +432,8 @@ def batched_extra(P, W, torch, steps=6000, stress=False):
     res["autotune_us_per_step"] = tuned_us
     # counter bytes of the batched kernel over all its launches / the
     # algorithmic bytes of the same launches (profiles/, same kernel source)
-    rec = recorded_traffic("k_step2d_x2_batch_fp32_" + ("stress64" if stress else "seeded64"))
-    res["traffic_over_algorithmic"] = rec
+    res["traffic_over_algorithmic"] = None if stress else recorded_traffic(
+        "k_step2d_x2_batch_fp32_seeded64", field="traffic_over_algorithmic")
     b.close()
     for s in sims:
         s.close()
@@ -563,6 +564,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extras", default="copy,cylinder,streams,sphere_line,magnetic,line,batched,stress,adjoint",
                     help="comma list of extra measurements to run")
+    ap.add_argument("--cylinder-steps", type=int, default=8000,
+                    help="time steps of the 2-D cylinder extras (workload: 8000; fewer for profiling runs)")
     ap.add_argument("--batch-steps", type=int, default=6000,
                     help="time steps of the batched extras (workload: 6000; fewer for profiling runs)")
     ap.add_argument("--tile", default=None,
@@ -675,11 +678,12 @@ def main():
             line["roofline"]["measured_copy_GBs"] = copy_ceiling(P)
         th2 = np.arange(0.0, 360.0, 0.5)
         tiles = None
+        cs = args.cylinder_steps
         if "cylinder" in want:
-            line["extra"]["cylinder_2d"], tiles = cylinder_extra(Simulation, W, torch, 8000, th2)
+            line["extra"]["cylinder_2d"], tiles = cylinder_extra(Simulation, W, torch, cs, th2)
         if "streams" in want:
-            line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, 8000, th2, tiles)
-            line["extra"]["batched_job"] = batched_job_extra(P, W, torch, 8000, th2, tiles)
+            line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, cs, th2, tiles)
+            line["extra"]["batched_job"] = batched_job_extra(P, W, torch, cs, th2, tiles)
         if "sphere_line" in want and 384 in sizes and args.lbm_steps >= 144:
             r, S_line = sphere_line_extra(Simulation, W, torch, args.lbm_steps, theta)
             d = {}
