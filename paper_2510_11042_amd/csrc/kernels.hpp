@@ -103,6 +103,33 @@ template <> struct Cplx<double> { typedef double2 type; };
 // Steps of the incident line kept in its table: one captured graph chunk.
 constexpr int kLineSlots = 64;
 
+// x/3 and x/6 as if the constants were exact.  The collision is
+// f* = 2 f^eq - f with 2 f^eq = combination / 3, and the rounded 1/3 of
+// FP32 is 3.0e-8 too large (FP64: 1.9e-17 too small): multiplying by it
+// scales the moments D and B, which the collision conserves exactly, by
+// (1 + 6e-8) every step -- a systematic gain of 1e-4 along the ~1500 steps
+// a wave needs to cross a 1024^2 grid.  Splitting the constant into its
+// rounded head and the tail, fma(x, head, x * tail), rounds x/3 correctly
+// in all but rare ties, so the remaining rounding errors have no bias.
+// sixth(2x) == third(x) bit for bit (the halved head and tail are exact).
+template <typename T> struct Frac3;
+template <> struct Frac3<float> {
+    static constexpr float hi = 1.0f / 3.0f;
+    static constexpr float lo = (float)(1.0 / 3.0 - (double)(1.0f / 3.0f));   // -9.93e-9
+};
+template <> struct Frac3<double> {
+    static constexpr double hi = 1.0 / 3.0;
+    static constexpr double lo = 1.850371707708594e-17;   // 1/3 - hi = 2^-54 / 3
+};
+template <typename T>
+__device__ inline T third(T x) {
+    return fma(x, Frac3<T>::hi, x * Frac3<T>::lo);
+}
+template <typename T>
+__device__ inline T sixth(T x) {
+    return fma(x, Frac3<T>::hi * T(0.5), x * (Frac3<T>::lo * T(0.5)));
+}
+
 template <typename T>
 struct StepArgs {
     int nx, ny, nz;
@@ -291,38 +318,47 @@ __device__ inline void equilibrium2d(const T F[3], T scale, T q[11]) {
     }
 }
 
-// Collision at tau = 1/2: f <- 2 f^eq(F) - f, each population one fused
-// multiply-add (c = 2/6).
+// 2 f^eq - f for the eleven scalars from the fields' thirds F3 = F/3
+// (each rounded correctly by third() or sixth(), so no bias from the
+// rounded constant; the combinations and the subtraction then round
+// without bias too).
+template <typename T, int POL>
+__device__ inline void collide2d_thirds(const T F3[3], T f[11]) {
+    if (POL == TM) {
+        const T ez = F3[0], hx = F3[1], hy = F3[2];
+        f[0] = (ez - hy) - f[0];
+        f[1] = (ez + hy) - f[1];
+        f[2] = (ez + hx) - f[2];
+        f[3] = (ez - hx) - f[3];
+        f[4] = hx - f[4];
+        f[5] = hx - f[5];
+        f[6] = hy - f[6];
+        f[7] = hy - f[7];
+        f[8] = ez - f[8];
+        f[9] = hx - f[9];
+        f[10] = hy - f[10];
+    } else {
+        const T ex = F3[0], ey = F3[1], hz = F3[2];
+        f[0] = ex - f[0];
+        f[1] = ex - f[1];
+        f[2] = (ex - hz) - f[2];
+        f[3] = (ex + hz) - f[3];
+        f[4] = (ey + hz) - f[4];
+        f[5] = (ey - hz) - f[5];
+        f[6] = ey - f[6];
+        f[7] = ey - f[7];
+        f[8] = ex - f[8];
+        f[9] = ey - f[9];
+        f[10] = hz - f[10];
+    }
+}
+
+// Collision at tau = 1/2: f <- 2 f^eq(F) - f, every population a
+// combination of the fields divided by 3.
 template <typename T, int POL>
 __device__ inline void collide2d(const T F[3], T f[11]) {
-    const T c = T(1) / T(3);
-    if (POL == TM) {
-        const T Ez = F[0], Hx = F[1], Hy = F[2];
-        f[0] = fma(c, Ez - Hy, -f[0]);
-        f[1] = fma(c, Ez + Hy, -f[1]);
-        f[2] = fma(c, Ez + Hx, -f[2]);
-        f[3] = fma(c, Ez - Hx, -f[3]);
-        f[4] = fma(c, Hx, -f[4]);
-        f[5] = fma(c, Hx, -f[5]);
-        f[6] = fma(c, Hy, -f[6]);
-        f[7] = fma(c, Hy, -f[7]);
-        f[8] = fma(c, Ez, -f[8]);
-        f[9] = fma(c, Hx, -f[9]);
-        f[10] = fma(c, Hy, -f[10]);
-    } else {
-        const T Ex = F[0], Ey = F[1], Hz = F[2];
-        f[0] = fma(c, Ex, -f[0]);
-        f[1] = fma(c, Ex, -f[1]);
-        f[2] = fma(c, Ex - Hz, -f[2]);
-        f[3] = fma(c, Ex + Hz, -f[3]);
-        f[4] = fma(c, Ey + Hz, -f[4]);
-        f[5] = fma(c, Ey - Hz, -f[5]);
-        f[6] = fma(c, Ey, -f[6]);
-        f[7] = fma(c, Ey, -f[7]);
-        f[8] = fma(c, Ex, -f[8]);
-        f[9] = fma(c, Ey, -f[9]);
-        f[10] = fma(c, Hz, -f[10]);
-    }
+    const T F3[3] = {third(F[0]), third(F[1]), third(F[2])};
+    collide2d_thirds<T, POL>(F3, f);
 }
 
 // Accumulate the running DFT of the fields at a contour / probe node.
@@ -502,10 +538,10 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
     if (!LINE && !LREC && !MU) {
         // Collision and layer in one pass: with f* = 2 f^eq(F) - f and
         // f' = f* + sig (f^eq(R) - f*), linearity of f^eq gives
-        // f' = f^eq(G) - s f, G = 2F + sig (R - 2F), s = 1 - sig; written as
-        // fma(1/6, combo(G), -(s f)), which for sig = 0 (G = 2F exactly,
-        // s f = f exactly, 1/6 = (1/3)/2 exactly) is the plain collision's
-        // fma(1/3, combo(F), -f) bit for bit.
+        // f' = f^eq(G) - s f, G = 2F + sig (R - 2F), s = 1 - sig: the plain
+        // collision's combinations of G/6 with -s f fused in, which for
+        // sig = 0 (G = 2F exactly, s = 1, sixth(2x) == third(x), fma(-1, f,
+        // q) == q - f) is the plain collision bit for bit.
         if (MODE == 2 || (MODE == 0 && !(sig > T(0)))) {
             collide2d<T, POL>(F, f);
             return;
@@ -522,23 +558,24 @@ __device__ inline void cell_update2d(const StepArgs<T> &a, const StepConst<T> &s
             const T F2 = F[k] + F[k];
             G[k] = fma(sig, R[k] - F2, F2);
         }
-        const T sc = T(1) - sig, c = T(1) / T(6);
+        const T sc = T(1) - sig;
+        const T g0 = sixth(G[0]), g1 = sixth(G[1]), g2 = sixth(G[2]);
         T q[11];
         if (POL == TM) {
-            const T Ez = G[0], Hx = G[1], Hy = G[2];
-            q[0] = Ez - Hy; q[1] = Ez + Hy; q[2] = Ez + Hx; q[3] = Ez - Hx;
-            q[4] = q[5] = q[9] = Hx;
-            q[6] = q[7] = q[10] = Hy;
-            q[8] = Ez;
+            const T ez = g0, hx = g1, hy = g2;
+            q[0] = ez - hy; q[1] = ez + hy; q[2] = ez + hx; q[3] = ez - hx;
+            q[4] = q[5] = q[9] = hx;
+            q[6] = q[7] = q[10] = hy;
+            q[8] = ez;
         } else {
-            const T Ex = G[0], Ey = G[1], Hz = G[2];
-            q[0] = q[1] = q[8] = Ex;
-            q[2] = Ex - Hz; q[3] = Ex + Hz; q[4] = Ey + Hz; q[5] = Ey - Hz;
-            q[6] = q[7] = q[9] = Ey;
-            q[10] = Hz;
+            const T ex = g0, ey = g1, hz = g2;
+            q[0] = q[1] = q[8] = ex;
+            q[2] = ex - hz; q[3] = ex + hz; q[4] = ey + hz; q[5] = ey - hz;
+            q[6] = q[7] = q[9] = ey;
+            q[10] = hz;
         }
 #pragma unroll
-        for (int i = 0; i < 11; ++i) f[i] = fma(c, q[i], -(sc * f[i]));
+        for (int i = 0; i < 11; ++i) f[i] = fma(-sc, f[i], q[i]);
         return;
     }
     collide2d<T, POL>(F, f);
@@ -1248,34 +1285,36 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
             GE[k] = fma(sig, Er[k] - E2, E2);
             GH[k] = fma(sig, Hr[k] - H2, H2);
         }
-        const T c = T(1) / T(6), sc = T(1) - sig, r = eps - T(1);
+        const T sc = T(1) - sig, r = eps - T(1);
+        const T GE6[3] = {sixth(GE[0]), sixth(GE[1]), sixth(GE[2])};
+        const T GH6[3] = {sixth(GH[0]), sixth(GH[1]), sixth(GH[2])};
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
             const T cv[3] = {T(C3[d][0]), T(C3[d][1]), T(C3[d][2])};
             T cxh[3];
-            cross3(cv, GH, cxh);
+            cross3(cv, GH6, cxh);     // exact: permuted, signed components
 #pragma unroll
-            for (int k = 0; k < 3; ++k) f[4 * d + k] = fma(c, GE[k] - cxh[k], -(sc * f[4 * d + k]));
-            f[4 * d + 3] = fma(c, cv[0] * GH[0] + cv[1] * GH[1] + cv[2] * GH[2], -(sc * f[4 * d + 3]));
+            for (int k = 0; k < 3; ++k) f[4 * d + k] = fma(-sc, f[4 * d + k], GE6[k] - cxh[k]);
+            f[4 * d + 3] = fma(-sc, f[4 * d + 3], cv[0] * GH6[0] + cv[1] * GH6[1] + cv[2] * GH6[2]);
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) f[24 + k] = fma(r, GE[k], -(sc * f[24 + k]));
         return;
     }
-    // collision f <- 2 f^eq - f, one fused multiply-add per population
-    // (for sig = 0 the one-pass form above rounds identically: the factor 2
-    // is exact and 1/6 is 1/3 halved)
+    // collision f <- 2 f^eq - f, every population a combination of E/3 and
+    // H/3 (each rounded correctly by third()) minus f
     {
-        const T c = T(1) / T(3);
         const T r = T(2) * (eps - T(1));
+        const T E3[3] = {third(E[0]), third(E[1]), third(E[2])};
+        const T H3[3] = {third(H[0]), third(H[1]), third(H[2])};
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
             const T cv[3] = {T(C3[d][0]), T(C3[d][1]), T(C3[d][2])};
             T cxh[3];
-            cross3(cv, H, cxh);
+            cross3(cv, H3, cxh);      // exact: permuted, signed components
 #pragma unroll
-            for (int k = 0; k < 3; ++k) f[4 * d + k] = fma(c, E[k] - cxh[k], -f[4 * d + k]);
-            f[4 * d + 3] = fma(c, cv[0] * H[0] + cv[1] * H[1] + cv[2] * H[2], -f[4 * d + 3]);
+            for (int k = 0; k < 3; ++k) f[4 * d + k] = (E3[k] - cxh[k]) - f[4 * d + k];
+            f[4 * d + 3] = (cv[0] * H3[0] + cv[1] * H3[1] + cv[2] * H3[2]) - f[4 * d + 3];
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) f[24 + k] = fma(r, E[k], -f[24 + k]);
@@ -1706,15 +1745,15 @@ __device__ inline void fields2d_T(const T u[3], T eps, T inv_eps, T o[11]) {
 // Q^T l: the equilibrium map transposed (fields <- 11 scalars).
 template <typename T, int POL>
 __device__ inline void equilibrium2d_T(const T l[11], T u[3]) {
-    const T c = T(1) / T(6);
+    // the factor 1/6 through sixth(): no bias from the rounded constant
     if (POL == TM) {
-        u[0] = c * (l[0] + l[1] + l[2] + l[3] + l[8]);
-        u[1] = c * (l[2] - l[3] + l[4] + l[5] + l[9]);
-        u[2] = c * (-l[0] + l[1] + l[6] + l[7] + l[10]);
+        u[0] = sixth(l[0] + l[1] + l[2] + l[3] + l[8]);
+        u[1] = sixth(l[2] - l[3] + l[4] + l[5] + l[9]);
+        u[2] = sixth(-l[0] + l[1] + l[6] + l[7] + l[10]);
     } else {
-        u[0] = c * (l[0] + l[1] + l[2] + l[3] + l[8]);
-        u[1] = c * (l[4] + l[5] + l[6] + l[7] + l[9]);
-        u[2] = c * (-l[2] + l[3] + l[4] - l[5] + l[10]);
+        u[0] = sixth(l[0] + l[1] + l[2] + l[3] + l[8]);
+        u[1] = sixth(l[4] + l[5] + l[6] + l[7] + l[9]);
+        u[2] = sixth(-l[2] + l[3] + l[4] - l[5] + l[10]);
     }
 }
 
