@@ -13,9 +13,11 @@ state (2 x 6.1 GB and 2 x 14.5 GB per run) is far larger than the 256 MB
 Infinity Cache, so the step kernel streams from HBM.
 
 Reported value: lattice updates per second over the whole step (MLUPS).
-roofline: the 3-D two-step kernel k_step3d_x2, 220 B per cell per launch
-(the 27-scalar state read and written once per two time steps, eps read),
-against the 8 TB/s HBM peak.  Extras: the 2-D cylinder job (1024^2, eight
+roofline: the 3-D two-step kernel k_step3d_x2 against the 8 TB/s HBM peak,
+counting each launch's minimal traffic: the state read and written once per
+two time steps -- 27 scalars and eps (220 B) for a dielectric cell, the 24
+moving scalars (192 B) for a vacuum cell, whose rest populations are
+identically zero.  Extras: the 2-D cylinder job (1024^2, eight
 solves, Infinity-Cache resident), two-stream and batched forms of it, the
 sphere with the exact incident line instead of the companion, the
 permeability and incident-line kernel variants, the batched configurations
@@ -38,7 +40,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS and % HBM roofline (fwd, adjoint, batched) at stated accuracy vs oracle"
 HBM_PEAK_GBS = 8000.0
 BYTES_2D = 11 * 4 * 2 + 4      # reduced 2-D state read + written, eps read (FP32)
-BYTES_3D = 27 * 4 * 2 + 4
+BYTES_3D = 27 * 4 * 2 + 4      # dielectric cell: 27 scalars read + written, eps read (FP32)
+BYTES_3D_VAC = 24 * 4 * 2      # vacuum cell: the 24 moving scalars (e_0 is identically zero)
 CSRC = os.path.join(ROOT, "paper_2510_11042_amd", "csrc")
 # the kernels and their launchers (the runtime lbm_em.hip is not hashed)
 KERNEL_SOURCES = sorted(os.path.join("paper_2510_11042_amd", "csrc", f) for f in os.listdir(CSRC)
@@ -203,6 +206,7 @@ def sphere_job(Simulation, W, n, lbm_steps, tile=None, precision="fp32"):
     """The sphere (x = 6, lambda = 24, eps 2.25, W = 24) on an n^3 grid and
     its eps = 1 companion, contour DFT over the last period."""
     case = W.sphere_case(n=n, steps=lbm_steps)
+    case.n_dielectric = int(np.count_nonzero(case.eps != 1.0))
     sims = []
     for eps in (case.eps, None):
         s = Simulation(n, n, n, pol="3D", precision=precision, absorb=(case.W,) * 3, sigma_max=W.SIGMA_MAX)
@@ -221,10 +225,17 @@ def sphere_job(Simulation, W, n, lbm_steps, tile=None, precision="fp32"):
 SPHERE_PHI = (0.0, 45.0, 90.0)
 
 
+def launch_bytes_3d(n, n_dielectric):
+    """Minimal bytes of one two-step launch of an n^3 grid with n_dielectric
+    cells of eps_r != 1 (FP32)."""
+    return (n ** 3 - n_dielectric) * BYTES_3D_VAC + n_dielectric * BYTES_3D
+
+
 def run_sphere(jobs, lbm_steps, theta, torch, events):
     """One benchmark step over the sphere jobs; appends (start, end event,
-    launches, cells) around the stepping of each grid size.  Runs too short
-    for the DFT window (profiling) skip the far field."""
+    launches, cells, minimal bytes per launch averaged over the sphere and its
+    companion) around the stepping of each grid size.  Runs too short for the
+    DFT window (profiling) skip the far field."""
     out = {}
     for case, (tot, inc) in jobs:
         tot.reset()
@@ -235,7 +246,8 @@ def run_sphere(jobs, lbm_steps, theta, torch, events):
         tot.step(lbm_steps)
         inc.step(lbm_steps)
         e1.record()
-        events.append((e0, e1, 2 * lbm_steps // tot.get_fusion(), case.n ** 3))
+        nb = 0.5 * (launch_bytes_3d(case.n, case.n_dielectric) + launch_bytes_3d(case.n, 0))
+        events.append((e0, e1, 2 * lbm_steps // tot.get_fusion(), case.n ** 3, nb))
         # profiling runs too short for the wave to reach the sphere skip the far field
         if lbm_steps >= 1000 and lbm_steps >= case.window[0] + case.window[1]:
             for phi in SPHERE_PHI:
@@ -619,30 +631,32 @@ def main():
     value = updates / (ms_per_step * 1e-3) / 1e6
 
     # the step kernel advances two time steps per launch (state read and
-    # written once per launch): 220 B per cell per launch are algorithmic
+    # written once per launch): 192 B per vacuum cell and 220 B per
+    # dielectric cell per launch are algorithmic
     tot0 = jobs[0][1][0]
     fuse = tot0.get_fusion()
     kname = "k_step3d_x2" if fuse == 2 else "k_step3d"
     per_size = {}
     for case, (tot, inc) in jobs:
-        ev = [(a, b, n) for a, b, n, c in events if c == case.n ** 3]
-        ms = sum(a.elapsed_time(b) for a, b, _ in ev) / sum(n for _, _, n in ev)
-        alg = case.n ** 3 * BYTES_3D
+        ev = [(a, b, n, nb) for a, b, n, c, nb in events if c == case.n ** 3]
+        ms = sum(a.elapsed_time(b) for a, b, _, _ in ev) / sum(n for _, _, n, _ in ev)
+        alg = ev[0][3]
         tl = list(tot.get_fusion_tile()) if fuse == 2 else list(tot.get_tile())
         per_size[str(case.n)] = {
             "ms_per_launch": ms, "algorithmic_bytes_per_launch": alg,
             "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "tile": tl, "MLUPS_per_instance": case.n ** 3 * fuse / (ms * 1e-3) / 1e6,
             "per_update_equivalent_GBs": alg * fuse / (ms * 1e-3) / 1e9,
+            "full_state_GBs": case.n ** 3 * BYTES_3D / (ms * 1e-3) / 1e9,
             "traffic": recorded_traffic(f"{kname}_fp32_{case.n}", tl if fuse == 2 else None)}
-    tot_ms = sum(a.elapsed_time(b) for a, b, _, _ in events)
-    tot_bytes = sum(n * c * BYTES_3D for _, _, n, c in events)
+    tot_ms = sum(a.elapsed_time(b) for a, b, _, _, _ in events)
+    tot_bytes = sum(n * nb for _, _, n, _, nb in events)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
     traffics = [per_size[k]["traffic"] for k in per_size]
     traffic = None
     if all(t is not None for t in traffics):
         # counter bytes over all launches of the step, per launch on average
-        nl = {str(case.n): sum(n for _, _, n, c in events if c == case.n ** 3) for case, _ in jobs}
+        nl = {str(case.n): sum(n for _, _, n, c, _ in events if c == case.n ** 3) for case, _ in jobs}
         traffic = sum(per_size[k]["traffic"] * nl[k] for k in per_size) / sum(nl.values())
     line = {
         "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -656,11 +670,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname + "<float>", "steps_per_launch": fuse,
                      "per_size": per_size,
-                     "frac_note": "achieved counts the launch's minimal traffic (the 27-scalar state read and "
-                                  "written once per launch, eps read: 220 B per cell), summed over every launch "
-                                  "of the timed steps and divided by their summed time (HIP events on the "
-                                  "library's stream around each run; the figure includes the gaps between "
-                                  "launches); per_update_equivalent_GBs counts 220 B per cell update",
+                     "frac_note": "achieved counts the launch's minimal traffic (the state read and written "
+                                  "once per launch: 27 scalars and eps, 220 B, per dielectric cell; the 24 moving "
+                                  "scalars, 192 B, per vacuum cell, whose rest populations are identically zero), "
+                                  "summed over every launch of the timed steps and divided by their summed time "
+                                  "(HIP events on the library's stream around each run; the figure includes the "
+                                  "gaps between launches); per_update_equivalent_GBs counts those bytes per cell "
+                                  "update; full_state_GBs counts 220 B per cell per launch",
                      "note": "state 2 x 6.1 GB (384^3) and 2 x 14.5 GB (512^3) per run: HBM-resident"},
     }
     for k, S in res.items():

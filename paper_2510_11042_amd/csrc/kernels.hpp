@@ -172,6 +172,10 @@ struct StepArgs {
     T *line_rec;
     double *line_acc;
     int line_axis, line_n;
+    // 3-D: per plane z, the box (x_lo, x_hi, y_lo, y_hi) holding every cell
+    // whose eps_r differs from 1 or whose rest populations may be non-zero
+    // (empty: x_lo > x_hi); NULL: no plane is known to be vacuum
+    const int4 *vbox;
 };
 
 // Layer strength at coordinate x of an axis of n cells with a layer of W
@@ -1240,7 +1244,7 @@ __device__ inline T sigma3d(const StepArgs<T> &a, int x, int y, int z) {
 // 3-D per-cell update (moments, DFT sample, collision, layer/source);
 // inv_eps = 1/eps and sig = sigma3d(x, y, z) from the caller; record: the
 // cell is in the domain and owned by this thread (DFT samples).
-template <typename T, bool LINE = false, bool LREC = false>
+template <typename T, bool LINE = false, bool LREC = false, bool DFT = true>
 __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, int z, T eps,
                                      T inv_eps, T sig, T f[27], bool record, const T *fl = nullptr,
                                      int fl_stride = 0) {
@@ -1258,7 +1262,7 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
                 pa[6 + 2 * c + 1] += (double)H[c] * st.ci;
             }
         }
-    } else if (st.dft && record) {
+    } else if (DFT && st.dft && record) {
         const double G[6] = {E[0], E[1], E[2], H[0], H[1], H[2]};
         dft_accumulate<0x3f>(a, st, 3, x, y, z, G);
     }
@@ -1358,8 +1362,10 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
 
 // Pulled populations and eps of the in-domain cell (x, y, z): direction d
 // (planes 4d .. 4d+3) from r - c_d with the open-boundary clamp or wrap.
+// vac: the cell is vacuum with zero rest populations (eps_r = 1 and e_0 = 0
+// exactly; see vacuum_plane), so neither is read.
 template <typename T>
-__device__ inline void pull3d(const StepArgs<T> &a, int x, int y, int z, T f[27], T &e) {
+__device__ inline void pull3d(const StepArgs<T> &a, int x, int y, int z, T f[27], T &e, bool vac = false) {
     const int64_t P = a.plane;
     const T *s = a.src;
     const uint32_t sy = (uint32_t)a.sy, sz = (uint32_t)a.sz;
@@ -1374,9 +1380,26 @@ __device__ inline void pull3d(const StepArgs<T> &a, int x, int y, int z, T f[27]
     for (int d = 0; d < 6; ++d)
 #pragma unroll
         for (int k = 0; k < 4; ++k) f[4 * d + k] = *at(s + (4 * d + k) * P, src[d]);
+    if (vac) {
+        f[24] = f[25] = f[26] = T(0);
+        e = T(1);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[24 + k] = *at(s + (24 + k) * P, c);
     e = *at(a.eps, c);
+}
+
+// Whether every cell of the rectangle [xl, xh] x [yl, yh] of plane z is
+// vacuum with zero rest populations.  A cell with eps_r = 1 whose e_0 is zero
+// keeps e_0 = 0: its equilibrium (eps_r - 1) E is zero, the collision only
+// flips the sign and the layer relaxes towards zero.  Such a cell needs
+// neither e_0 nor eps_r from memory, and its stored e_0 stays zero.
+template <typename T>
+__device__ inline bool vacuum_plane(const StepArgs<T> &a, int z, int xl, int xh, int yl, int yh) {
+    if (!a.vbox) return false;
+    const int4 b = a.vbox[z];
+    return b.x > b.y || b.y < xl || b.x > xh || b.w < yl || b.z > yh;
 }
 
 // LINE: the layer follows the exact incident line a.line_tab.
@@ -1494,7 +1517,11 @@ struct X3Lds {
 // LINE: exact incident line along z (the only direction a 3-D line takes):
 // its values depend on the plane alone, so each iteration stages the next
 // iteration's 2 x 27 values in LDS before its second barrier.
-template <typename T, int TX, int TY, bool LINE = false>
+// DFT: the launch may fall into the DFT window (the contour accumulation is
+// compiled in only then: it costs registers the plain steps do not need).
+// Planes on which the tile and its ring are vacuum (vacuum_plane) neither
+// read nor write the rest populations and read no eps_r.
+template <typename T, int TX, int TY, bool LINE = false, bool DFT = true>
 __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
     constexpr int NT = TX * TY;
     constexpr int NR = 2 * TX + 2 * TY;
@@ -1524,6 +1551,17 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
     else if (tid < 2 * TX + TY) { rx = x0 - 1; ry = y0 + (tid - 2 * TX); }
     else { rx = x0 + TX; ry = y0 + (tid - 2 * TX - TY); }
     const int rxf = fold(rx, a.nx, a.W[0]), ryf = fold(ry, a.ny, a.W[1]);
+    // folded x and y ranges of the tile and its ring (a periodic axis whose
+    // ring wraps takes the whole axis)
+    auto span = [](int lo, int hi, int n, int W, int &l, int &h) {
+        if (W) { l = max(lo, 0); h = min(hi, n - 1); }
+        else if (lo < 0 || hi >= n) { l = 0; h = n - 1; }
+        else { l = lo; h = hi; }
+    };
+    int vxl, vxh, vyl, vyh;
+    span(x0 - 1, x0 + TX, a.nx, a.W[0], vxl, vxh);
+    span(y0 - 1, y0 + TY, a.ny, a.W[1], vyl, vyh);
+    bool vprev = false;   // plane p - 1 was vacuum
     // per-column history: +z movers of planes p-2 (pz0) and p-1 (pz1); rest
     // scalars, eps, 1/eps and sigma of plane p-1
     T pz0[4], pz1[4], rest[3], ep = T(1), ip = T(1), sg = T(0);
@@ -1549,11 +1587,13 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
     for (int p = zb - 1; p <= ze; ++p) {
         const int pf = fold(p, a.nz, a.W[2]);
         X3Lds<T, TX, TY> &B = L[p & 1];
+        const bool vp = vacuum_plane(a, pf, vxl, vxh, vyl, vyh);
         // step t on plane p: own cell ...
         T f[27], e;
-        pull3d<T>(a, xf, yf, pf, f, e);
+        pull3d<T>(a, xf, yf, pf, f, e, vp);
         const T ie = recip(e), sgp = sigma3d<T>(a, xf, yf, pf);
-        cell_update3d<T, LINE>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze, lz[p & 1][0], 1);
+        cell_update3d<T, LINE, false, DFT>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze, lz[p & 1][0],
+                                           1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             B.xm[k][oy][ox + 1] = f[k];
@@ -1564,9 +1604,9 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
         // ... and the ring cell (only the movers that step t+1 pulls)
         if (ring) {
             T g[27], ge;
-            pull3d<T>(a, rxf, ryf, pf, g, ge);
-            cell_update3d<T, LINE>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf), g, false,
-                                   lz[p & 1][0], 1);
+            pull3d<T>(a, rxf, ryf, pf, g, ge, vp);
+            cell_update3d<T, LINE, false, DFT>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf), g,
+                                               false, lz[p & 1][0], 1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (tid < TX) B.ym[k][0][tid] = g[8 + k];
@@ -1597,11 +1637,15 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
             h[24] = rest[0];
             h[25] = rest[1];
             h[26] = rest[2];
-            cell_update3d<T, LINE>(a, s1, xf, yf, q, ep, ip, sg, h, own, lz[p & 1][1], 1);
+            cell_update3d<T, LINE, false, DFT>(a, s1, xf, yf, q, ep, ip, sg, h, own, lz[p & 1][1], 1);
             if (own) {
+                // streamed out: the next launch reads it from HBM
                 const uint32_t c = (uint32_t)q * sz + (uint32_t)y * sy + (uint32_t)x;
 #pragma unroll
-                for (int i = 0; i < 27; ++i) *at(a.dst + i * P, c) = h[i];
+                for (int i = 0; i < 24; ++i) __builtin_nontemporal_store(h[i], at(a.dst + i * P, c));
+                if (!vprev)
+#pragma unroll
+                    for (int i = 24; i < 27; ++i) __builtin_nontemporal_store(h[i], at(a.dst + i * P, c));
             }
         }
         if (LINE && p < ze) stage_line(p + 1);
@@ -1618,6 +1662,7 @@ __global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
         ep = e;
         ip = ie;
         sg = sgp;
+        vprev = vp;
     }
 }
 

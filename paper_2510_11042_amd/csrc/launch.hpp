@@ -37,9 +37,11 @@ inline bool launch_step2d_x2(const StepArgs<T> &a, int pol, int tx, int ty, hipS
     return pol == TM ? launch_step2d_x2_pol<T, TM>(a, tx, ty, s) : launch_step2d_x2_pol<T, TE>(a, tx, ty, s);
 }
 
-// Two steps, 3-D z march (k_step3d_x2), z chunks of zc planes.
+// Two steps, 3-D z march (k_step3d_x2), z chunks of zc planes.  dft: the
+// launch may fall into the DFT window (selects the instantiation that
+// accumulates the contour DFT).
 template <typename T>
-bool launch_step3d_x2(const StepArgs<T> &a, int tx, int ty, int zc, hipStream_t s);
+bool launch_step3d_x2(const StepArgs<T> &a, int tx, int ty, int zc, bool dft, hipStream_t s);
 
 // Batched persistent launches over a flat (instance, tile) list.
 template <typename T>

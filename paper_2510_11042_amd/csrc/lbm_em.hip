@@ -103,10 +103,18 @@ struct lbm_em {
     int probe[3] = {0, 0, 0};
     int64_t nnodes = 0, win0 = 0, winlen = 0;
     double *acc = nullptr;
-    // graph replay
+    // graph replay: [chunk may meet the DFT window][starting buffer parity]
     int64_t *t_dev = nullptr;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};   // indexed by starting buffer parity
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    mutable bool graph_dft = true;      // set while capturing: the chunk may meet the DFT window
     int dev = 0;
+    // 3-D vacuum planes (see vacuum_plane in kernels.hpp): per plane z the box
+    // of cells whose eps_r differs from 1 (eps_box) and the box the kernels
+    // use (run_box: also every cell that may still hold non-zero rest
+    // populations since the last reset); vbox is the device copy of run_box
+    std::vector<int4> eps_box, run_box;
+    int4 *vbox = nullptr;
+    mutable bool state_clean = true;    // both state buffers are zero (created or reset, never stepped)
     // inverse design (adjoint)
     bool adj_set = false;
     lbm_em *adj_inc = nullptr;
@@ -189,6 +197,7 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
     a.dst = (T *)dst;
     a.eps = (const T *)h->eps;
     a.mu = (const T *)h->mu;
+    a.vbox = h->vbox;
     a.src_on = h->src_on ? 1 : 0;
     a.period = h->period > 0 ? h->period : 1;
     if (h->src_on) {
@@ -225,6 +234,7 @@ StepArgs<T> make_args(const lbm_em *h, const void *src, void *dst) {
 template <typename T>
 void launch_step_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base,
                    int64_t t_off, hipStream_t s, bool dft, void *hist, int64_t hist_t0) {
+    h->state_clean = false;
     StepArgs<T> a = make_args<T>(h, src, dst);
     a.t_base = t_base;
     a.t_off = t_off;
@@ -344,7 +354,10 @@ void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
     a.tiles_y = (a.ny + ty - 1) / ty;
     const int tiles = a.tiles_x * a.tiles_y;
     const int zc = x3_chunk(a.nz, tiles, h->cus * std::max(1, 1024 / (tx * ty)));
-    if (!launch_step3d_x2<T>(a, tx, ty, zc, s)) fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
+    // the contour accumulation is compiled in only for launches that may
+    // meet the window: steps t_off, t_off + 1, or a captured chunk flagged so
+    const bool dft = a.dft_on && (a.t_base ? h->graph_dft : (a.t_off + 2 > h->win0 && a.t_off < h->win0 + h->winlen));
+    if (!launch_step3d_x2<T>(a, tx, ty, zc, dft, s)) fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
 }
 
 template <typename T>
@@ -357,6 +370,7 @@ void launch_step2_2d(StepArgs<T> a, int pol, int tx, int ty, hipStream_t s) {
 template <typename T>
 void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *t_base, int64_t t_off,
                     hipStream_t s, bool dft, void *hist = nullptr, int64_t hist_t0 = 0) {
+    h->state_clean = false;
     StepArgs<T> a = make_args<T>(h, src, dst);
     a.t_base = t_base;
     a.t_off = t_off;
@@ -401,16 +415,18 @@ bool tile_ok(const lbm_em *h, int vx, int bx, int by) {
 }
 
 void drop_graphs(lbm_em *h) {
-    for (auto &g : h->graph)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto &gw : h->graph)
+        for (auto &g : gw)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
 }
 
 // Capture kGraphChunk steps (starting from buffer parity p) plus the device
-// step-counter advance into one executable graph.
-hipGraphExec_t build_graph(lbm_em *h, int p) {
+// step-counter advance into one executable graph.  win: the chunks it will
+// replay may meet the DFT window (3-D: selects the kernel instantiation).
+hipGraphExec_t build_graph(lbm_em *h, int p, bool win) {
     hipStream_t cs = nullptr;
     hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
     hipGraph_t g = nullptr;
@@ -420,6 +436,7 @@ hipGraphExec_t build_graph(lbm_em *h, int p) {
         hip_check(e, "hipStreamBeginCapture");
     }
     int par = p;
+    h->graph_dft = win;
     // an incident line held in LDS takes the whole chunk in one launch up front
     const bool line_chunk = h->line && line_in_lds(h);
     if (line_chunk) launch_line(h, p, h->t_dev, 0, cs, kGraphChunk, false);
@@ -435,6 +452,7 @@ hipGraphExec_t build_graph(lbm_em *h, int p) {
         }
     }
     hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, cs, h->t_dev, (int64_t)kGraphChunk);
+    h->graph_dft = true;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
     hip_check(e, "hipStreamEndCapture");
@@ -451,11 +469,15 @@ void do_steps(lbm_em *h, int64_t n, hipStream_t on = nullptr) {
     hipStream_t st = on ? on : h->stream;
     int64_t chunks = n / kGraphChunk;
     if (chunks > 0) {
-        if (!h->graph[h->cur]) h->graph[h->cur] = build_graph(h, h->cur);
         hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, st, h->t_dev, h->t);
         hip_check(hipGetLastError(), "k_set_time");
         for (int64_t c = 0; c < chunks; ++c) {
-            hip_check(hipGraphLaunch(h->graph[h->cur], st), "hipGraphLaunch");
+            // 3-D chunks outside the DFT window replay the graph whose
+            // kernels carry no contour accumulation
+            const int64_t tc = h->t + c * kGraphChunk;
+            const int win = h->dim != 3 || (h->dft_set && tc < h->win0 + h->winlen && tc + kGraphChunk > h->win0);
+            if (!h->graph[win][h->cur]) h->graph[win][h->cur] = build_graph(h, h->cur, win);
+            hip_check(hipGraphLaunch(h->graph[win][h->cur], st), "hipGraphLaunch");
             // a chunk flips the buffers an even number of times (32 fused
             // or 64 single launches): the parity is unchanged
         }
@@ -873,10 +895,23 @@ void check_incident(const lbm_em *h, const lbm_em *inc) {
     if (inc->t < inc->win0 + inc->winlen) fail(LBM_EM_ESTATE, "incident DFT window not completed");
 }
 
+void upload_vbox(lbm_em *h) {
+    if (!h->vbox) return;
+    hip_check(hipMemcpyAsync(h->vbox, h->run_box.data(), h->run_box.size() * sizeof(int4), hipMemcpyHostToDevice,
+                             h->stream), "vacuum boxes H2D");
+    sync(h);
+}
+
 void reset_state(lbm_em *h) {
     const size_t bytes = (size_t)h->plane * h->nplanes * h->elem;
     hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset state");
     hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset state");
+    // zero state: only cells with eps_r != 1 can acquire rest populations
+    h->state_clean = true;
+    if (h->vbox) {
+        h->run_box = h->eps_box;
+        upload_vbox(h);
+    }
     if (h->acc)
         hip_check(hipMemsetAsync(h->acc, 0, (size_t)(h->nnodes + 1) * 12 * sizeof(double), h->stream), "hipMemset dft");
     h->t = 0;
@@ -958,12 +993,15 @@ void free_handle(lbm_em *h) {
     hfree(h->ck);
     hfree(h->adj_P);
     hfree(h->wtab);
+    hfree(h->vbox);
     delete h;
 }
 
 // Material map upload shared by eps_r and mu_r: validate (finite, >= 1) on
 // a host copy, then convert into the padded plane `dst` of the handle.
-void load_material(lbm_em *h, const void *src, int32_t where, int32_t dtype, void *dst, const char *name) {
+// boxes (3-D eps_r): per plane, the box of the cells whose value is not 1.
+void load_material(lbm_em *h, const void *src, int32_t where, int32_t dtype, void *dst, const char *name,
+                   std::vector<int4> *boxes = nullptr) {
     if (dtype != LBM_EM_FP32 && dtype != LBM_EM_FP64) fail(LBM_EM_EINVAL, "dtype must be FP32 or FP64");
     if (where != LBM_EM_HOST && where != LBM_EM_DEVICE) fail(LBM_EM_EINVAL, "where must be HOST or DEVICE");
     select_device(h);
@@ -979,6 +1017,19 @@ void load_material(lbm_em *h, const void *src, int32_t where, int32_t dtype, voi
     for (size_t i = 0; i < cells; ++i) {
         double v = dtype == LBM_EM_FP32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
         if (!std::isfinite(v) || v < 1.0) fail(LBM_EM_EINVAL, std::string(name) + " must be finite and >= 1");
+    }
+    if (boxes) {
+        boxes->assign(c.nz, make_int4(c.nx, -1, c.ny, -1));   // empty: x_lo > x_hi
+        for (size_t i = 0; i < cells; ++i) {
+            const double v = dtype == LBM_EM_FP32 ? ((const float *)host.data())[i] : ((const double *)host.data())[i];
+            if (v == 1.0) continue;
+            const int x = (int)(i % c.nx), y = (int)(i / c.nx % c.ny), z = (int)(i / ((size_t)c.nx * c.ny));
+            int4 &b = (*boxes)[z];
+            b.x = std::min(b.x, x);
+            b.y = std::max(b.y, x);
+            b.z = std::min(b.z, y);
+            b.w = std::max(b.w, y);
+        }
     }
     void *d_in = nullptr;
     hip_check(hipMalloc(&d_in, host.size()), "hipMalloc");
@@ -1195,6 +1246,12 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             hip_check(hipMemsetAsync(h->buf[0], 0, bytes, h->stream), "hipMemset");
             hip_check(hipMemsetAsync(h->buf[1], 0, bytes, h->stream), "hipMemset");
             fill_ones(h, h->eps);   // eps_r = 1 everywhere (padding included)
+            if (h->dim == 3) {
+                h->eps_box.assign(c.nz, make_int4(c.nx, -1, c.ny, -1));
+                h->run_box = h->eps_box;
+                hip_check(hipMalloc(&h->vbox, (size_t)c.nz * sizeof(int4)), "hipMalloc vacuum boxes");
+                upload_vbox(h);
+            }
             hip_check(hipStreamSynchronize(h->stream), "sync");
         } catch (...) {
             free_handle(h);
@@ -1216,7 +1273,23 @@ lbm_em_status lbm_em_set_permittivity(lbm_em_handle hh, const void *eps, int32_t
     return guarded([&] {
         lbm_em *h = check_handle(hh);
         if (!eps) fail(LBM_EM_EINVAL, "null eps");
-        load_material(h, eps, where, dtype, h->eps, "eps_r");
+        std::vector<int4> boxes;
+        load_material(h, eps, where, dtype, h->eps, "eps_r", h->vbox ? &boxes : nullptr);
+        if (h->vbox) {
+            // after steps, cells that were not vacuum may keep rest populations
+            std::vector<int4> run = boxes;
+            if (!h->state_clean)
+                for (size_t z = 0; z < run.size(); ++z) {
+                    const int4 o = h->run_box[z];
+                    int4 &b = run[z];
+                    if (o.x > o.y) continue;
+                    if (b.x > b.y) { b = o; continue; }
+                    b = make_int4(std::min(b.x, o.x), std::max(b.y, o.y), std::min(b.z, o.z), std::max(b.w, o.w));
+                }
+            h->eps_box = std::move(boxes);
+            h->run_box = std::move(run);
+            upload_vbox(h);
+        }
     });
 }
 

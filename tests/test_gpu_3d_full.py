@@ -3,9 +3,15 @@
 * 384^3 sphere (x = 6 at lambda = 24, eps 2.25, W = 24) in the library's
   default launch configuration (two steps per launch, default tile, z
   chunks chosen for the device): bit-identical to one step per launch over
-  two graph chunks and an odd trailing step, fields and contour phasors.
+  three graph chunks (the first outside the DFT window, so it replays the
+  kernels without the contour accumulation) and an odd trailing step,
+  fields and contour phasors.
 * FP64 and FP32 against the oracle on a 160 x 96 x 128 grid, where the
   default tile leaves ragged x tiles and the z march takes several chunks.
+* A permittivity map changed between steps, against the oracle: the 3-D
+  state keeps the rest populations e_0 as the literal scheme does, so cells
+  that leave the dielectric keep theirs (the two-step kernel must not treat
+  their planes as vacuum) and cells that enter it start from zero.
 """
 import numpy as np
 import pytest
@@ -37,19 +43,19 @@ def _sphere_sim(Sim, case, prec="fp32"):
 
 
 def test_sphere_384_two_steps_per_launch_bit_identical(Sim):
-    case = W.sphere_case(n=384, steps=131)
+    case = W.sphere_case(n=384, steps=195)
     runs = []
     for fuse in (2, 1):
         s = _sphere_sim(Sim, case)
         # a contour through the forced layers (the wave is there from the
-        # start), window inside the run
-        s.set_ntff((8, 8, 8), (375, 375, 375), 40, 72)
+        # start), window [100, 172): graph chunk [0, 64) lies before it
+        s.set_ntff((8, 8, 8), (375, 375, 375), 100, 72)
         if fuse == 1:
             s.set_fusion(1)
         say("384^3 fusion", s.get_fusion(), s.get_fusion_tile())
-        for n in (64, 64, 3):
+        for n in (64, 128, 3):
             s.step(n)
-        assert s.t == 131
+        assert s.t == 195
         E, H = s.fields()
         X, p = s.phasors()
         runs.append((E, H, X, p))
@@ -88,6 +94,52 @@ def test_multichunk_ragged_grid_vs_oracle(Sim, prec):
     Eg, Hg = s.fields()
     # the wave has reached the first scatterer
     assert np.abs(Eo[45:75, 35:60, 68:94]).max() > 0.1
+    if prec == "fp64":
+        err = max(max_rel(Eg, Eo), max_rel(Hg, Ho))
+        say("fp64 max rel", err)
+        assert err <= 1e-12
+    else:
+        err = rel_l2(np.concatenate([Eg.ravel(), Hg.ravel()]), np.concatenate([Eo.ravel(), Ho.ravel()]))
+        say("fp32 rel L2", err)
+        assert err <= 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("order,prec", [("leave", "fp64"), ("enter", "fp64"), ("leave", "fp32")])
+def test_permittivity_change_between_steps_vs_oracle(Sim, order, prec):
+    nx, ny, nz = 72, 40, 48
+    absorb = (8, 8, 8)
+    lam = 10.0
+    steps1, steps2 = 90, 60
+    z, y, x = np.ogrid[0:nz, 0:ny, 0:nx]
+    blob = np.ones((nz, ny, nx))
+    blob[(x - 30.0) ** 2 + (y - 20.0) ** 2 + (z - 24.0) ** 2 < 7.0 ** 2] = 2.5
+    vac = np.ones((nz, ny, nx))
+    first, second = (blob, vac) if order == "leave" else (vac, blob)
+    k3, e3 = [0.0, 0.0, 1.0], [1.0, 0.0, 0.0]
+    centre = [(nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0]
+    say("eps change", order, prec)
+    o = Oracle(nx, ny, nz, absorb, W.SIGMA_MAX)
+    o.set_eps(first)
+    o.set_source(lam, k3, e3, 1.0, 1.0, centre)
+    o.step(steps1)
+    if order == "leave":
+        # the dielectric holds rest populations e_0 (population 0, the
+        # first three components) when its map is removed
+        e0 = o.get_state()[..., 0, 0:3]
+        assert np.abs(e0).max() > 1e-3
+    o.set_eps(second)
+    o.step(steps2)
+    Eo, Ho = o.fields()
+    s = Sim(nx, ny, nz, pol="3D", precision=prec, absorb=absorb, sigma_max=W.SIGMA_MAX)
+    s.set_permittivity(first)
+    s.set_source(lam, k3, e3, 1.0, 1.0)
+    assert s.get_fusion() == 2
+    s.step(steps1)
+    s.set_permittivity(second)
+    s.step(steps2)
+    Eg, Hg = s.fields()
+    assert np.abs(Eo[17:32, 13:28, 23:38]).max() > 0.1
     if prec == "fp64":
         err = max(max_rel(Eg, Eo), max_rel(Hg, Ho))
         say("fp64 max rel", err)
