@@ -904,10 +904,15 @@ __host__ __device__ constexpr int x2_line_n() { return (TX > TY ? TX : TY) + 2; 
 
 // OWN: cell_update2d's MODE for the tile's own cells (1: the tile has layer
 // cells, 2: it has none, 0: decide per cell); ring cells decide per cell.
-template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false, int OWN = 0>
+// DFT = false: the launch lies outside the DFT window, and the contour
+// accumulation is compiled out (it costs registers the plain steps do not
+// need).
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false, int OWN = 0,
+          bool DFT = true>
 __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t,
                                       T *lslab = nullptr) {
-    const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
+    StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
+    if (!DFT) s0.dft = s1.dft = false;
     constexpr int VX = X2Lds<T, TX, TY>::VX;
     constexpr int TPR = TX / VX;             // segments per tile row
     constexpr int NT = x2_threads<T, TX, TY>();
@@ -1122,8 +1127,9 @@ __device__ inline int xcd_tile(int b, int ntiles) {
 // One block per tile, a 1-D grid of tiles_x * tiles_y blocks.  The launch
 // bound asks for 4 waves per SIMD (at most 128 VGPRs).
 // HIST: also record dE/deps of the design cells (recompute of the adjoint).
-// MU: permeability map a.mu.  LINE: exact incident line.
-template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false>
+// MU: permeability map a.mu.  LINE: exact incident line.  DFT: the launch
+// may meet the DFT window.
+template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = false, bool LINE = false, bool DFT = true>
 __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
     k_step2d_x2(StepArgs<T> a) {
     static_assert(!(HIST && (MU || LINE)), "the design-region history assumes mu_r = 1 and no line");
@@ -1136,8 +1142,8 @@ __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<
     // own cell, the others the plain collision (block-uniform choice)
     const bool in_layer = (a.W[0] && (x0 < a.W[0] || x0 + TX > a.nx - a.W[0])) ||
                           (a.W[1] && (y0 < a.W[1] || y0 + TY > a.ny - a.W[1]));
-    if (in_layer) step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE, 1>(a, lds, x0, y0, t, lslab);
-    else step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE, 2>(a, lds, x0, y0, t, lslab);
+    if (in_layer) step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE, 1, DFT>(a, lds, x0, y0, t, lslab);
+    else step2d_x2_tile<T, POL, TX, TY, HIST, MU, LINE, 2, DFT>(a, lds, x0, y0, t, lslab);
 }
 
 // One step on the two-step kernel's tiles (batched; a trailing odd step).
@@ -1161,8 +1167,9 @@ __global__ void __launch_bounds__((x2_threads<T, TX, TY>())) k_step2d_tile_batch
 
 // Batched form of the two-step kernel: a chip-sized grid strides over the
 // (instance, tile) work list (tiles of TX x TY cells); a barrier separates
-// consecutive tiles of a block because they share the LDS tile.
-template <typename T, int POL, int TX, int TY>
+// consecutive tiles of a block because they share the LDS tile.  DFT: the
+// launch may meet the DFT window of an instance.
+template <typename T, int POL, int TX, int TY, bool DFT = true>
 __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<T, TX, TY>()))
     k_step2d_x2_batch(const StepArgs<T> *__restrict__ descs,
                                                          const int *__restrict__ tile_inst,
@@ -1179,8 +1186,8 @@ __global__ void __launch_bounds__((x2_threads<T, TX, TY>()), (1024 / x2_threads<
         const int x0 = (local % a.tiles_x) * TX, y0 = (local / a.tiles_x) * TY;
         const bool in_layer = (a.W[0] && (x0 < a.W[0] || x0 + TX > a.nx - a.W[0])) ||
                               (a.W[1] && (y0 < a.W[1] || y0 + TY > a.ny - a.W[1]));
-        if (in_layer) step2d_x2_tile<T, POL, TX, TY, false, false, false, 1>(a, lds, x0, y0, t);
-        else step2d_x2_tile<T, POL, TX, TY, false, false, false, 2>(a, lds, x0, y0, t);
+        if (in_layer) step2d_x2_tile<T, POL, TX, TY, false, false, false, 1, DFT>(a, lds, x0, y0, t);
+        else step2d_x2_tile<T, POL, TX, TY, false, false, false, 2, DFT>(a, lds, x0, y0, t);
         __syncthreads();
     }
 }

@@ -29,12 +29,13 @@ template <typename T>
 void launch_step1(const StepArgs<T> &a, int pol, int vx, int bx, int by, hipStream_t s);
 
 // Two steps, 2-D (k_step2d_x2): a.tiles_x / a.tiles_y must be set.  One
-// translation unit per precision and polarisation.
+// translation unit per precision and polarisation.  dft: the launch may
+// meet the DFT window (selects the instantiation that accumulates it).
 template <typename T, int POL>
-bool launch_step2d_x2_pol(const StepArgs<T> &a, int tx, int ty, hipStream_t s);
+bool launch_step2d_x2_pol(const StepArgs<T> &a, int tx, int ty, bool dft, hipStream_t s);
 template <typename T>
-inline bool launch_step2d_x2(const StepArgs<T> &a, int pol, int tx, int ty, hipStream_t s) {
-    return pol == TM ? launch_step2d_x2_pol<T, TM>(a, tx, ty, s) : launch_step2d_x2_pol<T, TE>(a, tx, ty, s);
+inline bool launch_step2d_x2(const StepArgs<T> &a, int pol, int tx, int ty, bool dft, hipStream_t s) {
+    return pol == TM ? launch_step2d_x2_pol<T, TM>(a, tx, ty, dft, s) : launch_step2d_x2_pol<T, TE>(a, tx, ty, dft, s);
 }
 
 // Two steps, 3-D z march (k_step3d_x2), z chunks of zc planes.  dft: the
@@ -48,8 +49,9 @@ template <typename T>
 void launch_batch1(const StepArgs<T> *descs, int pol, int vx, int bx, int by, int grid, const int *tile_inst,
                    const int *tile_first, int ntiles, const int64_t *t_base, int64_t t_off, hipStream_t s);
 template <typename T>
-bool launch_batch_x2(const StepArgs<T> *descs, int pol, int tx, int ty, bool two, int grid, const int *tile_inst,
-                     const int *tile_first, int ntiles, const int64_t *t_base, int64_t t_off, hipStream_t s);
+bool launch_batch_x2(const StepArgs<T> *descs, int pol, int tx, int ty, bool two, bool dft, int grid,
+                     const int *tile_inst, const int *tile_first, int ntiles, const int64_t *t_base, int64_t t_off,
+                     hipStream_t s);
 
 // Adjoint: one reverse step, or two on the two-step tile.
 template <typename T>

@@ -144,7 +144,7 @@ struct BatchGroup {
     void *descs[2] = {nullptr, nullptr};   // StepArgs per instance, for buffer parity 0 / 1
     int *tile_inst = nullptr, *tile_first = nullptr;
     int ntiles = 0, grid = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [meets a DFT window][parity]
 };
 
 struct lbm_em_batch_s {
@@ -347,6 +347,14 @@ int x3_chunk(int nz, int tiles, int slots) {
     return best_zc;
 }
 
+// Whether a two-step launch may meet the DFT window: steps t_off and
+// t_off + 1, or a captured chunk flagged so.  Only such launches take the
+// kernel instantiation that carries the contour accumulation.
+template <typename T>
+bool launch_meets_window(const lbm_em *h, const StepArgs<T> &a) {
+    return a.dft_on && (a.t_base ? h->graph_dft : (a.t_off + 2 > h->win0 && a.t_off < h->win0 + h->winlen));
+}
+
 template <typename T>
 void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
     const int tx = h->ftx, ty = h->fty;
@@ -354,17 +362,17 @@ void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
     a.tiles_y = (a.ny + ty - 1) / ty;
     const int tiles = a.tiles_x * a.tiles_y;
     const int zc = x3_chunk(a.nz, tiles, h->cus * std::max(1, 1024 / (tx * ty)));
-    // the contour accumulation is compiled in only for launches that may
-    // meet the window: steps t_off, t_off + 1, or a captured chunk flagged so
-    const bool dft = a.dft_on && (a.t_base ? h->graph_dft : (a.t_off + 2 > h->win0 && a.t_off < h->win0 + h->winlen));
-    if (!launch_step3d_x2<T>(a, tx, ty, zc, dft, s)) fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
+    if (!launch_step3d_x2<T>(a, tx, ty, zc, launch_meets_window(h, a), s))
+        fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
 }
 
 template <typename T>
-void launch_step2_2d(StepArgs<T> a, int pol, int tx, int ty, hipStream_t s) {
+void launch_step2_2d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
+    const int tx = h->ftx, ty = h->fty;
     a.tiles_x = (a.nx + tx - 1) / tx;
     a.tiles_y = (a.ny + ty - 1) / ty;
-    if (!launch_step2d_x2<T>(a, pol, tx, ty, s)) fail(LBM_EM_EINVAL, "unsupported two-step tile");
+    if (!launch_step2d_x2<T>(a, h->cfg.pol, tx, ty, launch_meets_window(h, a), s))
+        fail(LBM_EM_EINVAL, "unsupported two-step tile");
 }
 
 template <typename T>
@@ -383,7 +391,7 @@ void launch_step2_t(const lbm_em *h, const void *src, void *dst, const int64_t *
             a.dhi[k] = h->dhi[k];
         }
     }
-    if (h->cfg.pol == LBM_EM_TM || h->cfg.pol == LBM_EM_TE) launch_step2_2d<T>(a, h->cfg.pol, h->ftx, h->fty, s);
+    if (h->cfg.pol == LBM_EM_TM || h->cfg.pol == LBM_EM_TE) launch_step2_2d<T>(h, a, s);
     else launch_step2_3d<T>(h, a, s);
 }
 
@@ -472,10 +480,10 @@ void do_steps(lbm_em *h, int64_t n, hipStream_t on = nullptr) {
         hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, st, h->t_dev, h->t);
         hip_check(hipGetLastError(), "k_set_time");
         for (int64_t c = 0; c < chunks; ++c) {
-            // 3-D chunks outside the DFT window replay the graph whose
-            // kernels carry no contour accumulation
+            // chunks outside the DFT window replay the graph whose kernels
+            // carry no contour accumulation
             const int64_t tc = h->t + c * kGraphChunk;
-            const int win = h->dim != 3 || (h->dft_set && tc < h->win0 + h->winlen && tc + kGraphChunk > h->win0);
+            const int win = h->dft_set && tc < h->win0 + h->winlen && tc + kGraphChunk > h->win0;
             if (!h->graph[win][h->cur]) h->graph[win][h->cur] = build_graph(h, h->cur, win);
             hip_check(hipGraphLaunch(h->graph[win][h->cur], st), "hipGraphLaunch");
             // a chunk flips the buffers an even number of times (32 fused
@@ -547,14 +555,15 @@ void fill_group(lbm_em_batch_s *b, BatchGroup &g, bool dft) {
 }
 
 // One launch of the batch.  With fused tiles (b->fuse == 2) `steps` is 2
-// (two-step kernel) or 1 (a single step on the same tiles).
+// (two-step kernel) or 1 (a single step on the same tiles).  dft: the launch
+// may meet the DFT window of an instance of the group.
 template <typename T>
 void launch_batch_t(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
-                    hipStream_t s, int steps) {
+                    hipStream_t s, int steps, bool dft) {
     const StepArgs<T> *d = (const StepArgs<T> *)g.descs[par];
     if (b->fuse == 2) {
-        if (!launch_batch_x2<T>(d, b->pol, b->ftx, b->fty, steps != 1, g.grid, g.tile_inst, g.tile_first, g.ntiles,
-                                t_base, t_off, s))
+        if (!launch_batch_x2<T>(d, b->pol, b->ftx, b->fty, steps != 1, dft, g.grid, g.tile_inst, g.tile_first,
+                                g.ntiles, t_base, t_off, s))
             fail(LBM_EM_EINVAL, "unsupported two-step tile");
     } else {
         launch_batch1<T>(d, b->pol, b->vx, b->bx, b->by, g.grid, g.tile_inst, g.tile_first, g.ntiles, t_base, t_off,
@@ -563,15 +572,25 @@ void launch_batch_t(const lbm_em_batch_s *b, const BatchGroup &g, int par, const
 }
 
 void launch_batch(const lbm_em_batch_s *b, const BatchGroup &g, int par, const int64_t *t_base, int64_t t_off,
-                  hipStream_t s, int steps = 0) {
-    if (b->precision == LBM_EM_FP32) launch_batch_t<float>(b, g, par, t_base, t_off, s, steps);
-    else launch_batch_t<double>(b, g, par, t_base, t_off, s, steps);
+                  hipStream_t s, int steps = 0, bool dft = true) {
+    if (b->precision == LBM_EM_FP32) launch_batch_t<float>(b, g, par, t_base, t_off, s, steps, dft);
+    else launch_batch_t<double>(b, g, par, t_base, t_off, s, steps, dft);
+}
+
+// Whether steps [t0, t0 + len) meet the DFT window of an instance of group g.
+bool group_meets_window(const lbm_em_batch_s *b, const BatchGroup &g, int64_t t0, int64_t len) {
+    for (int i = 0; i < g.count; ++i) {
+        const lbm_em *h = b->hs[g.first + i];
+        if (h->dft_set && t0 < h->win0 + h->winlen && t0 + len > h->win0) return true;
+    }
+    return false;
 }
 
 void free_groups(lbm_em_batch_s *b) {
     for (auto &g : b->groups) {
-        for (auto &ge : g.graph)
-            if (ge) (void)hipGraphExecDestroy(ge);
+        for (auto &gw : g.graph)
+            for (auto &ge : gw)
+                if (ge) (void)hipGraphExecDestroy(ge);
         hfree(g.descs[0]);
         hfree(g.descs[1]);
         hfree(g.tile_inst);
@@ -710,7 +729,8 @@ lbm_em_batch_s *make_batch(const lbm_em_handle *hs, int32_t count) {
     return b;
 }
 
-hipGraphExec_t build_batch_graph(lbm_em_batch_s *b, const BatchGroup &grp, int p) {
+// win: the chunks it replays may meet a DFT window of the group.
+hipGraphExec_t build_batch_graph(lbm_em_batch_s *b, const BatchGroup &grp, int p, bool win) {
     hipStream_t cs = nullptr;
     hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
     hipGraph_t g = nullptr;
@@ -721,7 +741,7 @@ hipGraphExec_t build_batch_graph(lbm_em_batch_s *b, const BatchGroup &grp, int p
     }
     int par = p;
     for (int k = 0; k < kGraphChunk; k += b->fuse) {
-        launch_batch(b, grp, par, b->t_dev, k, cs);
+        launch_batch(b, grp, par, b->t_dev, k, cs, 0, win);
         par ^= 1;
     }
     hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, cs, b->t_dev, (int64_t)kGraphChunk);
@@ -772,16 +792,21 @@ void batch_steps(lbm_em_batch_s *b, int64_t n, bool use_graph) {
         }
         int64_t chunks = use_graph ? n / kGraphChunk : 0;
         if (chunks > 0) {
-            if (!g.graph[cur]) g.graph[cur] = build_batch_graph(b, g, cur);
             hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, b->stream, b->t_dev, t);
             hip_check(hipGetLastError(), "k_set_time");
-            for (int64_t c = 0; c < chunks; ++c) hip_check(hipGraphLaunch(g.graph[cur], b->stream), "hipGraphLaunch");
+            for (int64_t c = 0; c < chunks; ++c) {
+                // chunks outside every DFT window of the group replay the
+                // graph whose kernels carry no contour accumulation
+                const int win = group_meets_window(b, g, t + c * kGraphChunk, kGraphChunk);
+                if (!g.graph[win][cur]) g.graph[win][cur] = build_batch_graph(b, g, cur, win);
+                hip_check(hipGraphLaunch(g.graph[win][cur], b->stream), "hipGraphLaunch");
+            }
             t += chunks * kGraphChunk;
         }
         int64_t rest = n - chunks * kGraphChunk;
         while (rest > 0) {
             const int adv = (b->fuse == 2 && rest >= 2) ? 2 : 1;   // a trailing odd step runs alone
-            launch_batch(b, g, cur, nullptr, t, b->stream, adv);
+            launch_batch(b, g, cur, nullptr, t, b->stream, adv, group_meets_window(b, g, t, adv));
             hip_check(hipGetLastError(), "batch kernel launch");
             cur ^= 1;
             t += adv;
@@ -1657,7 +1682,7 @@ lbm_em_status lbm_em_batch_autotune(lbm_em_batch b, int32_t launches, double *be
                         for (const auto &g : b->groups)
                             if (!g.direct)
                                 for (int i = 0; i < reps; ++i)
-                                    launch_batch(b, g, h0->cur, nullptr, h0->t, b->stream, 2);
+                                    launch_batch(b, g, h0->cur, nullptr, h0->t, b->stream, 2, false);
                     };
                     run(1);
                     hip_check(hipEventRecord(e0, b->stream), "hipEventRecord");
