@@ -198,8 +198,7 @@ class Simulation:
             table = json.load(open(cache))
             if key in table:
                 self.set_tile(*table[key]["tile"])
-                if self.n[2] == 1:
-                    self.set_fusion(table[key]["fusion"], table[key]["fusion_tile"])
+                self.set_fusion(table[key]["fusion"], table[key]["fusion_tile"])
                 return table[key]
         us = C.c_double()
         L.check(L.lib().lbm_em_autotune(self._h, int(launches), C.byref(us)))

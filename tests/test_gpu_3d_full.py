@@ -1,7 +1,8 @@
 """The 3-D two-step z march at the sizes the benchmark runs.
 
-* 384^3 sphere (x = 6 at lambda = 24, eps 2.25, W = 24) in the library's
-  default launch configuration (two steps per launch, default tile, z
+* 384^3 and 512^3 spheres (x = 6 at lambda = 24, eps 2.25, W = 24) in the
+  launch configuration the benchmark times (the autotuner's pick: two
+  steps per launch, 128 x 8 tiles at 384^3 and a wider tile at 512^3, z
   chunks chosen for the device): bit-identical to one step per launch over
   three graph chunks (the first outside the DFT window, so it replays the
   kernels without the contour accumulation) and an odd trailing step,
@@ -42,19 +43,23 @@ def _sphere_sim(Sim, case, prec="fp32"):
     return s
 
 
-def test_sphere_384_two_steps_per_launch_bit_identical(Sim):
-    case = W.sphere_case(n=384, steps=195)
+@pytest.mark.parametrize("n", [384, 512])
+def test_sphere_two_steps_per_launch_bit_identical(Sim, n):
+    case = W.sphere_case(n=n, steps=195)
     runs = []
     for fuse in (2, 1):
         s = _sphere_sim(Sim, case)
         # a contour through the forced layers (the wave is there from the
         # start), window [100, 172): graph chunk [0, 64) lies before it
-        s.set_ntff((8, 8, 8), (375, 375, 375), 100, 72)
-        if fuse == 1:
+        s.set_ntff((8, 8, 8), (n - 9, n - 9, n - 9), 100, 72)
+        if fuse == 2:
+            rec = s.autotune()
+            assert rec["fusion"] == 2, rec
+        else:
             s.set_fusion(1)
-        say("384^3 fusion", s.get_fusion(), s.get_fusion_tile())
-        for n in (64, 128, 3):
-            s.step(n)
+        say(f"{n}^3 fusion", s.get_fusion(), s.get_fusion_tile())
+        for k in (64, 128, 3):
+            s.step(k)
         assert s.t == 195
         E, H = s.fields()
         X, p = s.phasors()
