@@ -252,8 +252,9 @@ lbm_em_status lbm_em_get_tile(lbm_em_handle h, int32_t *vx, int32_t *bx, int32_t
  * (FP32 tiles 64x16, 128x8, 128x16, 256x8, 256x16, 128x32; FP64 32x16,
  * 64x8, 64x16, 128x8, 128x16, 64x32), in 3-D a TX x TY column tile that
  * marches along z with a one-plane lag (FP32 64x16, 64x8, 32x16, 128x8,
- * 256x4; FP64 32x16, 32x8, 16x16, 64x8, 128x4).  tile 0 x 0 keeps the current one; EINVAL for other
- * tiles.  get_fusion's tile outputs may be NULL. */
+ * 256x4, 128x4; FP64 32x16, 32x8, 16x16, 64x8, 128x4; 512-thread tiles run
+ * two blocks per compute unit).  tile 0 x 0 keeps the current one; EINVAL
+ * for other tiles.  get_fusion's tile outputs may be NULL. */
 lbm_em_status lbm_em_set_fusion(lbm_em_handle h, int32_t steps_per_launch, int32_t tile_x, int32_t tile_y);
 lbm_em_status lbm_em_get_fusion(lbm_em_handle h, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y);
 

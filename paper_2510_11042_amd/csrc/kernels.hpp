@@ -1529,7 +1529,7 @@ struct X3Lds {
 // Planes on which the tile and its ring are vacuum (vacuum_plane) neither
 // read nor write the rest populations and read no eps_r.
 template <typename T, int TX, int TY, bool LINE = false, bool DFT = true>
-__global__ void __launch_bounds__(TX * TY) k_step3d_x2(StepArgs<T> a, int zc) {
+__global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArgs<T> a, int zc) {
     constexpr int NT = TX * TY;
     constexpr int NR = 2 * TX + 2 * TY;
     static_assert(NR <= NT, "ring larger than the block");

@@ -16,9 +16,10 @@
 
 // 3-D two-step tiles (one cell per thread; the LDS holds two planes of the
 // tile's x/y movers: 136 KB for 64 x 16 FP32 and 32 x 16 FP64, 148 KB for
-// 256 x 4 FP32 and 128 x 4 FP64).  Wide tiles spend fewer 128-byte lines on
-// the ring columns.
-#define LBM_X3_TILES_F32(M) M(64, 16) M(64, 8) M(32, 16) M(128, 8) M(256, 4)
+// 256 x 4 FP32 and 128 x 4 FP64; the 512-thread FP32 tiles take about 70 KB
+// and run two blocks per compute unit).  Wide tiles spend fewer 128-byte
+// lines on the ring columns.
+#define LBM_X3_TILES_F32(M) M(64, 16) M(64, 8) M(32, 16) M(128, 8) M(256, 4) M(128, 4)
 #define LBM_X3_TILES_F64(M) M(32, 16) M(32, 8) M(16, 16) M(64, 8) M(128, 4)
 
 namespace lbm {

@@ -1749,7 +1749,7 @@ lbm_em_status lbm_em_set_fusion(lbm_em_handle hh, int32_t steps_per_launch, int3
         if (steps_per_launch == 2 && (tile_x || tile_y)) {
             if (!fused_tile_ok(h->dim, h->cfg.precision, tile_x, tile_y))
                 fail(LBM_EM_EINVAL,
-                     h->dim == 3 ? (h->cfg.precision == LBM_EM_FP32 ? "3-D FP32 two-step tile must be 64x16, 64x8, 32x16, 128x8 or 256x4"
+                     h->dim == 3 ? (h->cfg.precision == LBM_EM_FP32 ? "3-D FP32 two-step tile must be 64x16, 64x8, 32x16, 128x8, 256x4 or 128x4"
                                                                     : "3-D FP64 two-step tile must be 32x16, 32x8, 16x16, 64x8 or 128x4")
                      : h->cfg.precision == LBM_EM_FP32
                          ? "FP32 two-step tile must be 64x16, 128x8, 128x16, 256x8, 256x16 or 128x32"

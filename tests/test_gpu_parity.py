@@ -142,7 +142,7 @@ def test_source_phase_tables(gpu, prec):
         compare_fields(s, o, prec, f"tables 3-D t={o.t}")
 
 
-X3_TILES = {"fp32": [(64, 16), (64, 8), (32, 16), (128, 8), (256, 4)],
+X3_TILES = {"fp32": [(64, 16), (64, 8), (32, 16), (128, 8), (256, 4), (128, 4)],
             "fp64": [(32, 16), (32, 8), (16, 16), (64, 8), (128, 4)]}
 
 
