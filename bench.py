@@ -449,10 +449,13 @@ def batched_extra(P, W, torch, steps=6000, stress=False):
            "algorithmic_GBs": cells * steps / fuse * BYTES_2D / t_batch / 1e9}
     res["batched_over_single"] = res["MLUPS"] / res["single_instance_MLUPS"]
     res["autotune_us_per_step"] = tuned_us
-    # counter bytes of the batched kernel over all its launches / the
-    # algorithmic bytes of the same launches (profiles/, same kernel source)
-    res["traffic_over_algorithmic"] = None if stress else recorded_traffic(
-        "k_step2d_x2_batch_fp32_seeded64", field="traffic_over_algorithmic")
+    bfuse, btile = b.tile()
+    res["tile"] = list(btile)
+    # counter bytes of the batched kernel over a round of launches (every
+    # group once) / the algorithmic bytes of that round, at the tile the
+    # batch uses (profiles/, same kernel source)
+    res["traffic_over_algorithmic"] = None if stress or bfuse != 2 else recorded_traffic(
+        "k_step2d_x2_batch_fp32_seeded64", btile, field="traffic_over_algorithmic")
     b.close()
     for s in sims:
         s.close()
@@ -512,6 +515,20 @@ def copy_ceiling(P):
 
     g = C.c_double()
     _lib.check(_lib.lib().lbm_em_copy_bandwidth(2 ** 31, 10, C.byref(g)))
+    return g.value
+
+
+def stream_ceiling(P, n=384):
+    """The library's multi-plane streaming kernel on an n^3 grid: 24 planes
+    read and 24 written per cell (the 3-D two-step kernel's traffic for a
+    vacuum cell) without the arithmetic; a measured ceiling for its access
+    pattern (read + written bytes)."""
+    import ctypes as C
+
+    from paper_2510_11042_amd import _lib
+
+    g = C.c_double()
+    _lib.check(_lib.lib().lbm_em_stream_bandwidth(n ** 3, 24, 24, 10, C.byref(g)))
     return g.value
 
 
@@ -701,6 +718,7 @@ def main():
         say = lambda m: print(f"bench: extra {m}", file=sys.stderr, flush=True)
         if "copy" in want:
             line["roofline"]["measured_copy_GBs"] = copy_ceiling(P)
+            line["roofline"]["measured_stream_24x24_GBs"] = stream_ceiling(P)
         th2 = np.arange(0.0, 360.0, 0.5)
         tiles = None
         cs = args.cylinder_steps

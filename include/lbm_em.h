@@ -236,6 +236,9 @@ lbm_em_status lbm_em_batch_autotune(lbm_em_batch b, int32_t launches, double *be
 /* Number of groups of the current plan (an instance advanced by its own
  * kernels counts as one group). */
 lbm_em_status lbm_em_batch_groups(lbm_em_batch b, int32_t *groups);
+/* The batch's launch shape: steps per launch (1 or 2) and the two-step tile
+ * TX x TY of the persistent kernel (from batch_create or the autotuner). */
+lbm_em_status lbm_em_batch_get_tile(lbm_em_batch b, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y);
 lbm_em_status lbm_em_batch_destroy(lbm_em_batch b);
 
 /* Launch shape of the step kernel: every thread updates vx consecutive
@@ -355,6 +358,16 @@ lbm_em_status lbm_em_backward(lbm_em_handle h, double *grad_eps, int32_t where);
  * stream, counting bytes read + written.  Allocates and frees two buffers
  * of `bytes`.  The measured ceiling the step kernels are compared with. */
 lbm_em_status lbm_em_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
+
+/* Measurement helper: bandwidth of the step kernels' access pattern without
+ * their arithmetic -- every thread reads one cell of `planes_in` FP32 planes
+ * and writes it to `planes_out` planes with streamed stores (1 <= planes_out
+ * <= planes_in <= 32, 1 <= cells <= 2^31) -- averaged over `reps` launches
+ * on the null stream, counting bytes read + written.  Allocates and frees
+ * the planes (4 (planes_in + planes_out) cells bytes).  24 planes in and out
+ * is the 3-D two-step kernel's traffic for vacuum cells. */
+lbm_em_status lbm_em_stream_bandwidth(int64_t cells, int32_t planes_in, int32_t planes_out, int32_t reps,
+                                      double *gbs);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *lbm_em_last_error(void);

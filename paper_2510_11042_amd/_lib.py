@@ -21,12 +21,13 @@ EXPORTS = [
     "lbm_em_set_incident_line", "lbm_em_get_line_phasors",
     "lbm_em_set_source",
     "lbm_em_set_ntff", "lbm_em_step", "lbm_em_step_many", "lbm_em_batch_create", "lbm_em_batch_step",
-    "lbm_em_batch_set_grid", "lbm_em_batch_set_cache_budget", "lbm_em_batch_groups", "lbm_em_batch_autotune",
+    "lbm_em_batch_set_grid", "lbm_em_batch_set_cache_budget", "lbm_em_batch_groups", "lbm_em_batch_get_tile",
+    "lbm_em_batch_autotune",
     "lbm_em_batch_destroy", "lbm_em_set_tile", "lbm_em_get_tile", "lbm_em_set_fusion", "lbm_em_get_fusion",
     "lbm_em_autotune",
     "lbm_em_reset", "lbm_em_time", "lbm_em_get_fields",
     "lbm_em_get_phasors", "lbm_em_farfield", "lbm_em_farfield_static", "lbm_em_adjoint_setup", "lbm_em_forward_checkpointed",
-    "lbm_em_backward", "lbm_em_copy_bandwidth", "lbm_em_last_error",
+    "lbm_em_backward", "lbm_em_copy_bandwidth", "lbm_em_stream_bandwidth", "lbm_em_last_error",
 ]
 
 
@@ -77,6 +78,7 @@ def lib():
             "lbm_em_batch_set_grid": [H, C.c_int32],
             "lbm_em_batch_set_cache_budget": [H, C.c_int64],
             "lbm_em_batch_groups": [H, C.POINTER(C.c_int32)],
+            "lbm_em_batch_get_tile": [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "lbm_em_batch_autotune": [H, C.c_int32, C.POINTER(C.c_double)],
             "lbm_em_batch_destroy": [H],
             "lbm_em_set_tile": [H, C.c_int32, C.c_int32, C.c_int32],
@@ -98,6 +100,7 @@ def lib():
         sig["lbm_em_forward_checkpointed"] = [H, C.c_int64, C.POINTER(C.c_double)]
         sig["lbm_em_backward"] = [H, C.c_void_p, C.c_int32]
         sig["lbm_em_copy_bandwidth"] = [C.c_int64, C.c_int32, C.POINTER(C.c_double)]
+        sig["lbm_em_stream_bandwidth"] = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args

@@ -1205,6 +1205,29 @@ __global__ void k_ff_finish(const double *P, const double *probe, double u0, dou
 
 }  // namespace
 
+namespace {
+
+// Multi-plane streaming (measured ceiling of the step kernels' access
+// pattern): every thread reads cell c of nin planes and writes cell c of
+// nout planes (streamed stores, as the 3-D two-step kernel), plane stride P.
+__global__ void __launch_bounds__(256) k_stream_planes(const float *__restrict__ in, float *__restrict__ out,
+                                                               int64_t P, int64_t n, int nin, int nout) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    float v[32];
+    // every load is issued before any of them is used
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = i < nin ? in[i * P + c] : 0.f;
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc += v[i];
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        if (i < nout) __builtin_nontemporal_store(fmaf(v[i], 0.5f, acc), out + i * P + c);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *lbm_em_last_error(void) { return g_last_error.c_str(); }
@@ -1720,6 +1743,15 @@ lbm_em_status lbm_em_batch_groups(lbm_em_batch b, int32_t *groups) {
     return guarded([&] {
         if (!b || !groups) fail(LBM_EM_EINVAL, "null argument");
         *groups = (int32_t)b->groups.size();
+    });
+}
+
+lbm_em_status lbm_em_batch_get_tile(lbm_em_batch b, int32_t *steps_per_launch, int32_t *tile_x, int32_t *tile_y) {
+    return guarded([&] {
+        if (!b || !steps_per_launch || !tile_x || !tile_y) fail(LBM_EM_EINVAL, "null argument");
+        *steps_per_launch = b->fuse;
+        *tile_x = b->ftx;
+        *tile_y = b->fty;
     });
 }
 
@@ -2297,6 +2329,50 @@ lbm_em_status lbm_em_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs) {
             float ms = 0.f;
             hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
             *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+        } catch (...) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            hfree(a);
+            hfree(b);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        hfree(a);
+        hfree(b);
+    });
+}
+
+lbm_em_status lbm_em_stream_bandwidth(int64_t cells, int32_t planes_in, int32_t planes_out, int32_t reps,
+                                      double *gbs) {
+    return guarded([&] {
+        if (cells < 1 || cells > ((int64_t)1 << 31) || planes_in < 1 || planes_in > 32 || planes_out < 1 ||
+            planes_out > planes_in || reps < 1 || !gbs)
+            fail(LBM_EM_EINVAL, "need 1 <= cells <= 2^31, 1 <= planes_out <= planes_in <= 32, reps >= 1");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(LBM_EM_EDEVICE, "no HIP device");
+        const int64_t P = round_up(cells, 64);
+        void *a = nullptr, *b = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        try {
+            hip_check(hipMalloc(&a, (size_t)P * planes_in * sizeof(float)), "hipMalloc");
+            hip_check(hipMalloc(&b, (size_t)P * planes_out * sizeof(float)), "hipMalloc");
+            hip_check(hipMemset(a, 0, (size_t)P * planes_in * sizeof(float)), "hipMemset");
+            const unsigned blocks = (unsigned)((cells + 255) / 256);
+            auto launch = [&] {
+                hipLaunchKernelGGL(k_stream_planes, dim3(blocks), dim3(256), 0, nullptr, (const float *)a, (float *)b,
+                                   P, cells, planes_in, planes_out);
+            };
+            launch();
+            hip_check(hipEventCreate(&e0), "hipEventCreate");
+            hip_check(hipEventCreate(&e1), "hipEventCreate");
+            hip_check(hipEventRecord(e0, nullptr), "hipEventRecord");
+            for (int r = 0; r < reps; ++r) launch();
+            hip_check(hipEventRecord(e1, nullptr), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            *gbs = (double)(planes_in + planes_out) * 4.0 * (double)cells * reps / (ms * 1e-3) / 1e9;
         } catch (...) {
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);

@@ -356,6 +356,12 @@ class Batch:
         L.check(L.lib().lbm_em_batch_groups(self._b, C.byref(g)))
         return g.value
 
+    def tile(self):
+        """(steps per launch, (TX, TY)) of the persistent kernel."""
+        v, tx, ty = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.lib().lbm_em_batch_get_tile(self._b, C.byref(v), C.byref(tx), C.byref(ty)))
+        return v.value, (tx.value, ty.value)
+
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:
             L.check(L.lib().lbm_em_batch_destroy(self._b))
