@@ -729,7 +729,8 @@ def main():
             say("streams")
             line["extra"]["two_streams"] = two_stream_extra(Simulation, W, torch, cs, th2, tiles)
             line["extra"]["batched_job"] = batched_job_extra(P, W, torch, cs, th2, tiles)
-        if "sphere_line" in want and 384 in sizes and args.lbm_steps >= 144:
+        # the far field needs the incident wave at the sphere (profiling runs may be shorter)
+        if "sphere_line" in want and 384 in sizes and args.lbm_steps >= 1000:
             say("sphere_line")
             r, S_line = sphere_line_extra(Simulation, W, torch, args.lbm_steps, theta)
             d = {}
