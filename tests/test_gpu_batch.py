@@ -178,6 +178,9 @@ def test_batch_autotune_keeps_state_and_results(lib):
     before = [g.fields() for g in grouped]
     us = b.autotune(launches=3)
     assert us > 0
+    # the batch reports the launch shape its tuner kept
+    fuse, tile = b.tile()
+    assert fuse == 2 and tile in [(64, 16), (128, 8), (128, 16), (256, 8), (256, 16), (128, 32)], (fuse, tile)
     for g, (E, H) in zip(grouped, before):
         assert g.t == 110
         E2, H2 = g.fields()

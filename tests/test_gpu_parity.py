@@ -886,6 +886,31 @@ def test_incident_line_long_line_matches_oracle(gpu, prec, nx):
     s.close()
 
 
+def test_measured_ceilings(gpu):
+    """The measurement helpers: a plain copy and the multi-plane streaming
+    pattern report positive bandwidths (below a generous bound on the HBM
+    peak, above a floor any working device reaches) and refuse bad sizes
+    with EINVAL."""
+    import ctypes as C
+
+    from paper_2510_11042_amd import _lib
+
+    L = _lib.lib()
+    g = C.c_double()
+    assert L.lbm_em_copy_bandwidth(1 << 28, 3, C.byref(g)) == _lib.OK
+    say("copy GB/s", g.value)
+    assert 500.0 < g.value < 20000.0
+    for nin, nout in ((24, 24), (28, 27), (1, 1), (32, 32)):
+        g.value = 0.0
+        assert L.lbm_em_stream_bandwidth(1 << 22, nin, nout, 3, C.byref(g)) == _lib.OK
+        say("stream GB/s", nin, nout, g.value)
+        assert 100.0 < g.value < 20000.0
+    for cells, nin, nout, reps in ((0, 4, 4, 1), (1 << 20, 0, 0, 1), (1 << 20, 4, 5, 1), (1 << 20, 33, 4, 1),
+                                   (1 << 20, 4, 4, 0), ((1 << 31) + 1, 4, 4, 1)):
+        assert L.lbm_em_stream_bandwidth(cells, nin, nout, reps, C.byref(g)) == _lib.EINVAL
+    assert L.lbm_em_stream_bandwidth(1 << 20, 4, 4, 1, None) == _lib.EINVAL
+
+
 def test_edge_cases_and_errors(gpu):
     """Degenerate and invalid inputs: zero steps, negative steps, a 1 x 1
     periodic grid, empty or misplaced DFT windows and contours, the far field
