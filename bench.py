@@ -544,14 +544,18 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def cpu_baseline(Simulation, W, target_s=20.0, n=384):
+def cpu_baseline(Simulation, W, target_s=20.0, n=384, S=None, n_dielectric=None):
     """FP64 oracle (literal 42-scalar scheme, OpenMP on all host threads) on
     a bounded sample of the benchmark workload: the 384^3 sphere, its first
     steps; the GPU (FP32, the benchmark's launch configuration) runs the
-    same steps and its fields are compared with the oracle's."""
+    same steps and its fields are compared with the oracle's.  With the
+    timed step's |S|^2 (S, keyed by (grid, phi)) the accuracy gate also
+    scores them against the Lorenz-Mie series of the oracle package, at the
+    volume-equivalent radius of the staircase sphere."""
     import numpy as np
 
     from oracle import core as oracle_core
+    from oracle import mie
 
     case = W.sphere_case(n=n, steps=4000)
     c = (n - 1) / 2.0
@@ -580,14 +584,28 @@ def cpu_baseline(Simulation, W, target_s=20.0, n=384):
     num = float(np.sum((Eg - Eo) ** 2) + np.sum((Hg - Ho) ** 2))
     den = float(np.sum(Eo ** 2) + np.sum(Ho ** 2))
     model, ncpu = host_cpu()
+    field_err = float(np.sqrt(num / den)) if den > 0 else None
+    gate = {"fields_vs_oracle_rel_l2": field_err, "fields_bound": 1e-4}
+    if S:
+        theta = np.arange(0.0, 180.01, 0.5)
+        k = 2 * np.pi / case.lam
+        nr = {}
+        for (size, phi), s2 in S.items():
+            a_eq = (n_dielectric[size] * 3 / (4 * np.pi)) ** (1 / 3)
+            ref = mie.sphere_S2(theta, phi, k * a_eq, np.sqrt(case.eps_in))
+            nr[f"{size}_phi{phi:g}"] = float(np.sqrt(np.mean((s2 - ref) ** 2)) / ref.max())
+        gate["S2_vs_mie_nrms"] = nr
+        gate["S2_bound"] = 2e-2
+    gate["passed"] = bool(field_err is not None and field_err <= 1e-4 and
+                          all(v <= 2e-2 for v in gate.get("S2_vs_mie_nrms", {}).values()))
     return {"value": n ** 3 * nsteps / dt / 1e6, "unit": "MLUPS", "cores": oracle_core.threads(),
             "kind": "oracle",
             "sample": f"eps 2.25 sphere {n}^3 (x = 6, lambda = 24, W = 24), steps 3..{total} of 4000 timed "
                       f"({dt:.1f} s; {41.7 * (n / 384) ** 3:.1f} GB of FP64 literal 42-scalar state, allocated "
                       f"in {t_alloc:.1f} s)",
             "host_cpu": model, "nproc": ncpu,
-            "gpu_vs_oracle_rel_l2_fields": float(np.sqrt(num / den)) if den > 0 else None,
-            "sample_steps": total}
+            "gpu_vs_oracle_rel_l2_fields": field_err,
+            "sample_steps": total, "accuracy_gate": gate}
 
 
 def main():
@@ -757,7 +775,8 @@ def main():
             line["extra"]["adjoint"] = adjoint_extra(P, W, torch)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(Simulation, W)
+        line["cpu_baseline"] = cpu_baseline(Simulation, W, S=res,
+                                            n_dielectric={case.n: case.n_dielectric for case, _ in jobs})
     print(json.dumps(line), flush=True)
     return 0
 
