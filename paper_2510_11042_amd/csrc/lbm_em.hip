@@ -433,7 +433,8 @@ void drop_graphs(lbm_em *h) {
 
 // Capture kGraphChunk steps (starting from buffer parity p) plus the device
 // step-counter advance into one executable graph.  win: the chunks it will
-// replay may meet the DFT window (3-D: selects the kernel instantiation).
+// replay may meet the DFT window (selects the two-step kernels'
+// instantiation with the contour accumulation).
 hipGraphExec_t build_graph(lbm_em *h, int p, bool win) {
     hipStream_t cs = nullptr;
     hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
