@@ -102,6 +102,9 @@ template <> struct Cplx<double> { typedef double2 type; };
 
 // Steps of the incident line kept in its table: one captured graph chunk.
 constexpr int kLineSlots = 64;
+// Most planes one block of the 3-D two-step kernel marches (its z chunk
+// plus the two extra planes); the host caps the chunk length accordingly.
+constexpr int kX3MaxPlanes = 1024;
 
 // x/3 and x/6 as if the constants were exact.  The collision is
 // f* = 2 f^eq - f with 2 f^eq = combination / 3, and the rounded 1/3 of
@@ -216,12 +219,12 @@ struct StepConst {
     double cr, ci;      // (2 / winlen) (cos, -sin)(2 pi tau)
 };
 
+// The step's constants from its period phasor ph = wave_t[t mod T] and its
+// ramp value r = g(t) (1 past the ramp).
 template <typename T>
-__device__ inline StepConst<T> step_const(const StepArgs<T> &a, int64_t t) {
+__device__ inline StepConst<T> form_step_const(const StepArgs<T> &a, int64_t t, double2 ph, double r) {
     StepConst<T> c{t, T(0), T(0), false, 0.0, 0.0};
-    if (!a.src_on) return c;             // the DFT needs the source's period too
-    const double2 ph = a.wave_t[t % a.period];
-    const double g = ((double)t < a.t_ramp ? a.ramp[t] : 1.0) * a.amp;
+    const double g = r * a.amp;
     c.gs = (T)(g * ph.y);
     c.gc = (T)(g * ph.x);
     if (a.dft_on && t >= a.win0 && t < a.win0 + a.winlen) {
@@ -233,19 +236,60 @@ __device__ inline StepConst<T> step_const(const StepArgs<T> &a, int64_t t) {
     return c;
 }
 
+template <typename T>
+__device__ inline StepConst<T> step_const(const StepArgs<T> &a, int64_t t) {
+    if (!a.src_on) return StepConst<T>{t, T(0), T(0), false, 0.0, 0.0};   // the DFT needs the source's period too
+    return form_step_const(a, t, a.wave_t[t % a.period], (double)t < a.t_ramp ? a.ramp[t] : 1.0);
+}
+
+// The constants of steps t and t + 1 (the same values as step_const), their
+// table reads issued together.
+template <typename T>
+__device__ inline void step_consts2(const StepArgs<T> &a, int64_t t, StepConst<T> &c0, StepConst<T> &c1) {
+    if (!a.src_on) {
+        c0 = StepConst<T>{t, T(0), T(0), false, 0.0, 0.0};
+        c1 = StepConst<T>{t + 1, T(0), T(0), false, 0.0, 0.0};
+        return;
+    }
+    const int64_t k0 = t % a.period, k1 = k0 + 1 == a.period ? 0 : k0 + 1;
+    const double2 ph0 = a.wave_t[k0], ph1 = a.wave_t[k1];
+    double r0 = 1.0, r1 = 1.0;
+    if ((double)(t + 1) < a.t_ramp) {
+        r0 = a.ramp[t];
+        r1 = a.ramp[t + 1];
+    } else if ((double)t < a.t_ramp) {
+        r0 = a.ramp[t];
+    }
+    c0 = form_step_const(a, t, ph0, r0);
+    c1 = form_step_const(a, t + 1, ph1, r1);
+}
+
+// The x-y part e^{2 pi j (u_x(x) + u_y(y))} of a cell's phase factor.
+template <typename T>
+__device__ inline typename Cplx<T>::type xy_phase(const StepArgs<T> &a, int x, int y) {
+    const auto px = a.wave_x[x], py = a.wave_y[y];
+    typename Cplx<T>::type w;
+    w.x = px.x * py.x - px.y * py.y;
+    w.y = px.x * py.y + px.y * py.x;
+    return w;
+}
+
+// The incident value at a 3-D cell from its x-y factor and the z factor of
+// its plane.
+template <typename T>
+__device__ inline T plane_wave_xyz(const StepConst<T> &sc, typename Cplx<T>::type wxy, typename Cplx<T>::type pz) {
+    const T ur = wxy.x * pz.x - wxy.y * pz.y;
+    const T ui = wxy.x * pz.y + wxy.y * pz.x;
+    return sc.gs * ur - sc.gc * ui;
+}
+
 // The incident value at a cell, in the arithmetic type of the run (the
 // per-axis tables are stored in it).
 template <typename T, int DIM>
 __device__ inline T plane_wave(const StepArgs<T> &a, const StepConst<T> &sc, int x, int y, int z) {
-    const auto px = a.wave_x[x], py = a.wave_y[y];
-    T ur = px.x * py.x - px.y * py.y, ui = px.x * py.y + px.y * py.x;
-    if (DIM == 3) {
-        const auto pz = a.wave_z[z];
-        const T r = ur * pz.x - ui * pz.y;
-        ui = ur * pz.y + ui * pz.x;
-        ur = r;
-    }
-    return sc.gs * ur - sc.gc * ui;
+    const auto w = xy_phase(a, x, y);
+    if (DIM == 3) return plane_wave_xyz(sc, w, a.wave_z[z]);
+    return sc.gs * w.x - sc.gc * w.y;
 }
 
 // 1 / eps: for FP32 the hardware reciprocal refined by one Newton step
@@ -911,8 +955,7 @@ template <typename T, int POL, int TX, int TY, bool HIST = false, bool MU = fals
           bool DFT = true>
 __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L, int x0, int y0, int64_t t,
                                       T *lslab = nullptr) {
-    StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
-    if (!DFT) s0.dft = s1.dft = false;
+    StepConst<T> s0, s1;   // formed once the own state's loads are issued
     constexpr int VX = X2Lds<T, TX, TY>::VX;
     constexpr int TPR = TX / VX;             // segments per tile row
     constexpr int NT = x2_threads<T, TX, TY>();
@@ -937,6 +980,8 @@ __device__ inline void step2d_x2_tile(const StepArgs<T> &a, X2Lds<T, TX, TY> &L,
         const int yf = fold(y, a.ny, a.W[1]);
         T v[11][VX], e[VX];
         pull_row<T, VX>(a, x, yf, v, e);
+        step_consts2(a, t, s0, s1);
+        if (!DFT) s0.dft = s1.dft = false;
 #pragma unroll
         for (int k = 0; k < VX; ++k) mp[k] = imp[k] = T(1);
         // tiles whose cells or ring cells reach into the layer stage the
@@ -1251,10 +1296,13 @@ __device__ inline T sigma3d(const StepArgs<T> &a, int x, int y, int z) {
 // 3-D per-cell update (moments, DFT sample, collision, layer/source);
 // inv_eps = 1/eps and sig = sigma3d(x, y, z) from the caller; record: the
 // cell is in the domain and owned by this thread (DFT samples).
-template <typename T, bool LINE = false, bool LREC = false, bool DFT = true>
+// PH: the caller passes the cell's x-y phase factor wxy = xy_phase(x, y) and
+// its plane's z factor wz = wave_z[z] (the same value as from the tables).
+template <typename T, bool LINE = false, bool LREC = false, bool DFT = true, bool PH = false>
 __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &st, int x, int y, int z, T eps,
                                      T inv_eps, T sig, T f[27], bool record, const T *fl = nullptr,
-                                     int fl_stride = 0) {
+                                     int fl_stride = 0, typename Cplx<T>::type wxy = {},
+                                     typename Cplx<T>::type wz = {}) {
     T E[3], H[3];
     fields3d(f, inv_eps, E, H);
     if (LREC) {
@@ -1282,7 +1330,7 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
         // held in registers
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
         if (a.src_on && eps == T(1)) {
-            const T w = plane_wave<T, 3>(a, st, x, y, z);
+            const T w = PH ? plane_wave_xyz(st, wxy, wz) : plane_wave<T, 3>(a, st, x, y, z);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 Er[k] = w * a.ehat[k];
@@ -1340,7 +1388,7 @@ __device__ inline void cell_update3d(const StepArgs<T> &a, const StepConst<T> &s
         T Er[3] = {0, 0, 0}, Hr[3] = {0, 0, 0};
         const bool background = a.src_on && eps == T(1);
         if (background) {
-            const T w = plane_wave<T, 3>(a, st, x, y, z);
+            const T w = PH ? plane_wave_xyz(st, wxy, wz) : plane_wave<T, 3>(a, st, x, y, z);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 Er[k] = w * a.ehat[k];
@@ -1549,7 +1597,8 @@ __global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArg
     const bool own = x < a.nx && y < a.ny;
     const int xf = fold(x, a.nx, a.W[0]), yf = fold(y, a.ny, a.W[1]);
     const int64_t t = step_time(a.t_base, a.t_off);
-    const StepConst<T> s0 = step_const(a, t), s1 = step_const(a, t + 1);
+    StepConst<T> s0, s1;
+    step_consts2(a, t, s0, s1);
     // this thread's ring cell (same x-y position on every plane)
     const bool ring = tid < NR;
     int rx = 0, ry = 0;
@@ -1568,7 +1617,26 @@ __global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArg
     int vxl, vxh, vyl, vyh;
     span(x0 - 1, x0 + TX, a.nx, a.W[0], vxl, vxh);
     span(y0 - 1, y0 + TY, a.ny, a.W[1], vyl, vyh);
+    // which of the chunk's planes zb - 1 .. ze are vacuum for the tile and
+    // its ring, one bit per plane, formed once so that the march does not
+    // wait on the box table at every plane
+    __shared__ unsigned long long vbits[kX3MaxPlanes / 64];
+    const int np = ze - zb + 2;
+    for (int i0 = 0; i0 < np; i0 += NT) {
+        const int i = i0 + tid;
+        const bool v = i < np && vacuum_plane(a, fold(zb - 1 + i, a.nz, a.W[2]), vxl, vxh, vyl, vyh);
+        const unsigned long long m = __ballot(v);
+        if ((tid & 63) == 0 && i < np) vbits[i >> 6] = m;
+    }
     bool vprev = false;   // plane p - 1 was vacuum
+    // the incident wave's x-y phase factors of the own and the ring cell
+    // (fixed for the whole march) and the z factor of plane p - 1
+    using C2 = typename Cplx<T>::type;
+    C2 wo{}, wg{}, wzq{};
+    if (a.src_on) {
+        wo = xy_phase(a, xf, yf);
+        if (ring) wg = xy_phase(a, rxf, ryf);
+    }
     // per-column history: +z movers of planes p-2 (pz0) and p-1 (pz1); rest
     // scalars, eps, 1/eps and sigma of plane p-1
     T pz0[4], pz1[4], rest[3], ep = T(1), ip = T(1), sg = T(0);
@@ -1586,21 +1654,23 @@ __global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArg
             lz[p & 1][st1][i] = a.line_tab[((int64_t)((t + st1) & (kLineSlots - 1)) * 27 + i) * a.line_n + zz];
         }
     };
-    if (LINE) {
-        stage_line(zb - 1);
-        __syncthreads();
-    }
+    if (LINE) stage_line(zb - 1);
+    __syncthreads();
 
     for (int p = zb - 1; p <= ze; ++p) {
         const int pf = fold(p, a.nz, a.W[2]);
         X3Lds<T, TX, TY> &B = L[p & 1];
-        const bool vp = vacuum_plane(a, pf, vxl, vxh, vyl, vyh);
+        const int vi = p - zb + 1;
+        const bool vp = (vbits[vi >> 6] >> (vi & 63)) & 1ull;
+        // the plane's z phase factor, loaded with the state
+        C2 wzp{};
+        if (a.src_on) wzp = a.wave_z[pf];
         // step t on plane p: own cell ...
         T f[27], e;
         pull3d<T>(a, xf, yf, pf, f, e, vp);
         const T ie = recip(e), sgp = sigma3d<T>(a, xf, yf, pf);
-        cell_update3d<T, LINE, false, DFT>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze, lz[p & 1][0],
-                                           1);
+        cell_update3d<T, LINE, false, DFT, true>(a, s0, xf, yf, pf, e, ie, sgp, f, own && p >= zb && p < ze,
+                                                 lz[p & 1][0], 1, wo, wzp);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             B.xm[k][oy][ox + 1] = f[k];
@@ -1612,8 +1682,8 @@ __global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArg
         if (ring) {
             T g[27], ge;
             pull3d<T>(a, rxf, ryf, pf, g, ge, vp);
-            cell_update3d<T, LINE, false, DFT>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf), g,
-                                               false, lz[p & 1][0], 1);
+            cell_update3d<T, LINE, false, DFT, true>(a, s0, rxf, ryf, pf, ge, recip(ge), sigma3d<T>(a, rxf, ryf, pf),
+                                                     g, false, lz[p & 1][0], 1, wg, wzp);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (tid < TX) B.ym[k][0][tid] = g[8 + k];
@@ -1644,7 +1714,7 @@ __global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArg
             h[24] = rest[0];
             h[25] = rest[1];
             h[26] = rest[2];
-            cell_update3d<T, LINE, false, DFT>(a, s1, xf, yf, q, ep, ip, sg, h, own, lz[p & 1][1], 1);
+            cell_update3d<T, LINE, false, DFT, true>(a, s1, xf, yf, q, ep, ip, sg, h, own, lz[p & 1][1], 1, wo, wzq);
             if (own) {
                 // streamed out: the next launch reads it from HBM
                 const uint32_t c = (uint32_t)q * sz + (uint32_t)y * sy + (uint32_t)x;
@@ -1670,6 +1740,7 @@ __global__ void __launch_bounds__(TX * TY, 1024 / (TX * TY)) k_step3d_x2(StepArg
         ip = ie;
         sg = sgp;
         vprev = vp;
+        wzq = wzp;
     }
 }
 

@@ -330,12 +330,14 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
 // Two steps in one launch: reads src, writes f*(t+1) to dst.
 
 // z chunk of the 3-D two-step kernel: each block marches zc planes plus two
-// extra ones; pick the chunk count that minimises rounds x (zc + 2).
+// extra ones (at most kX3MaxPlanes in all); pick the chunk count that
+// minimises rounds x (zc + 2).
 int x3_chunk(int nz, int tiles, int slots) {
-    int best_zc = nz;
+    int best_zc = std::min(nz, kX3MaxPlanes - 2);
     int64_t best = INT64_MAX;
     for (int n = 1; n <= nz; ++n) {
         const int zc = (nz + n - 1) / n;
+        if (zc + 2 > kX3MaxPlanes) continue;
         const int64_t blocks = (int64_t)tiles * ((nz + zc - 1) / zc);
         const int64_t rounds = (blocks + slots - 1) / slots;
         const int64_t cost = rounds * (zc + 2);
