@@ -5,6 +5,7 @@ namespace lbm {
 
 template <typename T>
 bool launch_step3d_x2(const StepArgs<T> &a, int tx, int ty, int zc, bool dft, hipStream_t s) {
+    if (zc < 1 || zc + 2 > kX3MaxPlanes) return false;   // the chunk's vacuum flags live in LDS
     const int tiles = a.tiles_x * a.tiles_y;
     dim3 grid((unsigned)(tiles * ((a.nz + zc - 1) / zc)), 1, 1);
 #define LBM_X3_DFT(TX, TY, LINE)                                                                          \

@@ -39,9 +39,10 @@ inline bool launch_step2d_x2(const StepArgs<T> &a, int pol, int tx, int ty, bool
     return pol == TM ? launch_step2d_x2_pol<T, TM>(a, tx, ty, dft, s) : launch_step2d_x2_pol<T, TE>(a, tx, ty, dft, s);
 }
 
-// Two steps, 3-D z march (k_step3d_x2), z chunks of zc planes.  dft: the
-// launch may fall into the DFT window (selects the instantiation that
-// accumulates the contour DFT).
+// Two steps, 3-D z march (k_step3d_x2), z chunks of zc planes (1 <= zc <=
+// kX3MaxPlanes - 2).  dft: the launch may fall into the DFT window (selects
+// the instantiation that accumulates the contour DFT).  Returns false for an
+// uncompiled tile or a chunk out of range.
 template <typename T>
 bool launch_step3d_x2(const StepArgs<T> &a, int tx, int ty, int zc, bool dft, hipStream_t s);
 

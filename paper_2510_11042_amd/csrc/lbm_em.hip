@@ -365,7 +365,7 @@ void launch_step2_3d(const lbm_em *h, StepArgs<T> a, hipStream_t s) {
     const int tiles = a.tiles_x * a.tiles_y;
     const int zc = x3_chunk(a.nz, tiles, h->cus * std::max(1, 1024 / (tx * ty)));
     if (!launch_step3d_x2<T>(a, tx, ty, zc, launch_meets_window(h, a), s))
-        fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile");
+        fail(LBM_EM_EINVAL, "unsupported 3-D two-step tile or z chunk");
 }
 
 template <typename T>

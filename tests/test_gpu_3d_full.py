@@ -7,6 +7,9 @@
   three graph chunks (the first outside the DFT window, so it replays the
   kernels without the contour accumulation) and an odd trailing step,
   fields and contour phasors.
+* A 512-thread tile whose chunk is longer than its block (512^3, 128 x 4):
+  two steps per launch against one, with dielectric slabs that carry
+  fields on planes far apart in the chunk.
 * FP64 and FP32 against the oracle on a 160 x 96 x 128 grid, where the
   default tile leaves ragged x tiles and the z march takes several chunks.
 * A permittivity map changed between steps, against the oracle: the 3-D
@@ -69,6 +72,36 @@ def test_sphere_two_steps_per_launch_bit_identical(Sim, n):
     assert np.abs(E1).max() > 0 and np.abs(X1).max() > 0
     assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
     assert np.array_equal(X1, X2) and np.array_equal(p1, p2)
+
+
+def test_long_chunk_vacuum_flags_bit_identical(Sim):
+    """A 512-thread tile marching a chunk longer than its block: on a
+    256-CU device the 512^3 grid with 128 x 4 tiles takes a single chunk of
+    512 planes, so the block forms the planes' vacuum flags in two passes
+    and they span nine 64-bit words.  Dielectric slabs against the forced x
+    layer, on planes in several of those words, carry fields from the first
+    steps (a bug in the flags would treat them as vacuum).  Two steps per
+    launch against one, bit for bit."""
+    n, Wl = 512, 24
+    eps = np.ones((n, n, n))
+    slabs = (30, 100, 300, 505)
+    for z0 in slabs:
+        eps[z0:z0 + 6, :, Wl:Wl + 6] = 2.25
+    runs = []
+    for fuse, tile in ((2, (128, 4)), (1, (0, 0))):
+        s = Sim(n, n, n, pol="3D", precision="fp32", absorb=(Wl,) * 3, sigma_max=W.SIGMA_MAX)
+        s.set_permittivity(eps)
+        s.set_source(24.0, [0, 0, 1.0], [1.0, 0, 0], 1.0, 1.0)
+        s.set_fusion(fuse, tile)
+        say("512^3 long chunk, fusion", s.get_fusion(), s.get_fusion_tile())
+        for k in (64, 3):
+            s.step(k)
+        runs.append(s.fields())
+        s.close()
+    (E2, H2), (E1, H1) = runs
+    for z0 in slabs:
+        assert np.abs(E1[z0:z0 + 6, :, Wl:Wl + 6]).max() > 0, z0
+    assert np.array_equal(E1, E2) and np.array_equal(H1, H2)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
