@@ -533,14 +533,23 @@ def stream_ceiling(P, n=384):
 
 
 def host_cpu():
-    model = "unknown"
+    """The host CPU's model name with its family / model / stepping numbers
+    (virtual machines may report a generic name), and the thread count."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v
+            elif info:
                 break
     except OSError:
         pass
+    model = info.get("model name", "unknown")
+    ids = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    if ids:
+        model += " (" + ", ".join(ids) + ")"
     return model, os.cpu_count()
 
 
