@@ -364,8 +364,9 @@ lbm_em_status lbm_em_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
  * and writes it to `planes_out` planes with streamed stores (1 <= planes_out
  * <= planes_in <= 32, 1 <= cells <= 2^31) -- averaged over `reps` launches
  * on the null stream, counting bytes read + written.  Allocates and frees
- * the planes (4 (planes_in + planes_out) cells bytes).  24 planes in and out
- * is the 3-D two-step kernel's traffic for vacuum cells. */
+ * the planes (about 4 (planes_in + planes_out) cells bytes), laid out with
+ * the state's plane stride.  24 planes in and out is the 3-D two-step
+ * kernel's traffic for vacuum cells. */
 lbm_em_status lbm_em_stream_bandwidth(int64_t cells, int32_t planes_in, int32_t planes_out, int32_t reps,
                                       double *gbs);
 

@@ -2357,11 +2357,13 @@ static __global__ void __launch_bounds__(256) k_copy16(const float4 *__restrict_
     if (i < n) b[i] = a[i];
 }
 
-// Element-wise equality check (autotuner): any mismatch sets *flag = 1.
+// Element-wise equality check (autotuner) over the first `cells` elements
+// of every plane of stride P (the gap after them is never written): any
+// mismatch sets *flag = 1.
 template <typename T>
-__global__ void k_compare(const T *a, const T *b, int64_t n, int *flag) {
+__global__ void k_compare(const T *a, const T *b, int64_t n, int64_t P, int64_t cells, int *flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && a[i] != b[i]) flag[0] = 1;
+    if (i < n && i % P < cells && a[i] != b[i]) flag[0] = 1;
 }
 
 // Device step counter for graph replays (vector store from one lane).

@@ -329,6 +329,20 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
 
 // Two steps in one launch: reads src, writes f*(t+1) to dst.
 
+// Stride between population planes, in elements: the plane's cells rounded
+// up to an odd multiple of 4 KiB.  At strides that are multiples of large
+// powers of two (a 512^3 FP32 plane is 2^29 bytes) the 24-54 concurrent
+// plane streams of a launch meet the memory channels in step; 24 planes in
+// and 24 out at 512^3 stream at 5.12 TB/s with the bare stride and at
+// 5.59 TB/s with 4 KiB more per plane (384^3, whose plane already has an
+// odd factor, is unaffected).
+int64_t plane_stride(int64_t cells, int64_t elem) {
+    const int64_t unit = 4096 / elem;
+    int64_t p = (cells + unit - 1) / unit;
+    if (p % 2 == 0) ++p;
+    return p * unit;
+}
+
 // z chunk of the 3-D two-step kernel: each block marches zc planes plus two
 // extra ones (at most kX3MaxPlanes in all); pick the chunk count that
 // minimises rounds x (zc + 2).
@@ -1287,7 +1301,7 @@ lbm_em_status lbm_em_create(const lbm_em_config *cfg, lbm_em_handle *out) {
             }
             h->sy = round_up(c.nx, 64);
             h->sz = h->sy * c.ny;
-            h->plane = h->sz * c.nz;
+            h->plane = plane_stride(h->sz * c.nz, h->elem);
             h->stream = (hipStream_t)c.stream;
             const size_t bytes = (size_t)h->plane * h->nplanes * h->elem;
             hip_check(hipMalloc(&h->buf[0], bytes), "hipMalloc state");
@@ -1896,10 +1910,10 @@ lbm_em_status lbm_em_autotune(lbm_em_handle hh, int32_t launches, double *best_u
             const unsigned blocks = (unsigned)((n + 255) / 256);
             if (h->elem == 4)
                 hipLaunchKernelGGL((k_compare<float>), dim3(blocks), dim3(256), 0, h->stream, (const float *)ref,
-                                   (const float *)h->buf[h->cur ^ 1], (int64_t)n, flag);
+                                   (const float *)h->buf[h->cur ^ 1], (int64_t)n, h->plane, h->sz * h->cfg.nz, flag);
             else
                 hipLaunchKernelGGL((k_compare<double>), dim3(blocks), dim3(256), 0, h->stream, (const double *)ref,
-                                   (const double *)h->buf[h->cur ^ 1], (int64_t)n, flag);
+                                   (const double *)h->buf[h->cur ^ 1], (int64_t)n, h->plane, h->sz * h->cfg.nz, flag);
             int differs = 0;
             hip_check(hipMemcpyAsync(&differs, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream), "D2H");
             sync(h);
@@ -2354,7 +2368,7 @@ lbm_em_status lbm_em_stream_bandwidth(int64_t cells, int32_t planes_in, int32_t 
             fail(LBM_EM_EINVAL, "need 1 <= cells <= 2^31, 1 <= planes_out <= planes_in <= 32, reps >= 1");
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(LBM_EM_EDEVICE, "no HIP device");
-        const int64_t P = round_up(cells, 64);
+        const int64_t P = plane_stride(cells, 4);   // the state's plane layout
         void *a = nullptr, *b = nullptr;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         try {
