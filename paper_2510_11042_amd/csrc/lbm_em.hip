@@ -332,10 +332,10 @@ void launch_step(const lbm_em *h, int parity, const int64_t *t_base, int64_t t_o
 // Stride between population planes, in elements: the plane's cells rounded
 // up to an odd multiple of 4 KiB.  At strides that are multiples of large
 // powers of two (a 512^3 FP32 plane is 2^29 bytes) the 24-54 concurrent
-// plane streams of a launch meet the memory channels in step; 24 planes in
-// and 24 out at 512^3 stream at 5.12 TB/s with the bare stride and at
-// 5.59 TB/s with 4 KiB more per plane (384^3, whose plane already has an
-// odd factor, is unaffected).
+// plane streams of a launch meet the memory channels in step: 24 planes in
+// and 24 out at 512^3 (lbm_em_stream_bandwidth) stream at 5.35 TB/s with
+// the bare stride and at 5.80 TB/s with this one (384^3, whose plane
+// already has an odd factor, is unaffected).
 int64_t plane_stride(int64_t cells, int64_t elem) {
     const int64_t unit = 4096 / elem;
     int64_t p = (cells + unit - 1) / unit;
