@@ -165,6 +165,67 @@ def sphere_S2(theta_deg, phi_deg, x, m):
     return np.abs(S2) ** 2 * np.cos(ph) ** 2 + np.abs(S1) ** 2 * np.sin(ph) ** 2
 
 
+def sphere_near_field(R, x_size, k, m):
+    """Scattered field of a unit incident plane wave x_hat exp(i k z) (time
+    factor exp(-i omega t)) around a sphere of size parameter x_size = k a
+    centred at the origin, at points R (..., 3) outside it; units with unit
+    wave impedance.  Bohren & Huffman, section 4.4:
+        E_s = sum_n E_n (i a_n N_e1n - b_n M_o1n),
+        H_s = sum_n E_n (i b_n N_o1n + a_n M_e1n),   E_n = i^n (2n+1)/(n(n+1)),
+    with the vector spherical harmonics of the outgoing spherical Hankel
+    function h_n^(1)(kr):
+        M_o1n = cos(phi) pi_n h_n e_theta - sin(phi) tau_n h_n e_phi
+        M_e1n = -sin(phi) pi_n h_n e_theta - cos(phi) tau_n h_n e_phi
+        N_o1n = sin(phi) n(n+1) sin(theta) pi_n h_n/rho e_r
+                + sin(phi) tau_n D_n e_theta + cos(phi) pi_n D_n e_phi
+        N_e1n = cos(phi) n(n+1) sin(theta) pi_n h_n/rho e_r
+                + cos(phi) tau_n D_n e_theta - sin(phi) pi_n D_n e_phi
+    where rho = kr and D_n = (rho h_n)'/rho.  Returns (E, H), (..., 3)."""
+    a, b = sphere_coefficients(x_size, m)
+    R = np.asarray(R, dtype=float)
+    r = np.linalg.norm(R, axis=-1)
+    th = np.arccos(np.clip(R[..., 2] / r, -1.0, 1.0))
+    ph = np.arctan2(R[..., 1], R[..., 0])
+    rho = k * r
+    mu, st = np.cos(th), np.sin(th)
+    cp, sp_ = np.cos(ph), np.sin(ph)
+    Er = np.zeros(r.shape, complex)
+    Et = np.zeros(r.shape, complex)
+    Ep = np.zeros(r.shape, complex)
+    Hr = np.zeros(r.shape, complex)
+    Ht = np.zeros(r.shape, complex)
+    Hp = np.zeros(r.shape, complex)
+    pi_prev, pi_cur = np.zeros_like(mu), np.ones_like(mu)
+    for n in range(1, a.size + 1):
+        tau = n * mu * pi_cur - (n + 1) * pi_prev
+        j, dj = sp.spherical_jn(n, rho), sp.spherical_jn(n, rho, derivative=True)
+        y, dy = sp.spherical_yn(n, rho), sp.spherical_yn(n, rho, derivative=True)
+        h, dh = j + 1j * y, dj + 1j * dy
+        D = (h + rho * dh) / rho
+        En = (1j ** n) * (2 * n + 1) / (n * (n + 1))
+        an, bn = a[n - 1], b[n - 1]
+        radial = n * (n + 1) * st * pi_cur * h / rho
+        # E: i a_n N_e1n - b_n M_o1n
+        Er += En * (1j * an * cp * radial)
+        Et += En * (1j * an * cp * tau * D - bn * cp * pi_cur * h)
+        Ep += En * (-1j * an * sp_ * pi_cur * D + bn * sp_ * tau * h)
+        # H: i b_n N_o1n + a_n M_e1n
+        Hr += En * (1j * bn * sp_ * radial)
+        Ht += En * (1j * bn * sp_ * tau * D - an * sp_ * pi_cur * h)
+        Hp += En * (1j * bn * cp * pi_cur * D - an * cp * tau * h)
+        pi_next = ((2 * n + 1) / n) * mu * pi_cur - ((n + 1) / n) * pi_prev
+        pi_prev, pi_cur = pi_cur, pi_next
+
+    def cart(Fr, Ft, Fp):
+        out = np.zeros(r.shape + (3,), complex)
+        out[..., 0] = Fr * st * cp + Ft * mu * cp - Fp * sp_
+        out[..., 1] = Fr * st * sp_ + Ft * mu * sp_ + Fp * cp
+        out[..., 2] = Fr * mu - Ft * st
+        return out
+
+    return cart(Er, Et, Ep), cart(Hr, Ht, Hp)
+
+
 def sphere_efficiencies(x, m):
     a, b = sphere_coefficients(x, m)
     n = np.arange(1, a.size + 1)

@@ -132,3 +132,43 @@ def test_ntff_3d_dipole_second_order():
         errs.append(max(e))
     assert errs[1] < 5e-3
     assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_sphere_near_field_far_limit():
+    """The exact scattered near field of a sphere (Bohren & Huffman section
+    4.4) tends to the series amplitudes: (kr)^2 |E_s|^2 -> |S(theta, phi)|^2
+    with a 1/(kr) correction, and H_s -> r_hat x E_s (unit impedance)."""
+    x, m, k = 4 * np.pi, np.sqrt(2.0), 1.0
+    th = np.array([10.0, 60.0, 120.0, 175.0, 180.0 - 1e-9])
+    for rr, tol in ((2e4, 1e-2), (2e5, 1e-3)):
+        for phi in (0.0, 45.0, 90.0):
+            t, p = np.deg2rad(th), np.deg2rad(phi)
+            rhat = np.stack([np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)], 1)
+            E, H = mie.sphere_near_field(rr * rhat, x, k, m)
+            S = (k * rr) ** 2 * np.sum(np.abs(E) ** 2, 1)
+            assert np.max(np.abs(S / mie.sphere_S2(th, phi, x, m) - 1)) < tol
+            assert np.max(np.abs(H - np.cross(rhat, E))) < tol * np.max(np.abs(E))
+
+
+def test_ntff_3d_of_exact_mie_near_field():
+    """Section 2.4 in 3-D, with a far field that is not symmetric front to
+    back: the transform of the exact scattered near field of a sphere (x =
+    4 pi, m = sqrt 2, the a/lambda = 2 sphere of Table dielectric_sphere_er_2)
+    on a box contour reproduces the series in the scattering planes phi = 0,
+    45 and 90 degrees, the narrow backscatter lobe included."""
+    lam, m = 16.0, np.sqrt(2.0)
+    k, a = 2 * np.pi / lam, 2 * lam
+    hw = int(a + lam / 4 + 4)
+    c = np.array([hw + 0.3, hw - 0.2, hw + 0.1])
+    lo, hi = (0, 0, 0), (2 * hw,) * 3
+    nodes = ntff.box_nodes(lo, hi)
+    E, H = mie.sphere_near_field((nodes - c).astype(float), k * a, k, m)
+    # exp(-i w t) field of unit incidence -> this code's exp(+j w t) phasor
+    E, H = np.conj(1j * E), np.conj(1j * H)
+    th = np.arange(0, 180.1, 1.0)
+    for phi in (0.0, 45.0, 90.0):
+        S = ntff.farfield_3d(nodes, E, H, lo, hi, k, th, phi, c, 1.0)
+        ref = mie.sphere_S2(th, phi, k * a, m)
+        assert np.sqrt(np.mean((S - ref) ** 2)) / ref.max() < 1e-4
+        assert np.max(np.abs(S - ref)) / ref.max() < 1e-3
+        assert abs(S[-1] / ref[-1] - 1) < 1e-3          # backscatter
