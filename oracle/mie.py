@@ -18,6 +18,11 @@ Sphere:
   b_n = [psi_n(mx) psi_n'(x) - m psi_n(x) psi_n'(mx)] / [psi_n(mx) xi_n'(x) - m xi_n(x) psi_n'(mx)]
   S1 = sum (2n+1)/(n(n+1)) (a_n pi_n + b_n tau_n),  S2 = sum (2n+1)/(n(n+1)) (a_n tau_n + b_n pi_n)
 
+Near fields (used to pin the near-to-far-field transform of section 2.4):
+  cylinder_near_field -- the scattered z-field series with its curl;
+  sphere_near_field   -- the scattered field in vector spherical harmonics
+                         (section 4.4 of the book).
+
 Intensities in the paper's normalisation (section 2.3, Eq. S2D / S3D):
   2-D  |S(theta)|^2 = k r |E_s|^2/|E_i|^2 = (2/pi) |T(theta)|^2
   3-D  |S(theta,phi)|^2 = k^2 r^2 |E_s|^2/|E_i|^2 = |S2|^2 cos^2 phi + |S1|^2 sin^2 phi,
